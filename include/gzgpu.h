@@ -1,0 +1,152 @@
+/*
+ * gzgpu: two-pass parallel gzip decompression on one AMD Instinct MI355X.
+ *
+ * The method is the one of Kerbiriou & Chikhi, "Parallel decompression of
+ * gzip-compressed files and random access to DNA sequences", Section VI-C:
+ * the compressed payload of one gzip member is cut into parts; each part
+ * finds a DEFLATE block start (Section VI-A, Appendix A), decodes with a
+ * context of 32768 unique placeholder symbols (pass 1), the 32 KiB windows
+ * are resolved part after part, and every placeholder is replaced by its
+ * byte (pass 2).  The output is the exact gunzip of the member.
+ *
+ * Memory model
+ *   - Every buffer handed to these calls is HIP device memory owned by the
+ *     caller: compressed input, output and workspace.  The library allocates
+ *     no device memory; it keeps a small pinned host copy of each plan's job
+ *     table.
+ *   - The compressed input must stay alive and unmodified until the stream
+ *     work of a gz_decompress* call has completed.
+ *   - A plan is used by one stream at a time.  Distinct plans (with distinct
+ *     workspaces) are independent.
+ *
+ * Errors
+ *   - Every call returns an int: GZ_OK (0) or a negative GZ_E_* code; nothing
+ *     is thrown across this interface.  gz_strerror() gives a message.
+ *   - gz_decompress* only enqueues work.  Data errors are reported by
+ *     gz_result*, which waits for the stream.
+ */
+#ifndef GZGPU_H
+#define GZGPU_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GZ_OK 0
+#define GZ_E_ARG (-1)         /* invalid argument (NULL, size 0, bad options) */
+#define GZ_E_HEADER (-2)      /* gzip member header invalid (magic, CM, reserved FLG bits, FHCRC) */
+#define GZ_E_UNSUPPORTED (-3) /* bytes after the first member (multi-member input) */
+#define GZ_E_DATA (-4)        /* invalid DEFLATE data, truncation, distance too far back */
+#define GZ_E_CAPACITY (-5)    /* output or workspace too small; gz_result gives the sizes needed */
+#define GZ_E_SIZE (-7)        /* decoded length differs from the trailer's ISIZE (mod 2^32) */
+#define GZ_E_HIP (-9)         /* HIP runtime error */
+#define GZ_E_NOT_READY (-10)  /* gz_result before any gz_decompress on this plan */
+
+/* Options.  An all-zero struct means defaults.  (Section VI-C cuts the payload
+ * into n roughly equal parts; Section VI-A and Appendix A give the
+ * block-start checks whose constants appear here.) */
+typedef struct gz_opts {
+  uint64_t chunk_bytes;   /* nominal compressed bytes per chunk when n_chunks == 0 (default 1 MiB) */
+  uint32_t sym_factor;    /* symbol capacity per chunk = sym_factor * compressed bytes + slack (default 8) */
+  uint32_t window_syms;   /* per-wave LDS history in symbols: 8192, 16384 (default) or 32768 */
+  uint32_t scan_groups;   /* workgroups that search one chunk's start in parallel (default 8) */
+  uint32_t inflate_waves_per_cu; /* persistent inflate grid = this * CU count (default: occupancy) */
+  uint32_t reserved[8];
+} gz_opts;
+
+/* One file of a batch. */
+typedef struct gz_job {
+  const void *d_comp;     /* device pointer to the whole .gz file */
+  uint64_t comp_len;      /* bytes */
+  int32_t n_chunks;       /* 0: derived from opts.chunk_bytes */
+  int32_t pad;
+  void *d_out;            /* device output buffer (may be NULL at plan time for gz_decompress) */
+  uint64_t out_cap;       /* bytes available at d_out */
+} gz_job;
+
+typedef struct gz_info {
+  uint64_t ws_bytes;       /* workspace needed by gz_decompress* */
+  uint64_t payload_start;  /* first member: byte where the DEFLATE data begins (file 0 of a batch) */
+  uint64_t payload_end;    /* byte where the trailer begins (comp_len - 8) */
+  uint32_t n_files;
+  uint32_t n_chunks;       /* total over the batch */
+  uint32_t crc32;          /* trailer CRC-32 (file 0) */
+  uint32_t isize;          /* trailer ISIZE (file 0): length mod 2^32, never a size */
+} gz_info;
+
+typedef struct gz_result {
+  int32_t status;          /* GZ_OK or GZ_E_* for this file */
+  uint32_t n_chunks;
+  uint64_t out_len;        /* decompressed bytes (valid when status is OK or CAPACITY) */
+  uint64_t out_needed;     /* output bytes needed when out_cap was too small */
+  uint64_t ws_needed;      /* workspace bytes a re-plan needs when a chunk overflowed (0 otherwise) */
+  uint32_t n_nonempty;     /* chunks that decoded at least one block */
+  uint32_t n_repairs;      /* chunks re-decoded because a start was not on the block chain */
+  uint32_t n_extended;     /* chunks that continued past their first stop */
+  uint32_t n_retries;      /* candidate starts rejected by the trial decode */
+  uint64_t n_syms;         /* Huffman literal/length symbols decoded (end-of-block included) */
+  uint64_t n_placeholders; /* symbols that referenced a chunk's unknown window */
+  uint64_t n_blocks;
+} gz_result;
+
+typedef struct gz_plan_s *gz_plan_t;
+
+/* Plan one gzip file held at d_comp (device memory, comp_len bytes).
+ * Reads the member header and the 8-byte trailer with two small synchronous
+ * device-to-host copies, checks the header (RFC 1952 section 2.3), and lays
+ * out the chunks: chunk i covers the compressed bytes
+ * [h + floor(i*P/N), h + floor((i+1)*P/N)) of the payload (h = payload start,
+ * P = payload bytes, N = n_chunks; 0 means P / opts.chunk_bytes).
+ * opts may be NULL.  On success *plan owns a host object released by
+ * gz_plan_destroy.  Errors: GZ_E_ARG, GZ_E_HEADER, GZ_E_HIP. */
+int gz_plan(gz_plan_t *plan, const void *d_comp, size_t comp_len, int n_chunks, const gz_opts *opts);
+
+/* Plan a batch of n_jobs files decoded together by one launch sequence. */
+int gz_plan_batch(gz_plan_t *plan, const gz_job *jobs, int n_jobs, const gz_opts *opts);
+
+int gz_plan_info(gz_plan_t plan, gz_info *info);
+
+/* Enqueue the whole path for a one-file plan on `stream` (a hipStream_t;
+ * NULL is the default stream): upload of the job table, block-start scan,
+ * symbolic inflate, stitch check and repair, size scan, window propagation,
+ * translation into d_out.  d_ws must hold gz_info.ws_bytes bytes and be
+ * 256-byte aligned.  Returns without waiting.  Errors: GZ_E_ARG,
+ * GZ_E_CAPACITY (ws_bytes too small), GZ_E_HIP. */
+int gz_decompress(gz_plan_t plan, void *d_out, size_t out_cap, void *d_ws, size_t ws_bytes, void *stream);
+
+/* Enqueue the path for every file of a batch plan, outputs at the jobs'
+ * d_out.  One launch per pass covers all files and chunks. */
+int gz_decompress_batch(gz_plan_t plan, void *d_ws, size_t ws_bytes, void *stream);
+
+/* Wait for the stream of the last gz_decompress* on this plan and read the
+ * status and statistics of one file (file 0 for a one-file plan). */
+int gz_result_get(gz_plan_t plan, int file, gz_result *res);
+
+/* Per-chunk state after the stream completes (host copies, arrays of the
+ * file's n_chunks entries): accepted start bit (UINT64_MAX: empty chunk),
+ * scan candidate, end bit, symbol count |D_i|, output offset, status (GZ_*)
+ * and flags (1 final block reached, 2 empty, 4 extended, 8 repaired,
+ * 16 capacity overflow).  Any pointer may be NULL.  Used by tests to check
+ * each pass against the oracle. */
+int gz_chunk_table(gz_plan_t plan, int file, uint64_t *start, uint64_t *cand, uint64_t *end, uint64_t *len,
+                   uint64_t *out_off, int32_t *status, uint32_t *flags);
+
+/* Device addresses of a file's per-chunk symbol arrays and windows inside the
+ * workspace of the last call (for tests): symbols of chunk c start at
+ * sym_base + 2*sym_off[c]; its resolved window at win_base + 32768*c. */
+int gz_debug_layout(gz_plan_t plan, int file, uint64_t *sym_off, uint64_t *win_index, void **sym_base,
+                    void **win_base);
+
+void gz_plan_destroy(gz_plan_t plan);
+const char *gz_strerror(int code);
+
+/* Device count and compute-unit count of device `dev` (for sizing). */
+int gz_device_info(int dev, int *n_cu, int *lds_bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

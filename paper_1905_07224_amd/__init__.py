@@ -1,0 +1,338 @@
+"""Two-pass parallel gzip decompression on AMD Instinct MI355X (gfx950).
+
+Python binding over the C ABI of ``libgzgpu.so`` (declared in
+``include/gzgpu.h``).  It only marshals arguments: torch tensors provide the
+device memory (compressed input, output, workspace) and the stream; every
+step of the decompression runs in the library's HIP kernels.  There is no CPU
+fallback: without the built library every call raises.
+
+The method (Kerbiriou & Chikhi, Section VI-C): cut the compressed payload into
+chunks, find a block start in each (Section VI-A, Appendix A), decode each
+chunk with a context of 32768 unique placeholder symbols, resolve the 32 KiB
+windows chunk after chunk, and replace every placeholder by its byte.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+__all__ = ["GzError", "Plan", "BatchPlan", "decompress", "decompress_batch", "lib", "Opts", "LIB_PATH"]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgzgpu.so")
+
+GZ_OK, GZ_E_ARG, GZ_E_HEADER, GZ_E_UNSUPPORTED, GZ_E_DATA, GZ_E_CAPACITY = 0, -1, -2, -3, -4, -5
+GZ_E_SIZE, GZ_E_HIP, GZ_E_NOT_READY = -7, -9, -10
+NONE = (1 << 64) - 1
+
+
+class GzError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"gzgpu error {code}: {msg}")
+        self.code = code
+
+
+class Opts(C.Structure):
+    _fields_ = [("chunk_bytes", C.c_uint64), ("sym_factor", C.c_uint32), ("window_syms", C.c_uint32),
+                ("scan_groups", C.c_uint32), ("inflate_waves_per_cu", C.c_uint32), ("reserved", C.c_uint32 * 8)]
+
+
+class Job(C.Structure):
+    _fields_ = [("d_comp", C.c_void_p), ("comp_len", C.c_uint64), ("n_chunks", C.c_int32), ("pad", C.c_int32),
+                ("d_out", C.c_void_p), ("out_cap", C.c_uint64)]
+
+
+class Info(C.Structure):
+    _fields_ = [("ws_bytes", C.c_uint64), ("payload_start", C.c_uint64), ("payload_end", C.c_uint64),
+                ("n_files", C.c_uint32), ("n_chunks", C.c_uint32), ("crc32", C.c_uint32), ("isize", C.c_uint32)]
+
+
+class Result(C.Structure):
+    _fields_ = [("status", C.c_int32), ("n_chunks", C.c_uint32), ("out_len", C.c_uint64),
+                ("out_needed", C.c_uint64), ("ws_needed", C.c_uint64), ("n_nonempty", C.c_uint32),
+                ("n_repairs", C.c_uint32), ("n_extended", C.c_uint32), ("n_retries", C.c_uint32),
+                ("n_syms", C.c_uint64), ("n_placeholders", C.c_uint64), ("n_blocks", C.c_uint64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+EXPORTS = ["gz_plan", "gz_plan_batch", "gz_plan_info", "gz_decompress", "gz_decompress_batch", "gz_result_get",
+           "gz_chunk_table", "gz_debug_layout", "gz_plan_destroy", "gz_strerror", "gz_device_info"]
+
+
+def lib():
+    """The loaded HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                               "(the HIP library is the only implementation)")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, u64 = C.c_void_p, C.c_int, C.c_uint64
+        L.gz_plan.argtypes = [C.POINTER(vp), vp, C.c_size_t, i32, C.POINTER(Opts)]
+        L.gz_plan_batch.argtypes = [C.POINTER(vp), C.POINTER(Job), i32, C.POINTER(Opts)]
+        L.gz_plan_info.argtypes = [vp, C.POINTER(Info)]
+        L.gz_decompress.argtypes = [vp, vp, C.c_size_t, vp, C.c_size_t, vp]
+        L.gz_decompress_batch.argtypes = [vp, vp, C.c_size_t, vp]
+        L.gz_result_get.argtypes = [vp, i32, C.POINTER(Result)]
+        L.gz_chunk_table.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp]
+        L.gz_debug_layout.argtypes = [vp, i32, vp, vp, C.POINTER(vp), C.POINTER(vp)]
+        L.gz_plan_destroy.argtypes = [vp]
+        L.gz_plan_destroy.restype = None
+        L.gz_strerror.argtypes = [i32]
+        L.gz_strerror.restype = C.c_char_p
+        L.gz_device_info.argtypes = [i32, C.POINTER(i32), C.POINTER(i32)]
+        for name in EXPORTS:
+            if name not in ("gz_plan_destroy", "gz_strerror"):
+                getattr(L, name).restype = i32
+        _lib = L
+    return _lib
+
+
+def _check(code: int):
+    if code != GZ_OK:
+        raise GzError(code, lib().gz_strerror(code).decode())
+
+
+def _opts(**kw) -> Opts:
+    o = Opts()
+    for k, v in kw.items():
+        if v is not None:
+            setattr(o, k, v)
+    return o
+
+
+def _stream_handle(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _as_device_bytes(comp, device=None) -> torch.Tensor:
+    if isinstance(comp, torch.Tensor):
+        t = comp
+    else:
+        t = torch.frombuffer(bytearray(comp), dtype=torch.uint8)
+    if not t.is_cuda:
+        t = t.to(device or "cuda", non_blocking=False)
+    if t.dtype != torch.uint8 or not t.is_contiguous():
+        raise ValueError("compressed input must be a contiguous uint8 tensor")
+    return t
+
+
+def _out_guess(isize: int, comp_len: int) -> int:
+    # ISIZE is the length mod 2^32; text never decodes to much less than its
+    # compressed size, so the smallest value at or above that bound is the guess
+    floor = max(0, int(0.98 * (comp_len - 64)))
+    n = isize
+    while n < floor:
+        n += 1 << 32
+    return n
+
+
+class Plan:
+    """A one-file plan: chunk layout, workspace, and the launch sequence."""
+
+    def __init__(self, comp, n_chunks: int = 0, **opts):
+        self.comp = _as_device_bytes(comp)
+        self.device = self.comp.device
+        self.opts = _opts(**opts)
+        self._h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib().gz_plan(C.byref(self._h), C.c_void_p(self.comp.data_ptr()), self.comp.numel(),
+                                 int(n_chunks), C.byref(self.opts)))
+        self.info = Info()
+        _check(lib().gz_plan_info(self._h, C.byref(self.info)))
+        self.ws = None
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.gz_plan_destroy(h)
+            self._h = C.c_void_p()
+
+    @property
+    def n_chunks(self) -> int:
+        return self.info.n_chunks
+
+    def workspace(self) -> torch.Tensor:
+        if self.ws is None or self.ws.numel() < self.info.ws_bytes:
+            self.ws = torch.empty(self.info.ws_bytes, dtype=torch.uint8, device=self.device)
+        return self.ws
+
+    def launch(self, out: torch.Tensor | None, stream=None):
+        ws = self.workspace()
+        optr = C.c_void_p(out.data_ptr()) if out is not None and out.numel() else C.c_void_p()
+        ocap = out.numel() if out is not None else 0
+        with torch.cuda.device(self.device):
+            _check(lib().gz_decompress(self._h, optr, ocap, C.c_void_p(ws.data_ptr()), ws.numel(),
+                                       _stream_handle(stream)))
+
+    def result(self, file: int = 0) -> Result:
+        r = Result()
+        _check(lib().gz_result_get(self._h, file, C.byref(r)))
+        return r
+
+    def chunk_table(self, file: int = 0):
+        import numpy as np
+
+        n = self.info.n_chunks
+        arrs = {k: np.zeros(n, dtype=np.uint64) for k in ("start", "cand", "end", "len", "out_off")}
+        st = np.zeros(n, dtype=np.int32)
+        fl = np.zeros(n, dtype=np.uint32)
+        p = lambda a: C.c_void_p(a.ctypes.data)  # noqa: E731
+        _check(lib().gz_chunk_table(self._h, file, p(arrs["start"]), p(arrs["cand"]), p(arrs["end"]),
+                                    p(arrs["len"]), p(arrs["out_off"]), p(st), p(fl)))
+        arrs["status"] = st
+        arrs["flags"] = fl
+        return arrs
+
+    def symbols(self, chunk: int, length: int) -> torch.Tensor:
+        """The chunk's 16-bit symbols in the workspace (a view; valid until the next launch)."""
+        import numpy as np
+
+        n = self.info.n_chunks
+        off = np.zeros(n, dtype=np.uint64)
+        wi = np.zeros(n, dtype=np.uint64)
+        sb, wb = C.c_void_p(), C.c_void_p()
+        _check(lib().gz_debug_layout(self._h, 0, C.c_void_p(off.ctypes.data), C.c_void_p(wi.ctypes.data),
+                                     C.byref(sb), C.byref(wb)))
+        base = (sb.value - self.ws.data_ptr()) // 2 + int(off[chunk])
+        return self.ws.view(torch.int16)[base:base + length].view(torch.uint16) if hasattr(torch, "uint16") \
+            else self.ws.view(torch.int16)[base:base + length]
+
+    def window(self, chunk: int) -> torch.Tensor:
+        import numpy as np
+
+        n = self.info.n_chunks
+        off = np.zeros(n, dtype=np.uint64)
+        wi = np.zeros(n, dtype=np.uint64)
+        sb, wb = C.c_void_p(), C.c_void_p()
+        _check(lib().gz_debug_layout(self._h, 0, C.c_void_p(off.ctypes.data), C.c_void_p(wi.ctypes.data),
+                                     C.byref(sb), C.byref(wb)))
+        base = wb.value - self.ws.data_ptr() + 32768 * int(wi[chunk])
+        return self.ws[base:base + 32768]
+
+    def run(self, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        """Decompress into `out` (allocated when None); raises GzError on any failure."""
+        for _ in range(4):
+            if out is None:
+                out = torch.empty(_out_guess(self.info.isize, self.comp.numel()), dtype=torch.uint8,
+                                  device=self.device)
+            self.launch(out, stream)
+            r = self.result()
+            if r.status == GZ_E_CAPACITY and r.ws_needed:
+                # a chunk produced more symbols than planned: re-plan with room for it
+                factor = max(self.opts.sym_factor or 8, 8)
+                while True:
+                    factor *= 4
+                    self.opts.sym_factor = factor
+                    lib().gz_plan_destroy(self._h)
+                    self._h = C.c_void_p()
+                    _check(lib().gz_plan(C.byref(self._h), C.c_void_p(self.comp.data_ptr()), self.comp.numel(),
+                                         int(self.info.n_chunks), C.byref(self.opts)))
+                    _check(lib().gz_plan_info(self._h, C.byref(self.info)))
+                    if self.info.ws_bytes >= r.ws_needed or factor > 4096:
+                        break
+                continue
+            if r.status == GZ_E_CAPACITY and r.out_needed > out.numel():
+                out = torch.empty(r.out_needed, dtype=torch.uint8, device=self.device)
+                continue
+            _check(r.status)
+            return out[: r.out_len]
+        raise GzError(GZ_E_CAPACITY, "capacity retries exhausted")
+
+
+def decompress(comp, n_chunks: int = 0, out=None, stream=None, **opts) -> torch.Tensor:
+    """Decompress one gzip member held in a uint8 tensor (or bytes) on the GPU."""
+    return Plan(comp, n_chunks, **opts).run(out, stream)
+
+
+class BatchPlan:
+    """Many files decoded by one launch sequence (one launch per pass)."""
+
+    def __init__(self, comps, n_chunks=0, outs=None, **opts):
+        self.comps = [_as_device_bytes(c) for c in comps]
+        self.device = self.comps[0].device
+        self.opts = _opts(**opts)
+        nc = n_chunks if isinstance(n_chunks, (list, tuple)) else [n_chunks] * len(self.comps)
+        self.n_chunks_req = list(nc)
+        self.outs = outs
+        self._h = C.c_void_p()
+        self._make(outs)
+
+    def _make(self, outs):
+        n = len(self.comps)
+        jobs = (Job * n)()
+        self._isizes = []
+        for i, c in enumerate(self.comps):
+            jobs[i].d_comp = c.data_ptr()
+            jobs[i].comp_len = c.numel()
+            jobs[i].n_chunks = int(self.n_chunks_req[i])
+            if outs is not None:
+                jobs[i].d_out = outs[i].data_ptr()
+                jobs[i].out_cap = outs[i].numel()
+        if self._h.value:
+            lib().gz_plan_destroy(self._h)
+            self._h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib().gz_plan_batch(C.byref(self._h), jobs, n, C.byref(self.opts)))
+        self.info = Info()
+        _check(lib().gz_plan_info(self._h, C.byref(self.info)))
+        self.ws = None
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.gz_plan_destroy(h)
+            self._h = C.c_void_p()
+
+    def workspace(self) -> torch.Tensor:
+        if self.ws is None or self.ws.numel() < self.info.ws_bytes:
+            self.ws = torch.empty(self.info.ws_bytes, dtype=torch.uint8, device=self.device)
+        return self.ws
+
+    def launch(self, stream=None):
+        ws = self.workspace()
+        with torch.cuda.device(self.device):
+            _check(lib().gz_decompress_batch(self._h, C.c_void_p(ws.data_ptr()), ws.numel(), _stream_handle(stream)))
+
+    def result(self, file: int) -> Result:
+        r = Result()
+        _check(lib().gz_result_get(self._h, file, C.byref(r)))
+        return r
+
+
+def _isize_of(t: torch.Tensor) -> int:
+    tail = t[-4:].cpu().numpy().tobytes()
+    return int.from_bytes(tail, "little")
+
+
+def decompress_batch(comps, n_chunks=0, stream=None, **opts):
+    """Decompress several gzip files with one launch per pass; returns a list of tensors."""
+    comps = [_as_device_bytes(c) for c in comps]
+    outs = [torch.empty(_out_guess(_isize_of(c), c.numel()), dtype=torch.uint8, device=c.device) for c in comps]
+    bp = BatchPlan(comps, n_chunks, outs, **opts)
+    for _ in range(4):
+        bp.launch(stream)
+        res = [bp.result(i) for i in range(len(comps))]
+        redo = False
+        for i, r in enumerate(res):
+            if r.status == GZ_E_CAPACITY and r.ws_needed:
+                bp.opts.sym_factor = max(bp.opts.sym_factor or 8, 8) * 8
+                redo = True
+            elif r.status == GZ_E_CAPACITY and r.out_needed > outs[i].numel():
+                outs[i] = torch.empty(r.out_needed, dtype=torch.uint8, device=comps[i].device)
+                redo = True
+        if redo:
+            bp._make(outs)
+            continue
+        for r in res:
+            _check(r.status)
+        return [o[: r.out_len] for o, r in zip(outs, res)]
+    raise GzError(GZ_E_CAPACITY, "capacity retries exhausted")

@@ -1,0 +1,488 @@
+// C ABI of the two-pass gzip path: planning on the host, launch sequence on a
+// HIP stream, result read-back.  See include/gzgpu.h.
+#include <hip/hip_runtime.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <thread>
+#include <new>
+#include <vector>
+
+#include "../../include/gzgpu.h"
+#include "gz_internal.h"
+
+using namespace gzgpu;
+
+extern "C" {
+hipError_t gzk_init(ChunkState *, uint32_t, FileState *, uint32_t, Counters *, hipStream_t);
+hipError_t gzk_scan(const FileDesc *, const ChunkDesc *, ChunkState *, const uint32_t *, uint32_t, uint32_t,
+                    hipStream_t);
+hipError_t gzk_capacity(uint32_t, const FileDesc *, ChunkDesc *, const ChunkState *, uint32_t, hipStream_t);
+hipError_t gzk_inflate(int, uint32_t, const FileDesc *, const ChunkDesc *, ChunkState *, const uint32_t *, uint32_t,
+                       Counters *, uint16_t *, hipStream_t);
+hipError_t gzk_stitch(int, uint32_t, const FileDesc *, const ChunkDesc *, ChunkState *, uint32_t, Counters *,
+                      uint16_t *, hipStream_t);
+hipError_t gzk_finalize(int, uint32_t, const FileDesc *, const ChunkDesc *, ChunkState *, FileState *, uint16_t *,
+                        hipStream_t);
+hipError_t gzk_tilescan(const ChunkDesc *, const ChunkState *, const FileState *, uint32_t, uint64_t *, hipStream_t);
+hipError_t gzk_propagate(uint32_t, const FileDesc *, const ChunkDesc *, const ChunkState *, const FileState *,
+                         uint8_t *, const uint16_t *, hipStream_t);
+hipError_t gzk_translate(uint32_t, const FileDesc *, const ChunkDesc *, const ChunkState *, FileState *,
+                         const uint64_t *, uint32_t, const uint8_t *, const uint16_t *, Counters *, hipStream_t);
+}
+
+namespace {
+
+thread_local char g_err[256];
+
+uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
+
+// CRC-32 (RFC 1952 section 8), table driven; used only for the FHCRC field.
+uint32_t crc32_host(const uint8_t *p, size_t n) {
+  static uint32_t tab[256];
+  static bool init = false;
+  if (!init) {
+    for (uint32_t i = 0; i < 256; i++) {
+      uint32_t c = i;
+      for (int k = 0; k < 8; k++) c = (c >> 1) ^ (0xEDB88320u & (0u - (c & 1u)));
+      tab[i] = c;
+    }
+    init = true;
+  }
+  uint32_t c = 0xFFFFFFFFu;
+  for (size_t i = 0; i < n; i++) c = tab[(c ^ p[i]) & 0xFFu] ^ (c >> 8);
+  return c ^ 0xFFFFFFFFu;
+}
+
+// gzip member header (RFC 1952 section 2.3): returns the payload start or -1.
+int64_t parse_gzip_header(const uint8_t *h, size_t n) {
+  if (n < 10) return -1;
+  if (h[0] != 0x1f || h[1] != 0x8b || h[2] != 8) return -1;
+  const unsigned flg = h[3];
+  if (flg & 0xE0u) return -1;
+  size_t p = 10;
+  if (flg & 4u) {
+    if (p + 2 > n) return -1;
+    p += 2 + ((size_t)h[p] | ((size_t)h[p + 1] << 8));
+    if (p > n) return -1;
+  }
+  for (unsigned bit : {8u, 16u}) {
+    if (flg & bit) {
+      while (p < n && h[p]) p++;
+      if (p >= n) return -1;
+      p++;
+    }
+  }
+  if (flg & 2u) {
+    if (p + 2 > n) return -1;
+    const uint32_t want = (uint32_t)h[p] | ((uint32_t)h[p + 1] << 8);
+    if ((crc32_host(h, p) & 0xFFFFu) != want) return -1;
+    p += 2;
+  }
+  return (int64_t)p;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+  snprintf(g_err, sizeof(g_err), "%s: %s", what, hipGetErrorString(e));
+  return GZ_E_HIP;
+}
+
+}  // namespace
+
+struct gz_plan_s {
+  gz_opts opts{};
+  uint32_t win = 16384;
+  uint32_t groups = 8;
+  int n_cu = 256;
+  int device = 0;
+  std::vector<FileDesc> files;
+  std::vector<ChunkDesc> chunks;
+  std::vector<uint32_t> order;
+  std::vector<uint32_t> scan_list;
+  Layout lay{};
+  uint64_t order_bytes = 0, scan_off = 0;
+  uint8_t *pinned = nullptr;
+  hipEvent_t upload_done = nullptr;
+  bool upload_pending = false;
+  // last launch
+  uint8_t *ws = nullptr;
+  hipStream_t stream = nullptr;
+  bool launched = false;
+  bool fetched = false;
+  std::vector<FileState> fst;
+  std::vector<ChunkState> cst;
+  std::vector<ChunkDesc> cdev;  // the device's chunk table after the run (capacities)
+  std::vector<gz_job> jobs;
+};
+
+static int plan_common(gz_plan_t p) {
+  const uint32_t F = (uint32_t)p->jobs.size();
+  p->files.clear();
+  p->chunks.clear();
+  uint64_t sym_elems = 0;
+  for (uint32_t f = 0; f < F; f++) {
+    const gz_job &j = p->jobs[f];
+    if (!j.d_comp || j.comp_len < 18) {
+      snprintf(g_err, sizeof(g_err), "file %u: input too short for a gzip member", f);
+      return j.d_comp ? GZ_E_HEADER : GZ_E_ARG;
+    }
+    // header bytes (grown if the optional fields are long) and the trailer
+    size_t hn = (size_t)std::min<uint64_t>(j.comp_len, 4096);
+    std::vector<uint8_t> hb;
+    int64_t h = -1;
+    for (;;) {
+      hb.resize(hn);
+      hipError_t e = hipMemcpy(hb.data(), j.d_comp, hn, hipMemcpyDeviceToHost);
+      if (e != hipSuccess) return hip_fail(e, "reading the gzip header");
+      h = parse_gzip_header(hb.data(), hn);
+      if (h >= 0 || hn == j.comp_len) break;
+      hn = (size_t)std::min<uint64_t>(j.comp_len, (uint64_t)hn * 4);
+    }
+    if (h < 0 || (uint64_t)h + 8 >= j.comp_len) {
+      snprintf(g_err, sizeof(g_err), "file %u: invalid gzip member header", f);
+      return GZ_E_HEADER;
+    }
+    uint8_t tr[8];
+    hipError_t e = hipMemcpy(tr, (const uint8_t *)j.d_comp + j.comp_len - 8, 8, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "reading the gzip trailer");
+    FileDesc fd{};
+    fd.comp = (const uint8_t *)j.d_comp;
+    fd.comp_len = j.comp_len;
+    fd.payload_bit = 8ull * (uint64_t)h;
+    fd.trailer_byte = j.comp_len - 8;
+    fd.out = (uint8_t *)j.d_out;
+    fd.out_cap = j.out_cap;
+    fd.crc = (uint32_t)tr[0] | ((uint32_t)tr[1] << 8) | ((uint32_t)tr[2] << 16) | ((uint32_t)tr[3] << 24);
+    fd.isize = (uint32_t)tr[4] | ((uint32_t)tr[5] << 8) | ((uint32_t)tr[6] << 16) | ((uint32_t)tr[7] << 24);
+    const uint64_t P = fd.trailer_byte - (uint64_t)h;  // payload bytes
+    uint64_t N = j.n_chunks > 0 ? (uint64_t)j.n_chunks : (P + p->opts.chunk_bytes - 1) / p->opts.chunk_bytes;
+    N = std::max<uint64_t>(1, std::min<uint64_t>(N, P));
+    fd.first_chunk = (uint32_t)p->chunks.size();
+    fd.n_chunks = (uint32_t)N;
+    for (uint64_t i = 0; i < N; i++) {
+      ChunkDesc cd{};
+      const uint64_t a = (uint64_t)h + (uint64_t)((unsigned __int128)i * P / N);
+      const uint64_t b = (uint64_t)h + (uint64_t)((unsigned __int128)(i + 1) * P / N);
+      cd.lo_bit = 8 * a;
+      cd.hi_bit = 8 * b;
+      cd.file = f;
+      cd.index = (uint32_t)i;
+      cd.flags = i == 0 ? CF_FIRST : 0u;
+      p->chunks.push_back(cd);
+    }
+    // the chunks' capacities are set on the device from their actual spans;
+    // their sum is bounded by this
+    fd.pool_base = sym_elems;
+    fd.pool_elems = (uint64_t)p->opts.sym_factor * (P + N) + N * (SYM_SLACK + FLUSH_UNIT);
+    sym_elems += align_up(fd.pool_elems, FLUSH_UNIT);
+    p->files.push_back(fd);
+  }
+  const uint32_t N = (uint32_t)p->chunks.size();
+  // inflate order: longest compressed range first
+  p->order.resize(N);
+  for (uint32_t i = 0; i < N; i++) p->order[i] = i;
+  std::stable_sort(p->order.begin(), p->order.end(), [&](uint32_t x, uint32_t y) {
+    return (p->chunks[x].hi_bit - p->chunks[x].lo_bit) > (p->chunks[y].hi_bit - p->chunks[y].lo_bit);
+  });
+  p->scan_list.clear();
+  for (uint32_t i = 0; i < N; i++)
+    if (!(p->chunks[i].flags & CF_FIRST)) p->scan_list.push_back(i);
+  // workspace layout
+  Layout &L = p->lay;
+  uint64_t o = 0;
+  L.files_off = o;
+  o = align_up(o + F * sizeof(FileDesc), 256);
+  L.chunks_off = o;
+  o = align_up(o + (uint64_t)N * sizeof(ChunkDesc), 256);
+  L.order_off = o;
+  o = align_up(o + (uint64_t)N * 4, 256);
+  p->scan_off = o;
+  o = align_up(o + (uint64_t)p->scan_list.size() * 4 + 4, 256);
+  L.table_bytes = o;
+  L.cstate_off = o;
+  o = align_up(o + (uint64_t)N * sizeof(ChunkState), 256);
+  L.fstate_off = o;
+  o = align_up(o + F * sizeof(FileState), 256);
+  L.counters_off = o;
+  o = align_up(o + sizeof(Counters), 256);
+  L.tiles_off = o;
+  o = align_up(o + ((uint64_t)N + 1) * 8, 256);
+  L.win_off = o;
+  o = align_up(o + (uint64_t)N * WINDOW, 256);
+  L.sym_off = o;
+  L.sym_elems = sym_elems;
+  o = align_up(o + sym_elems * 2, 256);
+  L.total = o;
+  // pinned copy of the job table
+  if (p->pinned) (void)hipHostFree(p->pinned);
+  p->pinned = nullptr;
+  hipError_t e = hipHostMalloc((void **)&p->pinned, L.table_bytes, hipHostMallocDefault);
+  if (e != hipSuccess) return hip_fail(e, "pinned job table");
+  return GZ_OK;
+}
+
+static void fill_defaults(gz_plan_t p, const gz_opts *opts) {
+  if (opts) p->opts = *opts;
+  if (p->opts.chunk_bytes == 0) p->opts.chunk_bytes = 1 << 20;
+  if (p->opts.sym_factor == 0) p->opts.sym_factor = 8;
+  p->win = p->opts.window_syms == 8192 || p->opts.window_syms == 32768 ? p->opts.window_syms : 16384;
+  p->groups = p->opts.scan_groups ? p->opts.scan_groups : 8;
+  (void)hipGetDevice(&p->device);
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, p->device) == hipSuccess) p->n_cu = prop.multiProcessorCount;
+}
+
+static int make_plan(gz_plan_t *plan, const gz_job *jobs, int n, const gz_opts *opts) {
+  if (!plan || !jobs || n <= 0) return GZ_E_ARG;
+  *plan = nullptr;
+  gz_plan_t p = new (std::nothrow) gz_plan_s();
+  if (!p) return GZ_E_ARG;
+  fill_defaults(p, opts);
+  p->jobs.assign(jobs, jobs + n);
+  int r = plan_common(p);
+  if (r != GZ_OK) {
+    gz_plan_destroy(p);
+    return r;
+  }
+  (void)hipEventCreateWithFlags(&p->upload_done, hipEventDisableTiming);
+  *plan = p;
+  return GZ_OK;
+}
+
+extern "C" {
+
+int gz_plan(gz_plan_t *plan, const void *d_comp, size_t comp_len, int n_chunks, const gz_opts *opts) {
+  if (!d_comp || comp_len == 0 || n_chunks < 0) return GZ_E_ARG;
+  gz_job j{};
+  j.d_comp = d_comp;
+  j.comp_len = comp_len;
+  j.n_chunks = n_chunks;
+  return make_plan(plan, &j, 1, opts);
+}
+
+int gz_plan_batch(gz_plan_t *plan, const gz_job *jobs, int n_jobs, const gz_opts *opts) {
+  return make_plan(plan, jobs, n_jobs, opts);
+}
+
+int gz_plan_info(gz_plan_t p, gz_info *info) {
+  if (!p || !info) return GZ_E_ARG;
+  memset(info, 0, sizeof(*info));
+  info->ws_bytes = p->lay.total;
+  info->payload_start = p->files[0].payload_bit / 8;
+  info->payload_end = p->files[0].trailer_byte;
+  info->n_files = (uint32_t)p->files.size();
+  info->n_chunks = (uint32_t)p->chunks.size();
+  info->crc32 = p->files[0].crc;
+  info->isize = p->files[0].isize;
+  return GZ_OK;
+}
+
+static int launch(gz_plan_t p, uint8_t *ws, size_t ws_bytes, hipStream_t st) {
+  if (!ws || ws_bytes < p->lay.total || ((uintptr_t)ws & 255u)) {
+    snprintf(g_err, sizeof(g_err), "workspace needs %llu bytes, 256-byte aligned",
+             (unsigned long long)p->lay.total);
+    return ws && ws_bytes < p->lay.total ? GZ_E_CAPACITY : GZ_E_ARG;
+  }
+  const Layout &L = p->lay;
+  const uint32_t F = (uint32_t)p->files.size(), N = (uint32_t)p->chunks.size();
+  if (p->upload_pending) {
+    (void)hipEventSynchronize(p->upload_done);
+    p->upload_pending = false;
+  }
+  memcpy(p->pinned + L.files_off, p->files.data(), F * sizeof(FileDesc));
+  memcpy(p->pinned + L.chunks_off, p->chunks.data(), (size_t)N * sizeof(ChunkDesc));
+  memcpy(p->pinned + L.order_off, p->order.data(), (size_t)N * 4);
+  if (!p->scan_list.empty()) memcpy(p->pinned + p->scan_off, p->scan_list.data(), p->scan_list.size() * 4);
+  hipError_t e = hipMemcpyAsync(ws, p->pinned, L.table_bytes, hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return hip_fail(e, "job table upload");
+  (void)hipEventRecord(p->upload_done, st);
+  p->upload_pending = true;
+
+  const FileDesc *files = (const FileDesc *)(ws + L.files_off);
+  const ChunkDesc *chunks = (const ChunkDesc *)(ws + L.chunks_off);
+  const uint32_t *order = (const uint32_t *)(ws + L.order_off);
+  const uint32_t *scan = (const uint32_t *)(ws + p->scan_off);
+  ChunkState *cs = (ChunkState *)(ws + L.cstate_off);
+  FileState *fs = (FileState *)(ws + L.fstate_off);
+  Counters *ctr = (Counters *)(ws + L.counters_off);
+  uint64_t *tiles = (uint64_t *)(ws + L.tiles_off);
+  uint8_t *wins = ws + L.win_off;
+  uint16_t *pool = (uint16_t *)(ws + L.sym_off);
+
+  const uint32_t lds_per_cu = 160 * 1024;
+  const uint32_t per_wave = (uint32_t)(6272 + 2 * p->win + 512);
+  uint32_t waves_per_cu = p->opts.inflate_waves_per_cu ? p->opts.inflate_waves_per_cu
+                                                       : std::max<uint32_t>(1, lds_per_cu / per_wave);
+  uint32_t grid = std::min<uint32_t>(N, waves_per_cu * (uint32_t)p->n_cu);
+  if (grid == 0) grid = 1;
+
+  if ((e = gzk_init(cs, N, fs, F, ctr, st)) != hipSuccess) return hip_fail(e, "init");
+  if ((e = gzk_scan(files, chunks, cs, scan, (uint32_t)p->scan_list.size(), p->groups, st)) != hipSuccess)
+    return hip_fail(e, "scan");
+  if ((e = gzk_capacity(F, files, (ChunkDesc *)(ws + L.chunks_off), cs, p->opts.sym_factor, st)) != hipSuccess)
+    return hip_fail(e, "capacity");
+  if ((e = gzk_inflate((int)p->win, grid, files, chunks, cs, order, N, ctr, pool, st)) != hipSuccess)
+    return hip_fail(e, "inflate");
+  if ((e = gzk_stitch((int)p->win, grid, files, chunks, cs, N, ctr, pool, st)) != hipSuccess)
+    return hip_fail(e, "stitch");
+  if ((e = gzk_finalize((int)p->win, F, files, chunks, cs, fs, pool, st)) != hipSuccess) return hip_fail(e, "finalize");
+  if ((e = gzk_tilescan(chunks, cs, fs, N, tiles, st)) != hipSuccess) return hip_fail(e, "tilescan");
+  if ((e = gzk_propagate(F, files, chunks, cs, fs, wins, pool, st)) != hipSuccess) return hip_fail(e, "propagate");
+  if ((e = gzk_translate((uint32_t)p->n_cu * 8, files, chunks, cs, fs, tiles, N, wins, pool, ctr, st)) !=
+      hipSuccess)
+    return hip_fail(e, "translate");
+  p->ws = ws;
+  p->stream = st;
+  p->launched = true;
+  p->fetched = false;
+  return GZ_OK;
+}
+
+int gz_decompress(gz_plan_t p, void *d_out, size_t out_cap, void *d_ws, size_t ws_bytes, void *stream) {
+  if (!p || p->files.size() != 1) return GZ_E_ARG;
+  if (!d_out && out_cap) return GZ_E_ARG;
+  p->files[0].out = (uint8_t *)d_out;
+  p->files[0].out_cap = d_out ? out_cap : 0;
+  return launch(p, (uint8_t *)d_ws, ws_bytes, (hipStream_t)stream);
+}
+
+int gz_decompress_batch(gz_plan_t p, void *d_ws, size_t ws_bytes, void *stream) {
+  if (!p) return GZ_E_ARG;
+  return launch(p, (uint8_t *)d_ws, ws_bytes, (hipStream_t)stream);
+}
+
+static int fetch(gz_plan_t p) {
+  if (!p->launched) return GZ_E_NOT_READY;
+  if (p->fetched) return GZ_OK;
+  // wait with a deadline (GZGPU_TIMEOUT_S, default 120 s) instead of blocking
+  // forever on a stream that does not finish
+  double limit = 120.0;
+  if (const char *t = getenv("GZGPU_TIMEOUT_S")) limit = atof(t);
+  const auto t0 = std::chrono::steady_clock::now();
+  hipError_t e;
+  for (;;) {
+    e = hipStreamQuery(p->stream);
+    if (e != hipErrorNotReady) break;
+    const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (el > limit) {
+      snprintf(g_err, sizeof(g_err), "the stream did not finish within %.0f s", limit);
+      return GZ_E_HIP;
+    }
+    std::this_thread::sleep_for(std::chrono::microseconds(el < 0.01 ? 20 : 1000));
+  }
+  if (e != hipSuccess) return hip_fail(e, "stream synchronize");
+  const uint32_t F = (uint32_t)p->files.size(), N = (uint32_t)p->chunks.size();
+  p->fst.resize(F);
+  p->cst.resize(N);
+  e = hipMemcpy(p->fst.data(), p->ws + p->lay.fstate_off, F * sizeof(FileState), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "reading file state");
+  e = hipMemcpy(p->cst.data(), p->ws + p->lay.cstate_off, (size_t)N * sizeof(ChunkState), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "reading chunk state");
+  p->cdev.resize(N);
+  e = hipMemcpy(p->cdev.data(), p->ws + p->lay.chunks_off, (size_t)N * sizeof(ChunkDesc), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "reading chunk table");
+  p->fetched = true;
+  return GZ_OK;
+}
+
+int gz_result_get(gz_plan_t p, int file, gz_result *res) {
+  if (!p || !res || file < 0 || file >= (int)p->files.size()) return GZ_E_ARG;
+  int r = fetch(p);
+  if (r != GZ_OK) return r;
+  const FileState &s = p->fst[file];
+  const FileDesc &fd = p->files[file];
+  memset(res, 0, sizeof(*res));
+  res->status = s.status;
+  res->n_chunks = fd.n_chunks;
+  res->out_len = s.out_len;
+  res->out_needed = s.out_needed;
+  res->n_nonempty = s.n_nonempty;
+  res->n_repairs = s.n_repairs;
+  res->n_extended = s.n_extended;
+  res->n_retries = s.n_retries;
+  res->n_syms = s.n_syms;
+  res->n_placeholders = s.n_placeholders;
+  res->n_blocks = s.n_blocks;
+  if (s.overflow) {
+    // the workspace of a plan whose symbol factor covers the worst chunk
+    double worst = 0;
+    for (uint32_t c = fd.first_chunk; c < fd.first_chunk + fd.n_chunks; c++)
+      if (p->cst[c].flags & CS_OVERFLOW) {
+        const ChunkDesc &d = p->cdev[c];
+        const double span = d.sym_cap > SYM_SLACK ? (double)(d.sym_cap - SYM_SLACK) / p->opts.sym_factor : 1.0;
+        worst = std::max(worst, (double)p->cst[c].needed / span);
+      }
+    const uint64_t f2 = (uint64_t)(worst * 1.25) + 1;
+    res->ws_needed = p->lay.total + 2 * (f2 > p->opts.sym_factor ? f2 - p->opts.sym_factor : 1) *
+                                        (uint64_t)((fd.trailer_byte - fd.payload_bit / 8) + fd.n_chunks);
+  }
+  return GZ_OK;
+}
+
+int gz_chunk_table(gz_plan_t p, int file, uint64_t *start, uint64_t *cand, uint64_t *end, uint64_t *len,
+                   uint64_t *out_off, int32_t *status, uint32_t *flags) {
+  if (!p || file < 0 || file >= (int)p->files.size()) return GZ_E_ARG;
+  int r = fetch(p);
+  if (r != GZ_OK) return r;
+  const FileDesc &fd = p->files[file];
+  for (uint32_t i = 0; i < fd.n_chunks; i++) {
+    const ChunkState &s = p->cst[fd.first_chunk + i];
+    if (start) start[i] = s.start;
+    if (cand) cand[i] = s.cand;
+    if (end) end[i] = s.end;
+    if (len) len[i] = s.len;
+    if (out_off) out_off[i] = s.out_off;
+    if (status) status[i] = s.status;
+    if (flags) flags[i] = s.flags;
+  }
+  return GZ_OK;
+}
+
+int gz_debug_layout(gz_plan_t p, int file, uint64_t *sym_off, uint64_t *win_index, void **sym_base, void **win_base) {
+  if (!p || file < 0 || file >= (int)p->files.size() || !p->launched) return GZ_E_ARG;
+  int r = fetch(p);
+  if (r != GZ_OK) return r;
+  const FileDesc &fd = p->files[file];
+  for (uint32_t i = 0; i < fd.n_chunks; i++) {
+    if (sym_off) sym_off[i] = p->cdev[fd.first_chunk + i].sym_off;
+    if (win_index) win_index[i] = fd.first_chunk + i;
+  }
+  if (sym_base) *sym_base = p->ws + p->lay.sym_off;
+  if (win_base) *win_base = p->ws + p->lay.win_off;
+  return GZ_OK;
+}
+
+void gz_plan_destroy(gz_plan_t p) {
+  if (!p) return;
+  if (p->upload_pending) (void)hipEventSynchronize(p->upload_done);
+  if (p->upload_done) (void)hipEventDestroy(p->upload_done);
+  if (p->pinned) (void)hipHostFree(p->pinned);
+  delete p;
+}
+
+const char *gz_strerror(int code) {
+  switch (code) {
+    case GZ_OK: return "ok";
+    case GZ_E_ARG: return g_err[0] ? g_err : "invalid argument";
+    case GZ_E_HEADER: return "invalid gzip header";
+    case GZ_E_UNSUPPORTED: return "unsupported input (data after the first gzip member)";
+    case GZ_E_DATA: return "invalid compressed data";
+    case GZ_E_CAPACITY: return "output or workspace too small";
+    case GZ_E_SIZE: return "decompressed size does not match the trailer";
+    case GZ_E_HIP: return g_err[0] ? g_err : "HIP runtime error";
+    case GZ_E_NOT_READY: return "no decompression launched on this plan";
+    default: return "unknown error";
+  }
+}
+
+int gz_device_info(int dev, int *n_cu, int *lds_bytes) {
+  hipDeviceProp_t prop;
+  hipError_t e = hipGetDeviceProperties(&prop, dev);
+  if (e != hipSuccess) return hip_fail(e, "device properties");
+  if (n_cu) *n_cu = prop.multiProcessorCount;
+  if (lds_bytes) *lds_bytes = (int)prop.maxSharedMemoryPerMultiProcessor;
+  return GZ_OK;
+}
+
+}  // extern "C"

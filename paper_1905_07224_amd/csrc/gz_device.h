@@ -1,0 +1,506 @@
+// Device building blocks for the two-pass gzip path on gfx950 (CDNA4).
+//
+// A DEFLATE decoder that one 64-lane wavefront runs as a single sequential
+// decoder: the bit position, the current symbol and all control flow are
+// wave-uniform (scalar registers), the 64 lanes hold a 256-byte window of the
+// compressed stream, build the Huffman lookup tables in LDS, copy matches and
+// move output to HBM in coalesced 16-byte stores.
+//
+// Format: RFC 1951 (the paper defers to it in Section III).  Symbolic output:
+// decompress(C_i, w_hat_i) of Section VI-C, where the context before a chunk
+// is the 32768 unique symbols U_j, written 0x8000 | j.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "gz_internal.h"
+
+namespace gzgpu {
+
+// ---------------------------------------------------------------------------
+// Small wave helpers
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+// Orders LDS stores of some lanes before LDS loads of other lanes of the same
+// wave.  A wave executes its LDS instructions in order, so this is only a
+// compiler-level barrier on the GPU.
+__device__ __forceinline__ void wave_sync() { __builtin_amdgcn_wave_barrier(); }
+__device__ __forceinline__ uint64_t lanes_below() { return (1ull << lane_id()) - 1ull; }
+
+template <typename T>
+__device__ __forceinline__ T uni(T v) {  // value of lane 0, as a scalar
+  return (T)__builtin_amdgcn_readfirstlane((int)v);
+}
+__device__ __forceinline__ uint32_t uni32(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); }
+__device__ __forceinline__ uint64_t uni64(uint64_t v) {
+  uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+  uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ bool ascii_text(uint32_t c) {
+  // printable ASCII of the block-start checks: TAB, LF, CR, 0x20..0x7E
+  return c == 9u || c == 10u || c == 13u || (c >= 32u && c <= 126u);
+}
+
+// ---------------------------------------------------------------------------
+// Compressed input.  Bit positions are counted from the first byte of the
+// file.  The buffer may sit at any byte address: loads use the aligned dword
+// that holds the byte and zero the bytes outside [0, n).  An aligned dword
+// that contains at least one byte of the buffer lies in the same page as that
+// byte, so these loads never leave mapped memory.
+// ---------------------------------------------------------------------------
+
+struct Src {
+  const uint32_t *base;  // comp rounded down to 4 bytes
+  uint32_t mis;          // comp & 3
+  uint64_t nbytes;
+  uint64_t end_bits;     // 8 * nbytes
+
+  __device__ void init(const uint8_t *comp, uint64_t n) {
+    uintptr_t p = (uintptr_t)comp;
+    mis = (uint32_t)(p & 3u);
+    base = (const uint32_t *)(p - mis);
+    nbytes = n;
+    end_bits = 8ull * n;
+  }
+  // dword D of the aligned view (file byte 4D - mis .. 4D - mis + 3)
+  __device__ __forceinline__ uint32_t dw(int64_t D) const {
+    int64_t b0 = D * 4 - (int64_t)mis;  // file byte of the dword's first byte
+    if (b0 >= 0 && b0 + 4 <= (int64_t)nbytes) return __builtin_nontemporal_load(base + D);
+    if (b0 + 4 <= 0 || b0 >= (int64_t)nbytes) return 0u;
+    uint32_t w = base[D];
+    uint32_t m = 0;
+#pragma unroll
+    for (int k = 0; k < 4; k++)
+      if (b0 + k >= 0 && b0 + k < (int64_t)nbytes) m |= 0xFFu << (8 * k);
+    return w & m;
+  }
+  // 64 bits starting at file bit b (bits past the end read as zero); per lane
+  __device__ __forceinline__ uint64_t peek64(uint64_t b) const {
+    uint64_t a = b + 8ull * mis;
+    int64_t D = (int64_t)(a >> 5);
+    uint32_t s = (uint32_t)(a & 31);
+    uint64_t lo = ((uint64_t)dw(D + 1) << 32) | dw(D);
+    uint64_t hi = dw(D + 2);
+    return s ? ((lo >> s) | (hi << (64 - s))) : lo;
+  }
+  __device__ __forceinline__ uint32_t byte(uint64_t fb) const {
+    uint64_t a = fb + mis;
+    return (dw((int64_t)(a >> 2)) >> (8 * (a & 3))) & 0xFFu;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Wave-uniform bit reader.  Lane l holds the dword D of the aligned view with
+// D = l (mod 64) for D in [lo, lo + 64); lo is a multiple of 32.  When the read
+// position enters the upper half, the lanes of the consumed half take the
+// dwords prefetched one half earlier and prefetch the next ones, so a refill
+// never waits on memory in the decode loop.
+// ---------------------------------------------------------------------------
+
+struct WaveBits {
+  Src s;
+  uint64_t pos;  // file bit position (uniform)
+  int64_t lo;    // first dword held (uniform)
+  uint32_t win;  // per lane
+  uint32_t nxt;  // per lane
+
+  __device__ __forceinline__ int64_t dword_of(uint64_t p) const { return (int64_t)((p + 8ull * s.mis) >> 5); }
+
+  __device__ void init(uint64_t p) {
+    pos = p;
+    lo = dword_of(p) & ~31ll;
+    int l = lane_id();
+    int64_t D = lo + ((l - (int)(lo & 63)) & 63);
+    win = s.dw(D);
+    nxt = (D < lo + 32) ? s.dw(D + 64) : 0u;
+  }
+  __device__ __forceinline__ void advance() {
+    int64_t D = dword_of(pos);
+    if (D < lo + 32) return;
+    if (D >= lo + 48) {  // a jump (stored block): start over at pos
+      init(pos);
+      return;
+    }
+    int l = lane_id();
+    int64_t Dl = lo + ((l - (int)(lo & 63)) & 63);
+    bool old = Dl < lo + 32;
+    win = old ? nxt : win;
+    lo += 32;
+    int64_t D2 = lo + ((l - (int)(lo & 63)) & 63);
+    if (D2 < lo + 32) nxt = s.dw(D2 + 64);
+  }
+  // 64 bits at pos (valid while pos is inside the lower half, kept by advance)
+  __device__ __forceinline__ uint64_t peek() const {
+    uint64_t a = pos + 8ull * s.mis;
+    int64_t D = (int64_t)(a >> 5);
+    uint32_t sh = (uint32_t)(a & 31);
+    uint32_t w0 = (uint32_t)__builtin_amdgcn_readlane((int)win, (int)(D & 63));
+    uint32_t w1 = (uint32_t)__builtin_amdgcn_readlane((int)win, (int)((D + 1) & 63));
+    uint32_t w2 = (uint32_t)__builtin_amdgcn_readlane((int)win, (int)((D + 2) & 63));
+    uint64_t v = ((uint64_t)w1 << 32) | w0;
+    return sh ? ((v >> sh) | ((uint64_t)w2 << (64 - sh))) : v;
+  }
+  __device__ __forceinline__ void skip(uint32_t n) {
+    pos += n;
+    advance();
+  }
+  __device__ __forceinline__ bool past_end() const { return pos > s.end_bits; }
+};
+
+// ---------------------------------------------------------------------------
+// Huffman lookup tables (RFC 1951 section 3.2.2 canonical codes).
+// Entry: [3:0] code length, [7:4] kind, [15:8] extra bits or literal byte,
+// [31:16] base length / distance.
+// ---------------------------------------------------------------------------
+
+enum : uint32_t { K_LIT = 0, K_LEN = 1, K_EOB = 2, K_LONG = 3, K_BAD = 4, K_BADSYM = 5 };
+
+constexpr int LIT_BITS = 10;
+constexpr int DIST_BITS = 8;
+constexpr int CL_BITS = 7;
+
+// lengths 3..258 (section 3.2.5): codes 257..264 carry no extra bits, then
+// four codes per extra-bit count 1..5, then 285 = 258
+__device__ __forceinline__ uint32_t litlen_entry(uint32_t sym, uint32_t len) {
+  if (sym < 256u) return len | (K_LIT << 4) | (sym << 8);
+  if (sym == 256u) return len | (K_EOB << 4);
+  if (sym <= 285u) {
+    uint32_t i = sym - 257u, ex, base;
+    if (i < 8u) {
+      ex = 0;
+      base = 3u + i;
+    } else if (i == 28u) {
+      ex = 0;
+      base = 258u;
+    } else {
+      ex = (i - 4u) >> 2;
+      base = ((4u + (i & 3u)) << ex) + 3u;
+    }
+    return len | (K_LEN << 4) | (ex << 8) | (base << 16);
+  }
+  return len | (K_BADSYM << 4);
+}
+// distances 1..32768: codes 0..3 exact, then two codes per extra-bit count 1..13
+__device__ __forceinline__ uint32_t dist_entry(uint32_t sym, uint32_t len) {
+  if (sym < 30u) {
+    uint32_t ex, base;
+    if (sym < 4u) {
+      ex = 0;
+      base = sym + 1u;
+    } else {
+      ex = (sym >> 1) - 1u;
+      base = ((2u + (sym & 1u)) << ex) + 1u;
+    }
+    return len | (K_LEN << 4) | (ex << 8) | (base << 16);
+  }
+  return len | (K_BADSYM << 4);
+}
+__device__ __forceinline__ uint32_t cl_entry(uint32_t sym, uint32_t len) { return len | (sym << 8); }
+
+struct TreeInfo {
+  uint16_t first[16];  // first canonical code of each length
+  uint16_t count[16];
+  uint16_t base[16];   // index of the first symbol of each length in the sorted list
+};
+
+enum TreeKind { TREE_LIT = 0, TREE_DIST = 1, TREE_CL = 2 };
+
+// Per-tree build, run by the whole wave.  lens: n code lengths in LDS.
+// Returns the Kraft remainder scaled by 2^15 (0 complete, > 0 incomplete,
+// < 0 over-subscribed) and the number of codes.  With fill, also writes the
+// sorted symbol list, the per-length info and the 2^LB-entry lookup table
+// (codes longer than LB get K_LONG, unused bit patterns K_BAD).
+template <int LB, int KIND>
+__device__ int build_tree(const uint8_t *lens, int n, uint32_t *tab, TreeInfo *ti, uint16_t *sorted, int *ncodes,
+                          bool fill) {
+  const int lane = lane_id();
+  int cnt[16];
+#pragma unroll
+  for (int l = 0; l < 16; l++) cnt[l] = 0;
+  for (int b = 0; b < n; b += 64) {
+    int s = b + lane;
+    int L = s < n ? (int)lens[s] : 0;
+#pragma unroll
+    for (int l = 1; l < 16; l++) cnt[l] += __popcll(__ballot(L == l));
+  }
+  int nc = 0, left = 32768;
+#pragma unroll
+  for (int l = 1; l < 16; l++) {
+    nc += cnt[l];
+    left -= cnt[l] << (15 - l);
+  }
+  *ncodes = nc;
+  if (!fill || left < 0) return left;
+  int first[16], base[16];
+  {
+    int code = 0, b = 0;
+    first[0] = 0;
+    base[0] = 0;
+#pragma unroll
+    for (int l = 1; l < 16; l++) {
+      code = (code + (l > 1 ? cnt[l - 1] : 0)) << 1;
+      first[l] = code;
+      base[l] = b;
+      b += cnt[l];
+    }
+  }
+  if (lane < 16) {
+    int f = 0, c = 0, bb = 0;
+#pragma unroll
+    for (int l = 0; l < 16; l++)
+      if (lane == l) {
+        f = first[l];
+        c = cnt[l];
+        bb = base[l];
+      }
+    ti->first[lane] = (uint16_t)f;
+    ti->count[lane] = (uint16_t)c;
+    ti->base[lane] = (uint16_t)bb;
+  }
+  // symbols in (length, value) order
+  {
+    int run[16];
+#pragma unroll
+    for (int l = 0; l < 16; l++) run[l] = base[l];
+    const uint64_t below = lanes_below();
+    for (int b = 0; b < n; b += 64) {
+      int s = b + lane;
+      int L = s < n ? (int)lens[s] : 0;
+      int at = -1;
+#pragma unroll
+      for (int l = 1; l < 16; l++) {
+        uint64_t m = __ballot(L == l);
+        if (L == l) at = run[l] + __popcll(m & below);
+        run[l] += __popcll(m);
+      }
+      if (at >= 0) sorted[at] = (uint16_t)s;
+    }
+  }
+  wave_sync();
+  // lookup table: the LB-bit prefix P (first bit read = most significant)
+  // falls in the left-justified code interval of exactly one length
+  const int endLB = (first[LB] + cnt[LB]);  // in LB-bit units
+  const int end15 = first[15] + cnt[15];    // in 15-bit units
+  for (int x = lane; x < (1 << LB); x += 64) {
+    int P = (int)(__builtin_bitreverse32((uint32_t)x) >> (32 - LB));
+    uint32_t e;
+    if (P < endLB) {
+      int idx = 0, len = 0;
+      bool done = false;
+#pragma unroll
+      for (int l = 1; l <= LB; l++) {
+        int endl = (first[l] + cnt[l]) << (LB - l);
+        if (!done && P < endl) {
+          idx = base[l] + (P >> (LB - l)) - first[l];
+          len = l;
+          done = true;
+        }
+      }
+      uint32_t sym = sorted[idx];
+      e = KIND == TREE_LIT ? litlen_entry(sym, (uint32_t)len)
+          : KIND == TREE_DIST ? dist_entry(sym, (uint32_t)len)
+                              : cl_entry(sym, (uint32_t)len);
+    } else if ((P << (15 - LB)) < end15) {
+      e = K_LONG << 4;
+    } else {
+      e = K_BAD << 4;
+    }
+    tab[x] = e;
+  }
+  wave_sync();
+  return left;
+}
+
+// Codes longer than the table: compare the 15-bit prefix against each length.
+template <int LB, int KIND>
+__device__ __forceinline__ uint32_t decode_long(uint64_t v, const TreeInfo *ti, const uint16_t *sorted) {
+  uint32_t r = __builtin_bitreverse32((uint32_t)v) >> 17;  // next 15 bits, first bit most significant
+  for (int l = LB + 1; l <= 15; l++) {
+    uint32_t c = r >> (15 - l);
+    uint32_t f = uni32(ti->first[l]), n = uni32(ti->count[l]);
+    if (c - f < n) {
+      uint32_t sym = uni32(sorted[uni32(ti->base[l]) + (c - f)]);
+      return KIND == TREE_LIT ? litlen_entry(sym, (uint32_t)l) : dist_entry(sym, (uint32_t)l);
+    }
+  }
+  return K_BAD << 4;
+}
+
+// ---------------------------------------------------------------------------
+// Per-wave LDS
+// ---------------------------------------------------------------------------
+
+struct TablesLDS {
+  uint32_t lit[1 << LIT_BITS];
+  uint32_t dist[1 << DIST_BITS];  // also holds the code-length code table while lengths are read
+  uint16_t lsorted[288];
+  uint16_t dsorted[32];
+  TreeInfo li;
+  TreeInfo di;
+  uint8_t lens[320];
+};
+
+// reasons (only their class matters: a candidate is rejected, or data is invalid)
+enum : int { D_OK = 0, D_BAD = 1, D_TRUNC = 2, D_ASCII = 3, D_SIZE = 4, D_FAR = 5, D_STATIC = 6 };
+
+// Dynamic-block code tables (section 3.2.7).  strict: the literal/length code
+// must be complete (block-start checks); otherwise one lone 1-bit code is also
+// accepted.  fill = false only validates.
+__device__ int read_dynamic_tables(WaveBits &br, TablesLDS &sh, bool strict, bool fill, bool *no_dist) {
+  const int lane = lane_id();
+  uint64_t v = br.peek();
+  const uint32_t hlit = (uint32_t)(v & 31u) + 257u;
+  const uint32_t hdist = (uint32_t)((v >> 5) & 31u) + 1u;
+  const uint32_t hclen = (uint32_t)((v >> 10) & 15u) + 4u;
+  br.skip(14);
+  if (hlit > 286u || hdist > 30u) return D_BAD;
+  v = br.peek();
+  // code-length code lengths, sent in the order 16 17 18 0 8 7 9 6 10 5 11 4 12 3 13 2 14 1 15
+  if (lane < 19) sh.lens[lane] = 0;
+  wave_sync();
+  if (lane < (int)hclen) {
+    // position of lane's entry in that order, as 5-bit fields
+    const uint64_t ord_lo = (16ull) | (17ull << 5) | (18ull << 10) | (0ull << 15) | (8ull << 20) | (7ull << 25) |
+                            (9ull << 30) | (6ull << 35) | (10ull << 40) | (5ull << 45) | (11ull << 50) |
+                            (4ull << 55);
+    const uint64_t ord_hi = (12ull) | (3ull << 5) | (13ull << 10) | (2ull << 15) | (14ull << 20) | (1ull << 25) |
+                            (15ull << 30);
+    uint32_t sym = lane < 12 ? (uint32_t)((ord_lo >> (5 * lane)) & 31u) : (uint32_t)((ord_hi >> (5 * (lane - 12))) & 31u);
+    sh.lens[sym] = (uint8_t)((v >> (3 * lane)) & 7u);
+  }
+  br.skip(3 * hclen);
+  wave_sync();
+  int ncl;
+  int left = build_tree<CL_BITS, TREE_CL>(sh.lens, 19, sh.dist, &sh.di, sh.dsorted, &ncl, true);
+  if (left != 0) return D_BAD;  // code-length code over-subscribed or incomplete
+  const uint32_t total = hlit + hdist;
+  uint32_t i = 0, prev = 0;
+  int lit_left = 32768, dist_left = 32768;
+  // every pass stores at least one length, so total passes at most
+  for (uint32_t pass = 0; i < total; pass++) {
+    if (pass >= total) return D_BAD;
+    v = br.peek();
+    const uint32_t e = uni32(sh.dist[v & 127u]);
+    uint32_t cl = e & 15u, sym = e >> 8;
+    if (sym < 16u) {
+      if (lane == 0) sh.lens[i] = (uint8_t)sym;
+      if (sym) {
+        if (i < hlit) lit_left -= 1 << (15 - sym);
+        else dist_left -= 1 << (15 - sym);
+      }
+      prev = sym;
+      i++;
+      br.skip(cl);
+    } else {
+      uint32_t rep, val;
+      if (sym == 16u) {
+        if (i == 0) return D_BAD;
+        rep = 3u + (uint32_t)((v >> cl) & 3u);
+        val = prev;
+        br.skip(cl + 2);
+      } else if (sym == 17u) {
+        rep = 3u + (uint32_t)((v >> cl) & 7u);
+        val = 0;
+        br.skip(cl + 3);
+      } else {
+        rep = 11u + (uint32_t)((v >> cl) & 127u);
+        val = 0;
+        br.skip(cl + 7);
+      }
+      if (i + rep > total) return D_BAD;
+      for (uint32_t k = (uint32_t)lane; k < rep; k += 64) sh.lens[i + k] = (uint8_t)val;
+      if (val) {
+        uint32_t nl = i < hlit ? min(i + rep, hlit) - i : 0u;
+        lit_left -= (int)nl << (15 - val);
+        dist_left -= (int)(rep - nl) << (15 - val);
+      }
+      prev = val;
+      i += rep;
+    }
+    if (br.past_end()) return D_TRUNC;
+    if (lit_left < 0 || dist_left < 0) return D_BAD;
+  }
+  wave_sync();
+  if (uni32(sh.lens[256]) == 0) return D_BAD;  // no end-of-block code
+  int nlit, ndist;
+  left = build_tree<LIT_BITS, TREE_LIT>(sh.lens, (int)hlit, sh.lit, &sh.li, sh.lsorted, &nlit, fill);
+  if (left < 0) return D_BAD;
+  if (left > 0) {
+    bool lone = nlit == 1 && uni32(sh.lens[256]) == 1;  // only end-of-block, one bit
+    if (strict || !lone) return D_BAD;
+  }
+  left = build_tree<DIST_BITS, TREE_DIST>(sh.lens + hlit, (int)hdist, sh.dist, &sh.di, sh.dsorted, &ndist, fill);
+  if (left < 0) return D_BAD;
+  *no_dist = ndist == 0;
+  if (left > 0 && ndist != 0) {
+    bool lone = false;
+    if (ndist == 1) {
+      // the one code must be 1 bit long
+      int one = 0;
+      for (uint32_t k = (uint32_t)lane; k < hdist; k += 64) one |= sh.lens[hlit + k] == 1;
+      lone = __ballot(one) != 0;
+    }
+    if (!lone) return D_BAD;
+  }
+  return D_OK;
+}
+
+__device__ void fixed_tables(TablesLDS &sh) {
+  const int lane = lane_id();
+  for (int s = lane; s < 288; s += 64) sh.lens[s] = (uint8_t)(s < 144 ? 8 : s < 256 ? 9 : s < 280 ? 7 : 8);
+  wave_sync();
+  int n;
+  build_tree<LIT_BITS, TREE_LIT>(sh.lens, 288, sh.lit, &sh.li, sh.lsorted, &n, true);
+  if (lane < 32) sh.lens[lane] = 5;
+  wave_sync();
+  build_tree<DIST_BITS, TREE_DIST>(sh.lens, 32, sh.dist, &sh.di, sh.dsorted, &n, true);
+}
+
+// ---------------------------------------------------------------------------
+// Block-start checks of Appendix A, cheap stage: one lane per candidate bit.
+// BFINAL = 0, BTYPE = 10, HLIT <= 286, HDIST <= 30, complete code-length code.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ bool start_stage1(const Src &s, uint64_t b) {
+  if (b + 17 > s.end_bits) return false;
+  uint64_t v = s.peek64(b);
+  if ((v & 7u) != 4u) return false;
+  if (((v >> 3) & 31u) > 29u || ((v >> 8) & 31u) > 29u) return false;
+  uint32_t hclen = (uint32_t)((v >> 13) & 15u) + 4u;
+  uint64_t w = s.peek64(b + 17);
+  int left = 128;
+  for (uint32_t i = 0; i < hclen; i++) {
+    uint32_t L = (uint32_t)(w >> (3 * i)) & 7u;
+    if (L) left -= 128 >> L;
+  }
+  return left == 0;
+}
+
+// Full static check, whole wave: the dynamic tables at b + 3 are valid.
+__device__ __forceinline__ bool start_stage2(const Src &s, uint64_t b, TablesLDS &sh) {
+  WaveBits br;
+  br.s = s;
+  br.init(b + 3);
+  bool nd;
+  return read_dynamic_tables(br, sh, true, false, &nd) == D_OK;
+}
+
+// First candidate in [from, to) that passes the static checks, whole wave.
+__device__ uint64_t wave_find_start(const Src &s, uint64_t from, uint64_t to, TablesLDS &sh) {
+  const int lane = lane_id();
+  for (uint64_t b0 = from; b0 < to; b0 += 64) {
+    uint64_t b = b0 + (uint64_t)lane;
+    bool p = b < to && start_stage1(s, b);
+    uint64_t m = __ballot(p);
+    while (m) {
+      int l = __ffsll((unsigned long long)m) - 1;
+      m &= m - 1;
+      if (start_stage2(s, b0 + (uint64_t)l, sh)) return b0 + (uint64_t)l;
+    }
+  }
+  return NONE;
+}
+
+}  // namespace gzgpu

@@ -1,0 +1,116 @@
+// Internal layout shared by the host planner and the device passes.
+#pragma once
+#include <stdint.h>
+
+namespace gzgpu {
+
+constexpr uint64_t NONE = ~0ull;
+constexpr uint32_t WINDOW = 32768;       // DEFLATE history (RFC 1951 section 2; paper Section III)
+constexpr uint32_t FLUSH_UNIT = 512;     // symbols moved from LDS to HBM at a time
+constexpr uint32_t TRANSLATE_TILE = 8192;
+constexpr uint32_t SYM_SLACK = 2048;     // symbols added to every chunk's capacity
+
+// chunk flags
+enum : uint32_t {
+  CF_FIRST = 1u,        // first chunk of its file: starts at the payload, empty context
+};
+
+// chunk state flags
+enum : uint32_t {
+  CS_FINAL = 1u,        // decoding reached the final block
+  CS_EMPTY = 2u,        // no start in range (or dropped)
+  CS_EXTENDED = 4u,     // continued past the first stop
+  CS_REPAIRED = 8u,     // start replaced by the previous chunk's end
+  CS_OVERFLOW = 16u,    // symbol capacity exceeded before the stop
+};
+
+// device status codes (same numbers as the public GZ_E_*)
+enum : int32_t {
+  ST_OK = 0,
+  ST_UNSUPPORTED = -3,
+  ST_DATA = -4,
+  ST_CAPACITY = -5,
+  ST_SIZE = -7,
+};
+
+struct FileDesc {
+  const uint8_t *comp;     // device address of the .gz bytes
+  uint64_t comp_len;
+  uint64_t payload_bit;    // 8 * payload start byte
+  uint64_t trailer_byte;   // comp_len - 8
+  uint8_t *out;
+  uint64_t out_cap;
+  uint32_t first_chunk;
+  uint32_t n_chunks;
+  uint32_t isize;
+  uint32_t crc;
+  uint64_t pool_base;      // this file's part of the symbol pool (elements)
+  uint64_t pool_elems;
+};
+
+struct ChunkDesc {
+  uint64_t lo_bit;         // candidate range [lo_bit, hi_bit), bits from the file start
+  uint64_t hi_bit;
+  uint64_t sym_off;        // element offset of the chunk's symbols in the pool (set on the device)
+  uint64_t sym_cap;        // capacity in symbols, multiple of FLUSH_UNIT (set on the device)
+  uint32_t file;
+  uint32_t index;          // chunk index within its file
+  uint32_t flags;
+  uint32_t pad;
+};
+
+struct ChunkState {
+  uint64_t cand;           // smallest start passing the static checks (scan), NONE if none
+  uint64_t start;          // accepted start bit, NONE if the chunk is empty
+  uint64_t end;            // bit where decoding stopped (a block start, or the end of the final block)
+  uint64_t len;            // symbols produced up to the stop
+  uint64_t out_off;        // output offset
+  uint64_t needed;         // symbols produced when the capacity overflowed
+  uint64_t n_syms;
+  uint64_t n_placeholders;
+  int32_t status;
+  uint32_t flags;
+  uint32_t n_blocks;
+  uint32_t retries;
+  uint32_t valid;          // real history bytes before the chunk, capped at 32768
+  uint32_t pad;
+};
+
+struct FileState {
+  uint64_t out_len;
+  uint64_t out_needed;
+  uint64_t n_syms;
+  uint64_t n_placeholders;
+  uint64_t n_blocks;
+  int32_t status;
+  uint32_t n_repairs;
+  uint32_t n_extended;
+  uint32_t n_nonempty;
+  uint32_t n_retries;
+  uint32_t overflow;
+};
+
+struct Counters {
+  uint32_t inflate_next;   // persistent work queue head
+  uint32_t stitch_next;
+  uint32_t translate_next;
+  uint32_t pad[13];
+};
+
+// Workspace: offsets from the workspace base (all 256-byte aligned).
+struct Layout {
+  uint64_t files_off;      // FileDesc[F]
+  uint64_t chunks_off;     // ChunkDesc[N]
+  uint64_t order_off;      // uint32[N]: inflate work order
+  uint64_t table_bytes;    // bytes uploaded from the host (files + chunks + order)
+  uint64_t cstate_off;     // ChunkState[N]
+  uint64_t fstate_off;     // FileState[F]
+  uint64_t counters_off;   // Counters
+  uint64_t tiles_off;      // uint64[N+1] translate tile prefix
+  uint64_t win_off;        // uint8[N][32768] resolved windows
+  uint64_t sym_off;        // uint16 symbol pool
+  uint64_t sym_elems;
+  uint64_t total;
+};
+
+}  // namespace gzgpu

@@ -1,0 +1,92 @@
+"""Drive the device path's C ABI on the CPU through the test-side executor (tests/emu)."""
+import ctypes as C
+import os
+import sys
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.join(HERE, "emu"))
+ROOT = os.path.dirname(HERE)
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+class Opts(C.Structure):
+    _fields_ = [("chunk_bytes", C.c_uint64), ("sym_factor", C.c_uint32), ("window_syms", C.c_uint32),
+                ("scan_groups", C.c_uint32), ("inflate_waves_per_cu", C.c_uint32), ("reserved", C.c_uint32 * 8)]
+
+
+class Info(C.Structure):
+    _fields_ = [("ws_bytes", C.c_uint64), ("payload_start", C.c_uint64), ("payload_end", C.c_uint64),
+                ("n_files", C.c_uint32), ("n_chunks", C.c_uint32), ("crc32", C.c_uint32), ("isize", C.c_uint32)]
+
+
+class Result(C.Structure):
+    _fields_ = [("status", C.c_int32), ("n_chunks", C.c_uint32), ("out_len", C.c_uint64),
+                ("out_needed", C.c_uint64), ("ws_needed", C.c_uint64), ("n_nonempty", C.c_uint32),
+                ("n_repairs", C.c_uint32), ("n_extended", C.c_uint32), ("n_retries", C.c_uint32),
+                ("n_syms", C.c_uint64), ("n_placeholders", C.c_uint64), ("n_blocks", C.c_uint64)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = os.environ.get("GZEMU_LIB")
+        if not path:
+            import build as ebuild  # tests/emu/build.py
+
+            path = ebuild.build()
+        _lib = C.CDLL(path)
+        vp = C.c_void_p
+        _lib.gz_plan.argtypes = [C.POINTER(vp), vp, C.c_size_t, C.c_int, C.POINTER(Opts)]
+        _lib.gz_plan_info.argtypes = [vp, C.POINTER(Info)]
+        _lib.gz_decompress.argtypes = [vp, vp, C.c_size_t, vp, C.c_size_t, vp]
+        _lib.gz_result_get.argtypes = [vp, C.c_int, C.POINTER(Result)]
+        _lib.gz_chunk_table.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp, vp, vp]
+        _lib.gz_plan_destroy.argtypes = [vp]
+        _lib.gz_plan_destroy.restype = None
+        _lib.emu_set_sync_limit.argtypes = [C.c_uint64]
+    return _lib
+
+
+def run(comp: bytes, n_chunks: int, out_cap=None, sync_limit=0, **opts):
+    L = lib()
+    L.emu_set_sync_limit(sync_limit)
+    # the device path reads whole aligned dwords that hold input bytes; pad the
+    # host copy so that those reads stay inside the allocation
+    store = np.zeros(len(comp) + (-len(comp)) % 8, dtype=np.uint8)
+    store[: len(comp)] = np.frombuffer(bytes(comp), dtype=np.uint8)
+    buf = store[: len(comp)]
+    o = Opts()
+    for k, v in opts.items():
+        setattr(o, k, v)
+    h = C.c_void_p()
+    st = L.gz_plan(C.byref(h), C.c_void_p(buf.ctypes.data), buf.size, n_chunks, C.byref(o))
+    if st != 0:
+        return st, None, None, None
+    info = Info()
+    L.gz_plan_info(h, C.byref(info))
+    raw_ws = np.zeros(info.ws_bytes + 512, dtype=np.uint8)
+    off = (-raw_ws.ctypes.data) % 256
+    ws = raw_ws[off:off + info.ws_bytes]
+    if out_cap is None:
+        out_cap = max(1, int(info.isize))
+    out = np.zeros(out_cap, dtype=np.uint8)
+    st = L.gz_decompress(h, C.c_void_p(out.ctypes.data), out_cap, C.c_void_p(ws.ctypes.data), ws.size, None)
+    assert st == 0, st
+    r = Result()
+    L.gz_result_get(h, 0, C.byref(r))
+    n = info.n_chunks
+    tab = {k: np.zeros(n, dtype=np.uint64) for k in ("start", "cand", "end", "len", "out_off")}
+    sts = np.zeros(n, dtype=np.int32)
+    fl = np.zeros(n, dtype=np.uint32)
+    p = lambda a: C.c_void_p(a.ctypes.data)  # noqa: E731
+    L.gz_chunk_table(h, 0, p(tab["start"]), p(tab["cand"]), p(tab["end"]), p(tab["len"]), p(tab["out_off"]),
+                     p(sts), p(fl))
+    tab["status"], tab["flags"] = sts, fl
+    L.gz_plan_destroy(h)
+    return r.status, out[: r.out_len].tobytes(), r, tab

@@ -1,0 +1,237 @@
+"""Device path against the CPU oracle, through the C ABI (needs an MI355X).
+
+Bytes, chunk starts, chunk ends, symbol counts, the 16-bit symbolic output of
+pass 1, the resolved windows and the statuses are compared with the oracle on
+the same seeded inputs.  All of it is integer work, so the bar is equality.
+"""
+import numpy as np
+import pytest
+
+import synth
+from bitwriter import gzip_wrap
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _gz():
+    import paper_1905_07224_amd as gz
+    return gz
+
+
+def _dev(b):
+    return torch.frombuffer(bytearray(b), dtype=torch.uint8).to("cuda:0")
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+def _run(comp, n_chunks, **opts):
+    gz = _gz()
+    plan = gz.Plan(_dev(comp), n_chunks, **opts)
+    out = plan.run()
+    torch.cuda.synchronize()
+    return out.cpu().numpy().tobytes(), plan
+
+
+def _starts(tab):
+    gz = _gz()
+    return np.array([-1 if int(s) == gz.NONE else int(s) for s in tab["start"]], dtype=np.int64)
+
+
+def _check_against_oracle(orc, comp, n_chunks, raw=None, **opts):
+    got, plan = _run(comp, n_chunks, **opts)
+    ref = orc.pugz(comp, n_chunks)
+    assert ref.status == orc.OK, ref.reason
+    assert got == ref.out.tobytes()
+    if raw is not None:
+        assert got == raw
+    tab = plan.chunk_table()
+    assert np.array_equal(_starts(tab), ref.start), (list(_starts(tab)), list(ref.start))
+    ne = ref.start >= 0
+    assert np.array_equal(tab["end"][ne].astype(np.int64), ref.end[ne])
+    assert np.array_equal(tab["len"][ne].astype(np.int64), ref.len[ne])
+    assert np.array_equal(tab["out_off"][ne].astype(np.int64), ref.off[ne])
+    r = plan.result()
+    assert r.out_len == len(got)
+    assert r.n_placeholders == int(ref.placeholders.sum())
+    return plan, ref
+
+
+@pytest.fixture(scope="module")
+def c1():
+    raw = synth.fastq_like(4 << 20, 1)
+    return raw, synth.gzip_member(raw, 6)
+
+
+def test_c1_fastq_8_chunks(orc, c1):
+    raw, comp = c1
+    _say("fastq 4 MiB L6, 8 chunks")
+    _check_against_oracle(orc, comp, 8, raw)
+
+
+def test_c1_pass1_symbols_and_windows(orc, c1):
+    """Pass 1 symbols of every chunk equal decompress(C_i, w_hat_i) at the same start,
+    and pass 2 windows equal the true preceding 32 KiB."""
+    raw, comp = c1
+    _say("fastq 4 MiB L6, per-chunk symbols and windows")
+    plan, ref = _check_against_oracle(orc, comp, 8, raw)
+    N = ref.n_chunks
+    nz = [i for i in range(N) if ref.start[i] >= 0]
+    for k, i in enumerate(nz):
+        stop = ref.start[nz[k + 1]] if k + 1 < len(nz) else (1 << 62)
+        sr = orc.symbolic(comp, int(ref.start[i]), int(stop), first=(i == 0))
+        assert sr.status == orc.OK
+        L = int(ref.len[i])
+        dev = plan.symbols(i, L).cpu().numpy().view(np.uint16)
+        assert np.array_equal(dev, sr.sym[:L]), f"chunk {i}"
+        if k > 0:
+            w = plan.window(i).cpu().numpy()
+            v = int(ref.valid[i])
+            assert np.array_equal(w[32768 - v:], ref.windows[i][32768 - v:]), f"window {i}"
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 64, 500])
+def test_chunk_count_invariance(orc, c1, n):
+    raw, comp = c1
+    _say("fastq 4 MiB L6 chunks", n)
+    got, plan = _run(comp, n)
+    assert got == raw
+    if n <= 64:
+        ref = orc.pugz(comp, n)
+        assert np.array_equal(_starts(plan.chunk_table()), ref.start)
+
+
+@pytest.mark.parametrize("kind,level", [("words", 6), ("fastq", 1), ("fastq", 9), ("words", 1), ("dna", 6)])
+def test_other_inputs(orc, kind, level):
+    gen = {"words": lambda: synth.word_stream(3 << 20, 61), "fastq": lambda: synth.fastq_like(3 << 20, 62),
+           "dna": lambda: synth.random_dna(2 << 20, 63)}[kind]
+    raw = gen()
+    comp = synth.gzip_member(raw, level)
+    _say(kind, "level", level)
+    _check_against_oracle(orc, comp, 6, raw)
+
+
+@pytest.mark.parametrize("level", [0, 1, 6])
+def test_small_and_special(orc, level):
+    for name, raw in [("empty", b""), ("one", b"x"), ("tiny", b"hello gzip\n" * 3),
+                      ("20k", synth.fastq_like(20000, 5)),
+                      ("binary", np.random.default_rng(3).integers(0, 256, 300000, dtype=np.uint8).tobytes())]:
+        comp = synth.gzip_member(raw, level)
+        for n in (1, 3):
+            _say("special", name, "level", level, "chunks", n)
+            got, plan = _run(comp, n)
+            assert got == raw, (name, n)
+
+
+def test_segmented_member(orc):
+    raw = synth.fastq_like(3 << 20, 71)
+    comp = synth.gzip_member(raw, 6, segment_bytes=512 << 10)
+    _say("segmented member")
+    _check_against_oracle(orc, comp, 12, raw)
+
+
+def test_handbuilt_streams(orc):
+    from test_oracle import HAND, wrap_tokens
+
+    for name, blocks in HAND.items():
+        deflate, data = wrap_tokens(blocks)
+        _say("handbuilt", name)
+        got, _ = _run(gzip_wrap(deflate, data), 1)
+        assert got == data, name
+
+
+def test_negative_statuses(orc):
+    gz = _gz()
+    raw = synth.fastq_like(600 << 10, 81)
+    comp = bytearray(synth.gzip_member(raw, 6))
+    cases = {}
+    bad = bytearray(comp)
+    bad[-8] ^= 1
+    cases["crc_not_checked_but_size_ok"] = (bytes(bad), None)
+    bad = bytearray(comp)
+    bad[-4] ^= 1
+    cases["isize"] = (bytes(bad), gz.GZ_E_SIZE)
+    cases["truncated"] = (bytes(comp[: len(comp) // 2]) + bytes(comp[-8:]), "error")
+    cases["trailing_member"] = (bytes(comp) + synth.gzip_member(b"abc", 6), gz.GZ_E_UNSUPPORTED)
+    for name, (data, want) in cases.items():
+        _say("negative", name)
+        plan = gz.Plan(_dev(data), 4)
+        out = torch.empty(len(raw) + 1000, dtype=torch.uint8, device="cuda:0")
+        plan.launch(out)
+        r = plan.result()
+        if want is None:
+            assert r.status == 0
+        elif want == "error":
+            assert r.status != 0
+        else:
+            assert r.status == want, (name, r.status)
+    with pytest.raises(gz.GzError):
+        gz.Plan(_dev(b"\x1f\x8c" + bytes(30)), 1)
+
+
+def test_corrupt_bits_match_oracle_status(orc):
+    """Flipped bits: the device reports an error exactly when the oracle does,
+    and otherwise produces the oracle's bytes."""
+    gz = _gz()
+    raw = synth.word_stream(300 << 10, 91)
+    comp = synth.gzip_member(raw, 6)
+    rng = np.random.default_rng(5)
+    for k in range(12):
+        b = bytearray(comp)
+        pos = int(rng.integers(20, len(b) - 20))
+        b[pos] ^= 1 << int(rng.integers(0, 8))
+        ref = orc.pugz(bytes(b), 3)
+        _say("flip", k, pos, "oracle", ref.reason)
+        plan = gz.Plan(_dev(bytes(b)), 3)
+        out = torch.empty(2 * len(raw) + 4096, dtype=torch.uint8, device="cuda:0")
+        plan.launch(out)
+        r = plan.result()
+        if ref.status == orc.OK:
+            assert r.status == 0
+            assert out[: r.out_len].cpu().numpy().tobytes() == ref.out.tobytes()
+        elif ref.reason == "CRC":
+            # the device does not compute the CRC: it decodes what the oracle
+            # decoded and checks only the length against ISIZE
+            want = 0 if (len(ref.out) & 0xFFFFFFFF) == ref.isize_trailer else gz.GZ_E_SIZE
+            assert r.status == want, (k, r.status)
+            if want == 0:
+                assert out[: r.out_len].cpu().numpy().tobytes() == ref.out.tobytes()
+        else:
+            assert r.status != 0, (k, ref.reason)
+
+
+def test_batch_equals_single(orc):
+    gz = _gz()
+    files = [synth.gzip_member(synth.fastq_like((1 + i) * (300 << 10), 200 + i), [1, 6, 9][i % 3]) for i in range(5)]
+    files.append(synth.gzip_member(synth.word_stream(700 << 10, 299), 6))
+    _say("batch of", len(files))
+    outs = gz.decompress_batch([_dev(f) for f in files], n_chunks=4)
+    for f, o in zip(files, outs):
+        ref = orc.gunzip(f)
+        assert o.cpu().numpy().tobytes() == ref.out.tobytes()
+
+
+def test_repeat_determinism(orc, c1):
+    raw, comp = c1
+    _say("repeat determinism")
+    gz = _gz()
+    plan = gz.Plan(_dev(comp), 8)
+    outs = []
+    stats = []
+    for _ in range(3):
+        o = plan.run()
+        torch.cuda.synchronize()
+        outs.append(o.cpu().numpy().tobytes())
+        stats.append(plan.result().as_dict())
+    assert outs[0] == outs[1] == outs[2] == raw
+    assert stats[0] == stats[1] == stats[2]
+
+
+@pytest.mark.parametrize("win", [8192, 32768])
+def test_window_sizes(orc, c1, win):
+    raw, comp = c1
+    _say("LDS window", win)
+    _check_against_oracle(orc, comp, 8, raw, window_syms=win)
