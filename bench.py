@@ -1,0 +1,187 @@
+#!/usr/bin/env python
+"""Decompressed GB/s of two-pass gzip decompression on one MI355X.
+
+One step = one whole two-pass decompression of the workload's gzip member,
+compressed input already in HBM, output left in HBM: block-start scan,
+symbolic inflate, stitch, size scan, window propagation, translation.  The
+default workload is 1 GiB of FASTQ-like text (100/150 bp reads) compressed as
+one gzip member at level 6 and cut into 1 MiB compressed chunks.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+import zlib
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(sample_mib: int):
+    """The CPU oracle (single-threaded, bit-serial RFC 1951 inflate) on a bounded
+    sample of the same generator, in decompressed GB/s."""
+    import oracle
+    import synth
+
+    raw, gz = synth.make("fastq", sample_mib << 20, 2, 6, read_lens=(100, 150))
+    oracle.lib()
+    t0 = time.perf_counter()
+    r = oracle.gunzip(gz)
+    dt = time.perf_counter() - t0
+    ok = r.status == 0 and len(r.out) == len(raw)
+    return {
+        "value": round(len(raw) / dt / 1e9, 6),
+        "unit": "GB/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"{len(raw)} bytes of FASTQ-like text (same generator, 100/150 bp), gzip -6, "
+                  f"sequential CPU oracle on one host core, {dt:.1f} s, ok={ok}",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="fastq_1GiB_L6")
+    ap.add_argument("--chunk-bytes", type=int, default=1 << 20)
+    ap.add_argument("--waves-per-chunk", type=int, default=1)
+    ap.add_argument("--window", type=int, default=16384)
+    ap.add_argument("--cpu-sample-mib", type=int, default=256)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU; multi-GPU sharding of the chunk chain is "
+              "described in DESIGN.md but not implemented", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1905_07224_amd as gz
+    import synth
+
+    t = time.perf_counter()
+    log(f"workload {args.workload}: generating / loading")
+    raw, comp = synth.workload(args.workload)
+    log(f"input ready: {len(raw)} bytes raw, {len(comp)} compressed (ratio {len(raw) / len(comp):.3f}) "
+        f"in {time.perf_counter() - t:.1f} s")
+    crc_ref = zlib.crc32(raw) & 0xFFFFFFFF
+
+    dev = torch.device("cuda:0")
+    d_comp = torch.frombuffer(bytearray(comp), dtype=torch.uint8).to(dev)
+    out = torch.empty(len(raw), dtype=torch.uint8, device=dev)
+    plan = gz.Plan(d_comp, 0, chunk_bytes=args.chunk_bytes, waves_per_chunk=args.waves_per_chunk,
+                   window_syms=args.window, timing=1)
+    log(f"plan: {plan.n_chunks} chunks, workspace {plan.info.ws_bytes / 2**30:.2f} GiB")
+    stream = torch.cuda.current_stream()
+
+    # warmup, with a byte-exact check of the output against the source text
+    for w in range(max(1, args.warmup)):
+        plan.launch(out, stream)
+        r = plan.result()
+        if r.status != 0:
+            raise SystemExit(f"decompression failed: status {r.status}")
+        if w == 0:
+            ref = torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(dev)
+            exact = bool(torch.equal(out[: r.out_len], ref)) and r.out_len == len(raw)
+            del ref
+            log(f"warmup: status {r.status}, byte-exact {exact}, passes {plan.pass_times()}")
+            if not exact:
+                raise SystemExit("output differs from the source text")
+
+    # timed steps
+    passes = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.launch(out, stream)
+        r = plan.result()  # waits for the stream
+        if r.status != 0:
+            raise SystemExit(f"decompression failed: status {r.status}")
+        passes.append(plan.pass_times())
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    stats = plan.result().as_dict()
+    ms_step = dt / args.steps * 1e3
+    value = len(raw) * args.steps / dt / 1e9
+    log(f"timed: {args.steps} steps, {ms_step:.2f} ms/step, {value:.2f} GB/s decompressed")
+
+    # output check after the timed steps: length and CRC-32 against the trailer
+    crc_out = zlib.crc32(out.cpu().numpy().tobytes()) & 0xFFFFFFFF
+    if crc_out != crc_ref:
+        raise SystemExit("CRC-32 of the output differs after the timed steps")
+
+    avg = {k: sum(p[k] for p in passes) / len(passes) for k in passes[0]}
+    inflate_ms = avg["inflate"]
+    # algorithmic bytes of one inflate launch: read the compressed payload once,
+    # write one 16-bit symbol per decompressed byte
+    inflate_bytes = len(comp) + 2 * len(raw)
+    achieved = inflate_bytes / (inflate_ms / 1e3) / 1e9
+    roofline = {
+        "kernel": "k_inflate",
+        "bound": "hbm",
+        "achieved": round(achieved, 3),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 6),
+        "traffic": None,
+        "algorithmic_bytes": inflate_bytes,
+        "avg_ms": round(inflate_ms, 4),
+    }
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log(f"cpu baseline: oracle on a {args.cpu_sample_mib} MiB sample")
+        cpu = cpu_baseline(args.cpu_sample_mib)
+        log(f"cpu baseline: {cpu['value']} GB/s")
+
+    line = {
+        "metric": "decompressed GB/s on 1 MI355X (batched vs plain) + p50/p99 job latency; bit-exact",
+        "value": round(value, 4),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic",
+        "config": {
+            "workload": args.workload,
+            "path": "plain",
+            "uncompressed_bytes": len(raw),
+            "compressed_bytes": len(comp),
+            "ratio": round(len(raw) / len(comp), 4),
+            "chunk_bytes": args.chunk_bytes,
+            "waves_per_chunk": args.waves_per_chunk,
+            "n_chunks": plan.n_chunks,
+            "window_syms": args.window,
+            "compressed_MBps": round(len(comp) * args.steps / dt / 1e6, 1),
+        },
+        "passes_ms": {k: round(v, 4) for k, v in avg.items()},
+        "stats": {k: stats[k] for k in ("n_nonempty", "n_repairs", "n_extended", "n_retries", "n_syms",
+                                         "n_placeholders", "n_blocks")},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "bit_exact": True,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

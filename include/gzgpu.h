@@ -51,10 +51,12 @@ extern "C" {
 typedef struct gz_opts {
   uint64_t chunk_bytes;   /* nominal compressed bytes per chunk when n_chunks == 0 (default 1 MiB) */
   uint32_t sym_factor;    /* symbol capacity per chunk = sym_factor * compressed bytes + slack (default 8) */
-  uint32_t window_syms;   /* per-wave LDS history in symbols: 8192, 16384 (default) or 32768 */
+  uint32_t window_syms;   /* reserved: the per-wave LDS history always holds the 32768-symbol window */
   uint32_t scan_groups;   /* workgroups that search one chunk's start in parallel (default 8) */
   uint32_t inflate_waves_per_cu; /* persistent inflate grid = this * CU count (default: occupancy) */
-  uint32_t reserved[8];
+  uint32_t waves_per_chunk; /* each nominal chunk is split into this many sub-chunks, one wave each (default 1) */
+  uint32_t timing;        /* nonzero: record a HIP event at every pass boundary (see gz_pass_times) */
+  uint32_t reserved[6];
 } gz_opts;
 
 /* One file of a batch. */
@@ -139,6 +141,15 @@ int gz_chunk_table(gz_plan_t plan, int file, uint64_t *start, uint64_t *cand, ui
  * sym_base + 2*sym_off[c]; its resolved window at win_base + 32768*c. */
 int gz_debug_layout(gz_plan_t plan, int file, uint64_t *sym_off, uint64_t *win_index, void **sym_base,
                     void **win_base);
+
+/* Passes timed when opts.timing is set, in launch order. */
+#define GZ_N_PASSES 10
+/* Names: upload, init, scan, capacity, inflate, stitch, finalize, tilescan,
+ * propagate, translate.  Waits for the last launch and writes the duration of
+ * each pass in milliseconds (HIP events on the launch stream) into ms[0..n).
+ * Returns the number written, or GZ_E_NOT_READY without timing. */
+int gz_pass_times(gz_plan_t plan, float *ms, int n);
+const char *gz_pass_name(int i);
 
 void gz_plan_destroy(gz_plan_t plan);
 const char *gz_strerror(int code);

@@ -36,7 +36,8 @@ class GzError(RuntimeError):
 
 class Opts(C.Structure):
     _fields_ = [("chunk_bytes", C.c_uint64), ("sym_factor", C.c_uint32), ("window_syms", C.c_uint32),
-                ("scan_groups", C.c_uint32), ("inflate_waves_per_cu", C.c_uint32), ("reserved", C.c_uint32 * 8)]
+                ("scan_groups", C.c_uint32), ("inflate_waves_per_cu", C.c_uint32), ("waves_per_chunk", C.c_uint32),
+                ("timing", C.c_uint32), ("reserved", C.c_uint32 * 6)]
 
 
 class Job(C.Structure):
@@ -62,7 +63,9 @@ class Result(C.Structure):
 _lib = None
 
 EXPORTS = ["gz_plan", "gz_plan_batch", "gz_plan_info", "gz_decompress", "gz_decompress_batch", "gz_result_get",
-           "gz_chunk_table", "gz_debug_layout", "gz_plan_destroy", "gz_strerror", "gz_device_info"]
+           "gz_chunk_table", "gz_debug_layout", "gz_plan_destroy", "gz_strerror", "gz_device_info", "gz_pass_times",
+           "gz_pass_name"]
+GZ_N_PASSES = N_PASSES = 10
 
 
 def lib():
@@ -87,8 +90,11 @@ def lib():
         L.gz_strerror.argtypes = [i32]
         L.gz_strerror.restype = C.c_char_p
         L.gz_device_info.argtypes = [i32, C.POINTER(i32), C.POINTER(i32)]
+        L.gz_pass_times.argtypes = [vp, C.POINTER(C.c_float), i32]
+        L.gz_pass_name.argtypes = [i32]
+        L.gz_pass_name.restype = C.c_char_p
         for name in EXPORTS:
-            if name not in ("gz_plan_destroy", "gz_strerror"):
+            if name not in ("gz_plan_destroy", "gz_strerror", "gz_pass_name"):
                 getattr(L, name).restype = i32
         _lib = L
     return _lib
@@ -178,6 +184,10 @@ class Plan:
         _check(lib().gz_result_get(self._h, file, C.byref(r)))
         return r
 
+    def pass_times(self):
+        """{pass name: ms} of the last launch (needs timing=1 in the options)."""
+        return _pass_times(self._h)
+
     def chunk_table(self, file: int = 0):
         import numpy as np
 
@@ -248,6 +258,14 @@ class Plan:
         raise GzError(GZ_E_CAPACITY, "capacity retries exhausted")
 
 
+def _pass_times(h):
+    buf = (C.c_float * N_PASSES)()
+    n = lib().gz_pass_times(h, buf, N_PASSES)
+    if n < 0:
+        _check(n)
+    return {lib().gz_pass_name(i).decode(): float(buf[i]) for i in range(n)}
+
+
 def decompress(comp, n_chunks: int = 0, out=None, stream=None, **opts) -> torch.Tensor:
     """Decompress one gzip member held in a uint8 tensor (or bytes) on the GPU."""
     return Plan(comp, n_chunks, **opts).run(out, stream)
@@ -306,6 +324,9 @@ class BatchPlan:
         r = Result()
         _check(lib().gz_result_get(self._h, file, C.byref(r)))
         return r
+
+    def pass_times(self):
+        return _pass_times(self._h)
 
 
 def _isize_of(t: torch.Tensor) -> int:

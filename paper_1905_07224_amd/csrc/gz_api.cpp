@@ -92,7 +92,7 @@ int hip_fail(hipError_t e, const char *what) {
 
 struct gz_plan_s {
   gz_opts opts{};
-  uint32_t win = 16384;
+  uint32_t win = 32768;
   uint32_t groups = 8;
   int n_cu = 256;
   int device = 0;
@@ -105,6 +105,8 @@ struct gz_plan_s {
   uint8_t *pinned = nullptr;
   hipEvent_t upload_done = nullptr;
   bool upload_pending = false;
+  hipEvent_t pass_ev[GZ_N_PASSES + 1] = {};
+  bool timed = false;
   // last launch
   uint8_t *ws = nullptr;
   hipStream_t stream = nullptr;
@@ -157,6 +159,7 @@ static int plan_common(gz_plan_t p) {
     fd.isize = (uint32_t)tr[4] | ((uint32_t)tr[5] << 8) | ((uint32_t)tr[6] << 16) | ((uint32_t)tr[7] << 24);
     const uint64_t P = fd.trailer_byte - (uint64_t)h;  // payload bytes
     uint64_t N = j.n_chunks > 0 ? (uint64_t)j.n_chunks : (P + p->opts.chunk_bytes - 1) / p->opts.chunk_bytes;
+    N *= std::max<uint32_t>(1, p->opts.waves_per_chunk);
     N = std::max<uint64_t>(1, std::min<uint64_t>(N, P));
     fd.first_chunk = (uint32_t)p->chunks.size();
     fd.n_chunks = (uint32_t)N;
@@ -226,7 +229,7 @@ static void fill_defaults(gz_plan_t p, const gz_opts *opts) {
   if (opts) p->opts = *opts;
   if (p->opts.chunk_bytes == 0) p->opts.chunk_bytes = 1 << 20;
   if (p->opts.sym_factor == 0) p->opts.sym_factor = 8;
-  p->win = p->opts.window_syms == 8192 || p->opts.window_syms == 32768 ? p->opts.window_syms : 16384;
+  p->win = 32768;  // the LDS history always holds the whole DEFLATE window
   p->groups = p->opts.scan_groups ? p->opts.scan_groups : 8;
   (void)hipGetDevice(&p->device);
   hipDeviceProp_t prop;
@@ -246,6 +249,8 @@ static int make_plan(gz_plan_t *plan, const gz_job *jobs, int n, const gz_opts *
     return r;
   }
   (void)hipEventCreateWithFlags(&p->upload_done, hipEventDisableTiming);
+  if (p->opts.timing)
+    for (int i = 0; i <= GZ_N_PASSES; i++) (void)hipEventCreate(&p->pass_ev[i]);
   *plan = p;
   return GZ_OK;
 }
@@ -294,6 +299,11 @@ static int launch(gz_plan_t p, uint8_t *ws, size_t ws_bytes, hipStream_t st) {
   memcpy(p->pinned + L.chunks_off, p->chunks.data(), (size_t)N * sizeof(ChunkDesc));
   memcpy(p->pinned + L.order_off, p->order.data(), (size_t)N * 4);
   if (!p->scan_list.empty()) memcpy(p->pinned + p->scan_off, p->scan_list.data(), p->scan_list.size() * 4);
+  int ev = 0;
+  auto mark = [&]() {
+    if (p->opts.timing && ev <= GZ_N_PASSES) (void)hipEventRecord(p->pass_ev[ev++], st);
+  };
+  mark();
   hipError_t e = hipMemcpyAsync(ws, p->pinned, L.table_bytes, hipMemcpyHostToDevice, st);
   if (e != hipSuccess) return hip_fail(e, "job table upload");
   (void)hipEventRecord(p->upload_done, st);
@@ -311,27 +321,38 @@ static int launch(gz_plan_t p, uint8_t *ws, size_t ws_bytes, hipStream_t st) {
   uint16_t *pool = (uint16_t *)(ws + L.sym_off);
 
   const uint32_t lds_per_cu = 160 * 1024;
-  const uint32_t per_wave = (uint32_t)(6272 + 2 * p->win + 512);
+  const uint32_t per_wave = (uint32_t)(6272 + 2 * p->win + 256);
   uint32_t waves_per_cu = p->opts.inflate_waves_per_cu ? p->opts.inflate_waves_per_cu
                                                        : std::max<uint32_t>(1, lds_per_cu / per_wave);
   uint32_t grid = std::min<uint32_t>(N, waves_per_cu * (uint32_t)p->n_cu);
   if (grid == 0) grid = 1;
 
+  mark();
   if ((e = gzk_init(cs, N, fs, F, ctr, st)) != hipSuccess) return hip_fail(e, "init");
+  mark();
   if ((e = gzk_scan(files, chunks, cs, scan, (uint32_t)p->scan_list.size(), p->groups, st)) != hipSuccess)
     return hip_fail(e, "scan");
+  mark();
   if ((e = gzk_capacity(F, files, (ChunkDesc *)(ws + L.chunks_off), cs, p->opts.sym_factor, st)) != hipSuccess)
     return hip_fail(e, "capacity");
+  mark();
   if ((e = gzk_inflate((int)p->win, grid, files, chunks, cs, order, N, ctr, pool, st)) != hipSuccess)
     return hip_fail(e, "inflate");
+  mark();
   if ((e = gzk_stitch((int)p->win, grid, files, chunks, cs, N, ctr, pool, st)) != hipSuccess)
     return hip_fail(e, "stitch");
+  mark();
   if ((e = gzk_finalize((int)p->win, F, files, chunks, cs, fs, pool, st)) != hipSuccess) return hip_fail(e, "finalize");
+  mark();
   if ((e = gzk_tilescan(chunks, cs, fs, N, tiles, st)) != hipSuccess) return hip_fail(e, "tilescan");
+  mark();
   if ((e = gzk_propagate(F, files, chunks, cs, fs, wins, pool, st)) != hipSuccess) return hip_fail(e, "propagate");
+  mark();
   if ((e = gzk_translate((uint32_t)p->n_cu * 8, files, chunks, cs, fs, tiles, N, wins, pool, ctr, st)) !=
       hipSuccess)
     return hip_fail(e, "translate");
+  mark();
+  p->timed = p->opts.timing != 0;
   p->ws = ws;
   p->stream = st;
   p->launched = true;
@@ -453,10 +474,33 @@ int gz_debug_layout(gz_plan_t p, int file, uint64_t *sym_off, uint64_t *win_inde
   return GZ_OK;
 }
 
+int gz_pass_times(gz_plan_t p, float *ms, int n) {
+  if (!p || !ms || n < 0) return GZ_E_ARG;
+  if (!p->launched || !p->timed) return GZ_E_NOT_READY;
+  int r = fetch(p);
+  if (r != GZ_OK) return r;
+  int k = 0;
+  for (; k < n && k < GZ_N_PASSES; k++) {
+    float t = 0.f;
+    hipError_t e = hipEventElapsedTime(&t, p->pass_ev[k], p->pass_ev[k + 1]);
+    if (e != hipSuccess) return hip_fail(e, "event timing");
+    ms[k] = t;
+  }
+  return k;
+}
+
+const char *gz_pass_name(int i) {
+  static const char *names[GZ_N_PASSES] = {"upload",   "init",     "scan",     "capacity",  "inflate",
+                                           "stitch",   "finalize", "tilescan", "propagate", "translate"};
+  return i >= 0 && i < GZ_N_PASSES ? names[i] : "";
+}
+
 void gz_plan_destroy(gz_plan_t p) {
   if (!p) return;
   if (p->upload_pending) (void)hipEventSynchronize(p->upload_done);
   if (p->upload_done) (void)hipEventDestroy(p->upload_done);
+  for (int i = 0; i <= GZ_N_PASSES; i++)
+    if (p->pass_ev[i]) (void)hipEventDestroy(p->pass_ev[i]);
   if (p->pinned) (void)hipHostFree(p->pinned);
   delete p;
 }

@@ -51,23 +51,33 @@ __device__ __forceinline__ bool ascii_text(uint32_t c) {
 // byte, so these loads never leave mapped memory.
 // ---------------------------------------------------------------------------
 
+// Pointers to the input in the global address space, so that its loads are
+// tracked apart from LDS traffic.
+#ifndef GZ_GLOBAL
+#define GZ_GLOBAL __attribute__((address_space(1)))
+#endif
+typedef const GZ_GLOBAL uint32_t *gdw_ptr;
+
 struct Src {
-  const uint32_t *base;  // comp rounded down to 4 bytes
+  gdw_ptr base;          // comp rounded down to 4 bytes
   uint32_t mis;          // comp & 3
   uint64_t nbytes;
   uint64_t end_bits;     // 8 * nbytes
+  int64_t full_lo;       // dwords [full_lo, full_hi) lie wholly inside the buffer
+  int64_t full_hi;
 
   __device__ void init(const uint8_t *comp, uint64_t n) {
     uintptr_t p = (uintptr_t)comp;
     mis = (uint32_t)(p & 3u);
-    base = (const uint32_t *)(p - mis);
+    base = (gdw_ptr)(p - mis);
     nbytes = n;
     end_bits = 8ull * n;
+    full_lo = mis ? 1 : 0;
+    full_hi = (int64_t)((mis + n) >> 2);
   }
-  // dword D of the aligned view (file byte 4D - mis .. 4D - mis + 3)
-  __device__ __forceinline__ uint32_t dw(int64_t D) const {
-    int64_t b0 = D * 4 - (int64_t)mis;  // file byte of the dword's first byte
-    if (b0 >= 0 && b0 + 4 <= (int64_t)nbytes) return __builtin_nontemporal_load(base + D);
+  // a dword at an edge of the buffer: bytes outside [0, n) read as zero
+  __device__ uint32_t dw_edge(int64_t D) const {
+    int64_t b0 = D * 4 - (int64_t)mis;
     if (b0 + 4 <= 0 || b0 >= (int64_t)nbytes) return 0u;
     uint32_t w = base[D];
     uint32_t m = 0;
@@ -75,6 +85,11 @@ struct Src {
     for (int k = 0; k < 4; k++)
       if (b0 + k >= 0 && b0 + k < (int64_t)nbytes) m |= 0xFFu << (8 * k);
     return w & m;
+  }
+  // dword D of the aligned view (file bytes 4D - mis .. 4D - mis + 3)
+  __device__ __forceinline__ uint32_t dw(int64_t D) const {
+    if (D >= full_lo && D < full_hi) return base[D];
+    return dw_edge(D);
   }
   // 64 bits starting at file bit b (bits past the end read as zero); per lane
   __device__ __forceinline__ uint64_t peek64(uint64_t b) const {
@@ -93,10 +108,12 @@ struct Src {
 
 // ---------------------------------------------------------------------------
 // Wave-uniform bit reader.  Lane l holds the dword D of the aligned view with
-// D = l (mod 64) for D in [lo, lo + 64); lo is a multiple of 32.  When the read
-// position enters the upper half, the lanes of the consumed half take the
-// dwords prefetched one half earlier and prefetch the next ones, so a refill
-// never waits on memory in the decode loop.
+// D = l (mod 64) for D in [lo, lo + 64); lo is a multiple of 32.  refill(),
+// called before each peek(), moves the window when the read position has
+// entered the upper half: the lanes of the consumed half take the dwords
+// prefetched one half earlier and prefetch the next ones, so a refill never
+// waits on memory.  A symbol with its extra bits takes at most 48 bits, so one
+// peek() after a refill always has 64 valid bits.
 // ---------------------------------------------------------------------------
 
 struct WaveBits {
@@ -116,22 +133,22 @@ struct WaveBits {
     win = s.dw(D);
     nxt = (D < lo + 32) ? s.dw(D + 64) : 0u;
   }
-  __device__ __forceinline__ void advance() {
-    int64_t D = dword_of(pos);
-    if (D < lo + 32) return;
-    if (D >= lo + 48) {  // a jump (stored block): start over at pos
-      init(pos);
-      return;
-    }
+  __device__ void half_step() {
     int l = lane_id();
     int64_t Dl = lo + ((l - (int)(lo & 63)) & 63);
-    bool old = Dl < lo + 32;
-    win = old ? nxt : win;
+    win = Dl < lo + 32 ? nxt : win;
     lo += 32;
     int64_t D2 = lo + ((l - (int)(lo & 63)) & 63);
     if (D2 < lo + 32) nxt = s.dw(D2 + 64);
   }
-  // 64 bits at pos (valid while pos is inside the lower half, kept by advance)
+  __device__ __forceinline__ void refill() {
+    const int64_t D = dword_of(pos);
+    if (D >= lo + 32) {
+      if (D >= lo + 48) init(pos);  // a jump (stored block)
+      else half_step();
+    }
+  }
+  // 64 bits at pos; valid after refill() and until 48 more bits are skipped
   __device__ __forceinline__ uint64_t peek() const {
     uint64_t a = pos + 8ull * s.mis;
     int64_t D = (int64_t)(a >> 5);
@@ -142,10 +159,11 @@ struct WaveBits {
     uint64_t v = ((uint64_t)w1 << 32) | w0;
     return sh ? ((v >> sh) | ((uint64_t)w2 << (64 - sh))) : v;
   }
-  __device__ __forceinline__ void skip(uint32_t n) {
-    pos += n;
-    advance();
+  __device__ __forceinline__ uint64_t next() {
+    refill();
+    return peek();
   }
+  __device__ __forceinline__ void skip(uint32_t n) { pos += n; }
   __device__ __forceinline__ bool past_end() const { return pos > s.end_bits; }
 };
 
@@ -350,13 +368,13 @@ enum : int { D_OK = 0, D_BAD = 1, D_TRUNC = 2, D_ASCII = 3, D_SIZE = 4, D_FAR = 
 // accepted.  fill = false only validates.
 __device__ int read_dynamic_tables(WaveBits &br, TablesLDS &sh, bool strict, bool fill, bool *no_dist) {
   const int lane = lane_id();
-  uint64_t v = br.peek();
+  uint64_t v = br.next();
   const uint32_t hlit = (uint32_t)(v & 31u) + 257u;
   const uint32_t hdist = (uint32_t)((v >> 5) & 31u) + 1u;
   const uint32_t hclen = (uint32_t)((v >> 10) & 15u) + 4u;
   br.skip(14);
   if (hlit > 286u || hdist > 30u) return D_BAD;
-  v = br.peek();
+  v = br.next();
   // code-length code lengths, sent in the order 16 17 18 0 8 7 9 6 10 5 11 4 12 3 13 2 14 1 15
   if (lane < 19) sh.lens[lane] = 0;
   wave_sync();
@@ -381,7 +399,7 @@ __device__ int read_dynamic_tables(WaveBits &br, TablesLDS &sh, bool strict, boo
   // every pass stores at least one length, so total passes at most
   for (uint32_t pass = 0; i < total; pass++) {
     if (pass >= total) return D_BAD;
-    v = br.peek();
+    v = br.next();
     const uint32_t e = uni32(sh.dist[v & 127u]);
     uint32_t cl = e & 15u, sym = e >> 8;
     if (sym < 16u) {

@@ -40,8 +40,12 @@ struct DecodeResult {
 
 template <int WIN>
 struct Inflater {
+  // The ring holds the whole DEFLATE window (32768 symbols), so every match
+  // source is in LDS: a source pos - d + k (d <= 32768) is read before any
+  // write of this match reaches its slot, and the unit being moved to HBM is
+  // never older than 512 + 258 symbols.
+  static_assert(WIN == 32768, "the LDS history must hold the whole window");
   static constexpr uint32_t RMASK = WIN - 1;
-  static constexpr uint32_t FAR = WIN - 1024;  // farther distances are read back from HBM
 
   InflateLDS<WIN> &sh;
   WaveBits br;
@@ -82,40 +86,39 @@ struct Inflater {
     if (pos - flushed >= FLUSH_UNIT) flush_unit();
   }
 
-  // Copy len symbols from dist back.  The source of element k is before the
+  // Copy len symbols from d back.  The source of element k is before the
   // match start: pos - d + k when d >= 64 (an earlier 64-step already wrote
   // it), pos - d + (k mod d) when d < 64.  Sources before the chunk are the
   // placeholders U_j.
   __device__ __forceinline__ int put_match(uint32_t len, uint32_t d) {
     if (first && (uint64_t)d > pos) return D_FAR;
     const int lane = lane_id();
-    const bool far = d > FAR;
-    if (far) __builtin_amdgcn_s_waitcnt(0x0F70);  // this wave's flush stores are done
-    const float rd = 1.0f / (float)d;
-    for (uint32_t k0 = 0; k0 < len; k0 += 64) {
-      wave_sync();
-      uint32_t k = k0 + (uint32_t)lane;
-      if (k < len) {
-        int64_t src;
-        if (d >= 64u) {
-          src = (int64_t)pos + k - d;
-        } else {
+    if (d >= 64u) {
+      for (uint32_t k0 = 0; k0 < len; k0 += 64) {
+        wave_sync();
+        const uint32_t k = k0 + (uint32_t)lane;
+        if (k < len) {
+          const int64_t src = (int64_t)pos + k - d;
+          const uint32_t v = src < 0 ? 0x8000u | (uint32_t)(32768 + src) : (uint32_t)sh.ring[src & RMASK];
+          nph += v >> 15;
+          sh.ring[(pos + k) & RMASK] = (uint16_t)v;
+        }
+      }
+    } else {
+      const float rd = 1.0f / (float)d;
+      for (uint32_t k0 = 0; k0 < len; k0 += 64) {
+        wave_sync();
+        const uint32_t k = k0 + (uint32_t)lane;
+        if (k < len) {
           int q = (int)((float)k * rd);
           int r = (int)k - q * (int)d;
           if (r >= (int)d) r -= (int)d;
           if (r < 0) r += (int)d;
-          src = (int64_t)pos - d + r;
+          const int64_t src = (int64_t)pos - d + r;
+          const uint32_t v = src < 0 ? 0x8000u | (uint32_t)(32768 + src) : (uint32_t)sh.ring[src & RMASK];
+          nph += v >> 15;
+          sh.ring[(pos + k) & RMASK] = (uint16_t)v;
         }
-        uint32_t v;
-        if (src < 0) {
-          v = 0x8000u | (uint32_t)(32768 + src);
-        } else if (far) {
-          v = (uint64_t)src < cap ? (uint32_t)D[src] : 0u;
-        } else {
-          v = sh.ring[src & RMASK];
-        }
-        nph += v >> 15;
-        sh.ring[(pos + k) & RMASK] = (uint16_t)v;
       }
     }
     pos += len;
@@ -127,8 +130,7 @@ struct Inflater {
   __device__ int stored(bool check) {
     const int lane = lane_id();
     br.pos = (br.pos + 7) & ~7ull;
-    br.advance();
-    uint64_t v = br.peek();
+    uint64_t v = br.next();
     uint32_t n = (uint32_t)(v & 0xFFFFu), nn = (uint32_t)((v >> 16) & 0xFFFFu);
     br.skip(32);
     if (br.past_end()) return D_TRUNC;
@@ -136,7 +138,7 @@ struct Inflater {
     const uint64_t fb = br.pos >> 3;
     if (br.pos + 8ull * n > br.s.end_bits) return D_TRUNC;
     for (uint32_t k0 = 0; k0 < n; k0 += 64) {
-      uint32_t k = k0 + (uint32_t)lane;
+      const uint32_t k = k0 + (uint32_t)lane;
       bool bad = false;
       if (k < n) {
         uint32_t c = br.s.byte(fb + k);
@@ -148,7 +150,6 @@ struct Inflater {
       maybe_flush();
     }
     br.pos += 8ull * n;
-    br.advance();
     return D_OK;
   }
 
@@ -158,7 +159,7 @@ struct Inflater {
     const uint64_t budget = br.s.end_bits - br.pos + 1;
     for (uint64_t it = 0;; it++) {
       if (it > budget) return D_BAD;
-      const uint64_t v = br.peek();
+      const uint64_t v = br.next();
       uint32_t e = uni32(sh.t.lit[v & ((1u << LIT_BITS) - 1)]);
       uint32_t kind = (e >> 4) & 15u;
       if (kind == K_LONG) {
@@ -207,7 +208,7 @@ struct Inflater {
   // candidate block itself (must be a non-final dynamic block with a complete
   // literal/length code and a size in (1 KiB, 4 MiB)).
   __device__ int block(bool check, bool strict, bool *final_out) {
-    const uint64_t v = br.peek();
+    const uint64_t v = br.next();
     const uint32_t bfinal = (uint32_t)(v & 1u), btype = (uint32_t)((v >> 1) & 3u);
     br.skip(3);
     if (br.past_end()) return D_TRUNC;
@@ -964,19 +965,10 @@ hipError_t gzk_scan(const FileDesc *files, const ChunkDesc *chunks, ChunkState *
 }
 
 #define GZ_WIN_SWITCH(win, CALL) \
-  switch (win) {                 \
-    case 8192: {                 \
-      constexpr int W = 8192;    \
-      CALL;                      \
-    } break;                     \
-    case 32768: {                \
-      constexpr int W = 32768;   \
-      CALL;                      \
-    } break;                     \
-    default: {                   \
-      constexpr int W = 16384;   \
-      CALL;                      \
-    } break;                     \
+  {                              \
+    (void)(win);                 \
+    constexpr int W = 32768;     \
+    CALL;                        \
   }
 
 hipError_t gzk_inflate(int win, uint32_t grid, const FileDesc *files, const ChunkDesc *chunks, ChunkState *cs,
