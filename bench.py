@@ -58,7 +58,7 @@ def main():
     ap.add_argument("--workload", default="fastq_1GiB_L6")
     ap.add_argument("--chunk-bytes", type=int, default=1 << 20)
     ap.add_argument("--waves-per-chunk", type=int, default=1)
-    ap.add_argument("--window", type=int, default=16384)
+    ap.add_argument("--window", type=int, default=0, help="LDS history ring per decoding wave (0: library default)")
     ap.add_argument("--cpu-sample-mib", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()

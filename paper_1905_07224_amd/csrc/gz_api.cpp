@@ -229,7 +229,9 @@ static void fill_defaults(gz_plan_t p, const gz_opts *opts) {
   if (opts) p->opts = *opts;
   if (p->opts.chunk_bytes == 0) p->opts.chunk_bytes = 1 << 20;
   if (p->opts.sym_factor == 0) p->opts.sym_factor = 8;
-  p->win = 32768;  // the LDS history always holds the whole DEFLATE window
+  // LDS history ring of each decoding wave: older match sources are read back
+  // from HBM, so a smaller ring trades those reads for more waves per CU
+  p->win = p->opts.window_syms ? p->opts.window_syms : DEFAULT_RING;
   p->groups = p->opts.scan_groups ? p->opts.scan_groups : 8;
   (void)hipGetDevice(&p->device);
   hipDeviceProp_t prop;
@@ -242,6 +244,10 @@ static int make_plan(gz_plan_t *plan, const gz_job *jobs, int n, const gz_opts *
   gz_plan_t p = new (std::nothrow) gz_plan_s();
   if (!p) return GZ_E_ARG;
   fill_defaults(p, opts);
+  if (p->win != 4096 && p->win != 8192 && p->win != 16384 && p->win != 32768) {
+    gz_plan_destroy(p);
+    return GZ_E_ARG;
+  }
   p->jobs.assign(jobs, jobs + n);
   int r = plan_common(p);
   if (r != GZ_OK) {
@@ -321,7 +327,7 @@ static int launch(gz_plan_t p, uint8_t *ws, size_t ws_bytes, hipStream_t st) {
   uint16_t *pool = (uint16_t *)(ws + L.sym_off);
 
   const uint32_t lds_per_cu = 160 * 1024;
-  const uint32_t per_wave = (uint32_t)(6272 + 2 * p->win + 256);
+  const uint32_t per_wave = inflate_lds_bytes(p->win) + 256;
   uint32_t waves_per_cu = p->opts.inflate_waves_per_cu ? p->opts.inflate_waves_per_cu
                                                        : std::max<uint32_t>(1, lds_per_cu / per_wave);
   uint32_t grid = std::min<uint32_t>(N, waves_per_cu * (uint32_t)p->n_cu);

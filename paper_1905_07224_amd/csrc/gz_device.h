@@ -163,6 +163,22 @@ struct WaveBits {
     refill();
     return peek();
   }
+  // 128 bits at pos as four dwords (q0 holds bits pos .. pos + 31)
+  __device__ __forceinline__ void view128(uint32_t &q0, uint32_t &q1, uint32_t &q2, uint32_t &q3) {
+    refill();
+    const uint64_t a = pos + 8ull * s.mis;
+    const int64_t D = (int64_t)(a >> 5);
+    const uint32_t sh = (uint32_t)(a & 31);
+    const uint32_t w0 = (uint32_t)__builtin_amdgcn_readlane((int)win, (int)(D & 63));
+    const uint32_t w1 = (uint32_t)__builtin_amdgcn_readlane((int)win, (int)((D + 1) & 63));
+    const uint32_t w2 = (uint32_t)__builtin_amdgcn_readlane((int)win, (int)((D + 2) & 63));
+    const uint32_t w3 = (uint32_t)__builtin_amdgcn_readlane((int)win, (int)((D + 3) & 63));
+    const uint32_t w4 = (uint32_t)__builtin_amdgcn_readlane((int)win, (int)((D + 4) & 63));
+    q0 = (uint32_t)((((uint64_t)w1 << 32) | w0) >> sh);
+    q1 = (uint32_t)((((uint64_t)w2 << 32) | w1) >> sh);
+    q2 = (uint32_t)((((uint64_t)w3 << 32) | w2) >> sh);
+    q3 = (uint32_t)((((uint64_t)w4 << 32) | w3) >> sh);
+  }
   __device__ __forceinline__ void skip(uint32_t n) { pos += n; }
   __device__ __forceinline__ bool past_end() const { return pos > s.end_bits; }
 };
@@ -173,16 +189,18 @@ struct WaveBits {
 // [31:16] base length / distance.
 // ---------------------------------------------------------------------------
 
-enum : uint32_t { K_LIT = 0, K_LEN = 1, K_EOB = 2, K_LONG = 3, K_BAD = 4, K_BADSYM = 5 };
+// K_LITX: a literal outside the block-start check's ASCII set (kind & 7 is
+// K_LIT for both literal kinds)
+enum : uint32_t { K_LIT = 0, K_LEN = 1, K_EOB = 2, K_LONG = 3, K_BAD = 4, K_BADSYM = 5, K_LITX = 8 };
 
 constexpr int LIT_BITS = 10;
-constexpr int DIST_BITS = 8;
+constexpr int DIST_BITS = 10;
 constexpr int CL_BITS = 7;
 
 // lengths 3..258 (section 3.2.5): codes 257..264 carry no extra bits, then
 // four codes per extra-bit count 1..5, then 285 = 258
 __device__ __forceinline__ uint32_t litlen_entry(uint32_t sym, uint32_t len) {
-  if (sym < 256u) return len | (K_LIT << 4) | (sym << 8);
+  if (sym < 256u) return len | ((ascii_text(sym) ? K_LIT : K_LITX) << 4) | (sym << 8);
   if (sym == 256u) return len | (K_EOB << 4);
   if (sym <= 285u) {
     uint32_t i = sym - 257u, ex, base;

@@ -28,6 +28,10 @@ struct InflateLDS {
   TablesLDS t;
   alignas(16) uint16_t ring[WIN];  // the last WIN symbols produced, by position mod WIN
 };
+static_assert(sizeof(InflateLDS<4096>) <= inflate_lds_bytes(4096) && sizeof(InflateLDS<8192>) <= inflate_lds_bytes(8192) &&
+                  sizeof(InflateLDS<16384>) <= inflate_lds_bytes(16384) &&
+                  sizeof(InflateLDS<32768>) <= inflate_lds_bytes(32768),
+              "decoder LDS larger than the occupancy estimate");
 
 struct DecodeResult {
   int status;        // D_OK or failure
@@ -40,11 +44,15 @@ struct DecodeResult {
 
 template <int WIN>
 struct Inflater {
-  // The ring holds the whole DEFLATE window (32768 symbols), so every match
-  // source is in LDS: a source pos - d + k (d <= 32768) is read before any
-  // write of this match reaches its slot, and the unit being moved to HBM is
-  // never older than 512 + 258 symbols.
-  static_assert(WIN == 32768, "the LDS history must hold the whole window");
+  // The ring holds the last WIN symbols (WIN a power of two, 4096..32768).
+  // A batch reads all its sources before it writes any of its symbols, so a
+  // source pos - d + k with d <= WIN is in the ring; an older one (only when
+  // WIN < 32768) is read back from this chunk's symbols in HBM, which were
+  // stored at least WIN - 576 symbols earlier: every unit store waits for the
+  // stores before it, so those are complete, and the read bypasses the L1,
+  // which may still hold lines of an earlier attempt at this chunk.  The unit
+  // being moved to HBM is never older than 512 + 64 symbols.
+  static_assert(WIN >= 4096 && WIN <= 32768 && (WIN & (WIN - 1)) == 0, "ring size");
   static constexpr uint32_t RMASK = WIN - 1;
 
   InflateLDS<WIN> &sh;
@@ -58,10 +66,15 @@ struct Inflater {
   uint32_t nph_stop; // per lane placeholder count at the stop (symbols of D_i only)
   bool first;        // empty context
   bool over;         // capacity exceeded somewhere
+  bool emit;         // false: blocks past the stop are only parsed and counted
 
   __device__ Inflater(InflateLDS<WIN> &s) : sh(s) {}
+  __device__ __forceinline__ uint32_t sh_lit(uint32_t i) const { return sh.t.lit[i]; }
+  __device__ __forceinline__ uint32_t sh_dist(uint32_t i) const { return sh.t.dist[i]; }
 
   __device__ __forceinline__ void flush_unit() {
+    // earlier unit stores complete (vmcnt 0) before this one is issued
+    if (WIN < 32768) __builtin_amdgcn_s_waitcnt(0xF70);
     wave_sync();
     const int lane = lane_id();
     const uint64_t u = flushed;
@@ -78,52 +91,6 @@ struct Inflater {
   }
   __device__ void flush_all() {
     while (flushed < pos) flush_unit();
-  }
-
-  __device__ __forceinline__ void put_lit(uint32_t c) {
-    if (lane_id() == 0) sh.ring[pos & RMASK] = (uint16_t)c;
-    pos++;
-    if (pos - flushed >= FLUSH_UNIT) flush_unit();
-  }
-
-  // Copy len symbols from d back.  The source of element k is before the
-  // match start: pos - d + k when d >= 64 (an earlier 64-step already wrote
-  // it), pos - d + (k mod d) when d < 64.  Sources before the chunk are the
-  // placeholders U_j.
-  __device__ __forceinline__ int put_match(uint32_t len, uint32_t d) {
-    if (first && (uint64_t)d > pos) return D_FAR;
-    const int lane = lane_id();
-    if (d >= 64u) {
-      for (uint32_t k0 = 0; k0 < len; k0 += 64) {
-        wave_sync();
-        const uint32_t k = k0 + (uint32_t)lane;
-        if (k < len) {
-          const int64_t src = (int64_t)pos + k - d;
-          const uint32_t v = src < 0 ? 0x8000u | (uint32_t)(32768 + src) : (uint32_t)sh.ring[src & RMASK];
-          nph += v >> 15;
-          sh.ring[(pos + k) & RMASK] = (uint16_t)v;
-        }
-      }
-    } else {
-      const float rd = 1.0f / (float)d;
-      for (uint32_t k0 = 0; k0 < len; k0 += 64) {
-        wave_sync();
-        const uint32_t k = k0 + (uint32_t)lane;
-        if (k < len) {
-          int q = (int)((float)k * rd);
-          int r = (int)k - q * (int)d;
-          if (r >= (int)d) r -= (int)d;
-          if (r < 0) r += (int)d;
-          const int64_t src = (int64_t)pos - d + r;
-          const uint32_t v = src < 0 ? 0x8000u | (uint32_t)(32768 + src) : (uint32_t)sh.ring[src & RMASK];
-          nph += v >> 15;
-          sh.ring[(pos + k) & RMASK] = (uint16_t)v;
-        }
-      }
-    }
-    pos += len;
-    maybe_flush();
-    return D_OK;
   }
 
   // Stored block: LEN raw bytes copied 64 at a time.
@@ -143,63 +110,242 @@ struct Inflater {
       if (k < n) {
         uint32_t c = br.s.byte(fb + k);
         bad = check && !ascii_text(c);
-        sh.ring[(pos + (uint32_t)lane) & RMASK] = (uint16_t)c;
+        if (emit) sh.ring[(pos + (uint32_t)lane) & RMASK] = (uint16_t)c;
       }
       if (__ballot(bad)) return D_ASCII;
       pos += min(64u, n - k0);
-      maybe_flush();
+      if (emit) maybe_flush();
     }
     br.pos += 8ull * n;
     return D_OK;
   }
 
-  // Huffman-coded block body until end-of-block (section 3.2.5).
-  __device__ int huffman(bool check, bool no_dist, uint64_t size_cap, uint64_t blk0) {
-    // each symbol consumes at least one bit: the remaining bits bound the loop
-    const uint64_t budget = br.s.end_bits - br.pos + 1;
+  // Output of one batch: lane l < j describes symbol pos + l.  A value
+  // >= REF_LIT is a literal (low 16 bits); otherwise it is l - distance, a
+  // lane of this batch when >= 0, else a symbol produced before the batch.
+  static constexpr int32_t REF_LIT = 0x10000;
+
+  // Resolve and store the j symbols of a batch.  Sources before the batch
+  // come from the ring, from HBM, or are the placeholders U_j before a chunk
+  // (a distance past the start of the first chunk is invalid data); sources
+  // in the batch are earlier lanes, followed by pointer jumping: a lane whose
+  // source is still open takes that lane's source, so after k rounds every
+  // chain of up to 2^k links is closed.
+  __device__ __forceinline__ int expand(int32_t ref, uint32_t j) {
+    const int lane = lane_id();
+    const bool act = lane < (int)j;
+    uint32_t val = 0;
+    int32_t p = lane;  // open lanes point at their source, closed lanes at themselves
+    bool far = false, before = false;
+    int64_t a = 0;
+    wave_sync();
+    if (act) {
+      if (ref >= REF_LIT) {
+        val = (uint32_t)ref & 0xFFFFu;
+      } else if (ref < 0) {
+        a = (int64_t)pos + ref;
+        if (a < 0) {
+          before = true;
+          val = 0x8000u | (uint32_t)(a + WINDOW);
+        } else if (WIN == 32768 || a >= (int64_t)pos - WIN) {
+          val = (uint32_t)sh.ring[a & RMASK];
+        } else {
+          far = true;
+        }
+      } else {
+        p = ref;
+      }
+    }
+    if (first && __ballot(before)) return D_FAR;
+    if (WIN < 32768 && __ballot(far)) {
+      // past capacity nothing was stored: the chunk fails with a capacity
+      // status, so any value will do
+      if (far)
+        val = (uint64_t)a < cap ? (uint32_t)__hip_atomic_load(D + a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                : 0u;
+    }
+    for (int it = 0; it < 8; it++) {
+      if (__ballot(p != lane) == 0) break;
+      const uint32_t vs = __shfl(val, p);
+      const int32_t ps = __shfl(p, p);
+      if (p != lane) {
+        if (ps == p) {
+          val = vs;
+          p = lane;
+        } else {
+          p = ps;
+        }
+      }
+    }
+    if (__ballot(p != lane)) return D_BAD;  // unreachable: chains are shorter than 64
+    if (act) {
+      sh.ring[(pos + (uint32_t)lane) & RMASK] = (uint16_t)val;
+      nph += val >> 15;
+    }
+    pos += j;
+    maybe_flush();
+    return D_OK;
+  }
+
+  __device__ __forceinline__ int put_batch(int32_t ref, uint32_t j) {
+    if (!emit) {
+      pos += j;
+      return D_OK;
+    }
+    return expand(ref, j);
+  }
+
+  // A symbol whose code is longer than the lookup tables, decoded alone at
+  // br.pos: *len_out = 0 for a literal (stored in *lit), 0xFFFFFFFF for
+  // end-of-block, else a match of *len_out symbols at *dist_out.
+  __device__ int slow_symbol(bool check, uint32_t *lit, uint32_t *len_out, uint32_t *dist_out) {
+    const uint64_t v = br.next();
+    uint32_t e = uni32(sh.t.lit[v & ((1u << LIT_BITS) - 1u)]);
+    if (((e >> 4) & 15u) == K_LONG) e = decode_long<LIT_BITS, TREE_LIT>(v, &sh.t.li, sh.t.lsorted);
+    const uint32_t kind = (e >> 4) & 15u, cl = e & 15u;
+    nsyms++;
+    if ((kind & 7u) == K_LIT) {
+      if (check && kind == K_LITX) return D_ASCII;
+      *lit = (e >> 8) & 255u;
+      *len_out = 0;
+      br.skip(cl);
+      return br.past_end() ? D_TRUNC : D_OK;
+    }
+    if (kind == K_EOB) {
+      *len_out = 0xFFFFFFFFu;
+      br.skip(cl);
+      return br.past_end() ? D_TRUNC : D_OK;
+    }
+    if (kind != K_LEN) return D_BAD;
+    const uint32_t ex = (e >> 8) & 255u;
+    const uint32_t len = (e >> 16) + ((uint32_t)(v >> cl) & ((1u << ex) - 1u));
+    const uint32_t used = cl + ex;
+    const uint64_t v2 = v >> used;
+    uint32_t ed = uni32(sh.t.dist[v2 & ((1u << DIST_BITS) - 1u)]);
+    if (((ed >> 4) & 15u) == K_LONG) ed = decode_long<DIST_BITS, TREE_DIST>(v2, &sh.t.di, sh.t.dsorted);
+    if (((ed >> 4) & 15u) != K_LEN) return D_BAD;
+    const uint32_t dl = ed & 15u, dex = (ed >> 8) & 255u;
+    *dist_out = (ed >> 16) + ((uint32_t)(v2 >> dl) & ((1u << dex) - 1u));
+    *len_out = len;
+    br.skip(used + dl + dex);
+    return br.past_end() ? D_TRUNC : D_OK;
+  }
+
+  // Token descriptors of one lookup round (per lane k: the token that would
+  // start at bit offset k).  TOK_SPECIAL set: the walk stops there, with the
+  // kind in bits 29..28 (end-of-block: its code length in the low bits).
+  static constexpr uint32_t TOK_SPECIAL = 0x80000000u;
+  static constexpr uint32_t TOK_EOB = TOK_SPECIAL | (1u << 28);
+  static constexpr uint32_t TOK_SLOW = TOK_SPECIAL | (2u << 28);   // longer code, or invalid: decoded alone
+  static constexpr uint32_t TOK_ASCII = TOK_SPECIAL | (3u << 28);  // non-ASCII literal in a checked block
+
+  // Huffman-coded block body until end-of-block (section 3.2.5), decoded in
+  // rounds of 64 bit offsets.  Lane k reads the 64 stream bits at offset k
+  // from br.pos and decodes the token that would start there: its
+  // literal/length code, extra length bits, distance code and extra
+  // distance bits (at most 48 bits, RFC 1951 section 3.2.5), with one lookup
+  // in each table.  The scalar walk then follows the real tokens from offset
+  // 0 (each one bit count further) while they start below offset 64, and
+  // turns them into batches of up to 64 output symbols.  CHECK: literals must
+  // be ASCII text (block-start trial and confirmation).
+  template <bool CHECK>
+  __device__ int huffman(uint64_t size_cap, uint64_t blk0) {
+    const int lane = lane_id();
+    const uint32_t LMASK = (1u << LIT_BITS) - 1u, DMASK = (1u << DIST_BITS) - 1u;
+    uint32_t info = 0;  // bits used | output symbols << 8, or a TOK_ kind
+    int32_t tval = 0;   // REF_LIT | literal, or -distance
+    uint32_t off = 0;   // bit offset of the walk from br.pos, where the round was decoded
+    bool need = true;   // a round to be decoded at br.pos + off
+    uint32_t rem = 0, mdist = 0;  // part of a match still to be produced
+    // a batch consumes at least one bit or produces 64 symbols (<= 258 per
+    // code): the remaining bits bound the batches
+    const uint64_t budget = 8ull * (br.s.end_bits - br.pos + 64);
     for (uint64_t it = 0;; it++) {
       if (it > budget) return D_BAD;
-      const uint64_t v = br.next();
-      uint32_t e = uni32(sh.t.lit[v & ((1u << LIT_BITS) - 1)]);
-      uint32_t kind = (e >> 4) & 15u;
-      if (kind == K_LONG) {
-        e = decode_long<LIT_BITS, TREE_LIT>(v, &sh.t.li, sh.t.lsorted);
-        kind = (e >> 4) & 15u;
+      if (need) {
+        br.pos += off;
+        uint32_t q0, q1, q2, q3;
+        br.view128(q0, q1, q2, q3);
+        const bool lo_half = lane < 32;
+        const uint32_t a0 = lo_half ? q0 : q1, a1 = lo_half ? q1 : q2, a2 = lo_half ? q2 : q3;
+        const uint32_t sh = (uint32_t)lane & 31u;
+        const uint32_t w0 = __builtin_amdgcn_alignbit(a1, a0, sh);
+        const uint32_t w1 = __builtin_amdgcn_alignbit(a2, a1, sh);
+        const uint64_t w = ((uint64_t)w1 << 32) | w0;
+        const uint32_t e = sh_lit(w0 & LMASK);
+        const uint32_t kind = (e >> 4) & 15u, cl = e & 15u, ex = (e >> 8) & 15u;
+        const uint32_t u = cl + ex;
+        const uint32_t ed = sh_dist((uint32_t)(w >> u) & DMASK);
+        const uint32_t dl = ed & 15u, dex = (ed >> 8) & 15u;
+        const uint32_t len = (e >> 16) + ((w0 >> cl) & ((1u << ex) - 1u));
+        const uint32_t dist = (ed >> 16) + ((uint32_t)(w >> (u + dl)) & ((1u << dex) - 1u));
+        if ((kind & 7u) == K_LIT) {
+          info = (CHECK && kind == K_LITX) ? TOK_ASCII : (cl | (1u << 8));
+          tval = (int32_t)(REF_LIT | ((e >> 8) & 255u));
+        } else if (kind == K_LEN) {
+          info = ((ed >> 4) & 15u) == K_LEN ? (u + dl + dex) | (len << 8) : TOK_SLOW;
+          tval = -(int32_t)dist;
+        } else {
+          info = kind == K_EOB ? (TOK_EOB | cl) : TOK_SLOW;
+        }
+        off = 0;
+        need = false;
       }
-      const uint32_t cl = e & 15u;
-      nsyms++;
-      if (kind == K_LIT) {
-        const uint32_t c = (e >> 8) & 255u;
-        if (check && !ascii_text(c)) return D_ASCII;
-        put_lit(c);
-        br.skip(cl);
-        if (br.past_end()) return D_TRUNC;
-        continue;
+      int32_t ref = 0;
+      uint32_t j = 0;
+      if (rem) {
+        const uint32_t n = min(rem, 64u);
+        if ((uint32_t)lane < n) ref = lane - (int32_t)mdist;
+        j = n;
+        rem -= n;
       }
-      if (kind == K_EOB) {
-        br.skip(cl);
-        return br.past_end() ? D_TRUNC : D_OK;
+      uint32_t x = 0, ntok = 0;
+      while (j < 64u && off < 64u) {
+        x = (uint32_t)__builtin_amdgcn_readlane((int)info, (int)off);
+        if (x & TOK_SPECIAL) break;
+        const int32_t v = __builtin_amdgcn_readlane(tval, (int)off);
+        const uint32_t len = x >> 8;
+        const uint32_t n = min(len, 64u - j);
+        const int32_t add = v < 0 ? lane : 0;
+        if ((uint32_t)lane - j < n) ref = v + add;
+        j += n;
+        rem = len - n;
+        mdist = (uint32_t)(-v);
+        off += x & 255u;
+        ntok++;
+        x = 0;
       }
-      if (kind != K_LEN) return D_BAD;
-      const uint32_t ex = (e >> 8) & 255u;
-      const uint32_t len = (e >> 16) + ((uint32_t)(v >> cl) & ((1u << ex) - 1u));
-      uint32_t used = cl + ex;
-      if (no_dist) return D_BAD;
-      const uint64_t v2 = v >> used;
-      uint32_t ed = uni32(sh.t.dist[v2 & ((1u << DIST_BITS) - 1)]);
-      uint32_t kd = (ed >> 4) & 15u;
-      if (kd == K_LONG) {
-        ed = decode_long<DIST_BITS, TREE_DIST>(v2, &sh.t.di, sh.t.dsorted);
-        kd = (ed >> 4) & 15u;
+      nsyms += ntok;
+      if (j) {
+        const int r = put_batch(ref, j);
+        if (r != D_OK) return r;
       }
-      if (kd != K_LEN) return D_BAD;
-      const uint32_t dl = ed & 15u, dex = (ed >> 8) & 255u;
-      const uint32_t dist = (ed >> 16) + ((uint32_t)(v2 >> dl) & ((1u << dex) - 1u));
-      used += dl + dex;
-      br.skip(used);
-      if (br.past_end()) return D_TRUNC;
-      int r = put_match(len, dist);
-      if (r) return r;
+      if (x & TOK_SPECIAL) {
+        if (x == TOK_ASCII) return D_ASCII;
+        if ((x & ~255u) == TOK_EOB) {
+          nsyms++;
+          br.pos += off + (x & 255u);
+          return br.past_end() ? D_TRUNC : D_OK;
+        }
+        // TOK_SLOW: one symbol decoded alone, then a new round
+        br.pos += off;
+        off = 0;
+        need = true;
+        uint32_t c = 0, len = 0, dist = 0;
+        const int r = slow_symbol(CHECK, &c, &len, &dist);
+        if (r != D_OK) return r;
+        if (len == 0xFFFFFFFFu) return D_OK;
+        if (len == 0) {
+          const int r2 = put_batch(lane == 0 ? (int32_t)(REF_LIT | c) : 0, 1u);
+          if (r2 != D_OK) return r2;
+        } else {
+          rem = len;
+          mdist = dist;
+        }
+      } else if (off >= 64u) {
+        need = true;
+      }
+      if (br.pos + off > br.s.end_bits) return D_TRUNC;
       if (pos - blk0 >= size_cap) return D_SIZE;
     }
   }
@@ -218,13 +364,20 @@ struct Inflater {
     int r;
     if (btype == 0u) {
       r = stored(check);
-    } else if (btype == 1u) {
-      fixed_tables(sh.t);
-      r = huffman(check, false, ~0ull, blk0);
-    } else if (btype == 2u) {
-      bool nd = false;
-      r = read_dynamic_tables(br, sh.t, strict, true, &nd);
-      if (r == D_OK) r = huffman(check, nd, strict ? (4ull << 20) : ~0ull, blk0);
+    } else if (btype <= 2u) {
+      if (btype == 1u) {
+        fixed_tables(sh.t);
+        r = D_OK;
+      } else {
+        // with no distance codes the distance table holds only invalid
+        // entries, so a length code fails as the format requires
+        bool nd = false;
+        r = read_dynamic_tables(br, sh.t, strict, true, &nd);
+      }
+      if (r == D_OK) {
+        const uint64_t cap_sz = strict ? (4ull << 20) : ~0ull;
+        r = check ? huffman<true>(cap_sz, blk0) : huffman<false>(cap_sz, blk0);
+      }
     } else {
       r = D_BAD;
     }
@@ -257,6 +410,10 @@ struct Inflater {
         res.end = br.pos;
         res.len = pos;
         nph_stop = nph;
+        // the confirmation blocks still to come are not part of this chunk:
+        // their symbols are checked and counted but not stored
+        flush_all();
+        emit = false;
       }
       if (res.end != NONE && nb >= check_blocks) break;
       bool fin = false;
@@ -281,7 +438,7 @@ struct Inflater {
     res.blocks = nb;
     if (res.end == NONE) nph_stop = nph;
     if (res.status == D_OK) res.confirmed = true;
-    flush_all();
+    if (emit) flush_all();
     return res;
   }
 };
@@ -299,6 +456,7 @@ __device__ __forceinline__ void inflater_setup(Inflater<WIN> &inf, const FileDes
   inf.nph_stop = 0;
   inf.first = (cd.flags & CF_FIRST) != 0;
   inf.over = false;
+  inf.emit = true;
 }
 
 // Next chunk of the same file that has a start (scan candidate or accepted).
@@ -812,37 +970,64 @@ __global__ __launch_bounds__(256) void k_finalize(const FileDesc *files, const C
 // of (w_hat_i ++ D_i); the first chunk's window is unknown (zero).
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(1024) void k_propagate(const FileDesc *files, const ChunkDesc *chunks,
-                                                    const ChunkState *cs, const FileState *fs, uint8_t *wins,
-                                                    const uint16_t *pool) {
+// The chain is sequential, so its cost is the latency of one step: each
+// thread holds 32 of the 32768 tail symbols of the chunk being resolved in
+// registers and loads the next chunk's while this one goes through LDS.
+constexpr int PROP_THREADS = 1024;
+constexpr int PROP_PER = WINDOW / PROP_THREADS;
+
+__device__ __forceinline__ uint32_t next_accepted(const ChunkState *cs, uint32_t j, uint32_t c1) {
+  for (uint32_t g = 0; j < c1 && g < c1 && cs[j].start == NONE; g++) j++;
+  return j;
+}
+
+// symbols k = i * PROP_THREADS + tid of the last 32768 of (w_hat ++ D_j)
+__device__ __forceinline__ void load_tail(const uint16_t *__restrict__ Dj, uint64_t L, int tid,
+                                          uint32_t (&t)[PROP_PER]) {
+#pragma unroll
+  for (int i = 0; i < PROP_PER; i++) {
+    const uint64_t q = L + (uint64_t)(i * PROP_THREADS + tid);
+    t[i] = q < WINDOW ? (0x8000u | (uint32_t)q) : (uint32_t)Dj[q - WINDOW];
+  }
+}
+
+__global__ __launch_bounds__(PROP_THREADS) void k_propagate(const FileDesc *files, const ChunkDesc *chunks,
+                                                            const ChunkState *cs, const FileState *fs,
+                                                            uint8_t *__restrict__ wins,
+                                                            const uint16_t *__restrict__ pool) {
   __shared__ uint8_t wbuf[2][WINDOW];
   const uint32_t f = blockIdx.x;
   const FileDesc fd = files[f];
   if (fs[f].status != ST_OK) return;
   const int tid = (int)threadIdx.x;
   const uint32_t c0 = fd.first_chunk, c1 = fd.first_chunk + fd.n_chunks;
-  for (int k = tid; k < (int)WINDOW; k += blockDim.x) wbuf[0][k] = 0;
+  for (int k = tid; k < (int)WINDOW; k += PROP_THREADS) wbuf[0][k] = 0;
+  uint32_t j = next_accepted(cs, c0, c1);
+  if (j >= c1) return;
+  uint32_t t[PROP_PER], tn[PROP_PER];
+  load_tail(pool + chunks[j].sym_off, cs[j].len, tid, t);
   __syncthreads();
   int cur = 0;
-  uint32_t j = c0;
-  for (uint32_t g = 0; g < fd.n_chunks && j < c1 && cs[j].start == NONE; g++) j++;
-  for (uint32_t step = 0; step < fd.n_chunks && j < c1; step++) {
-    uint32_t jn = j + 1;
-    for (uint32_t g = 0; g < fd.n_chunks && jn < c1 && cs[jn].start == NONE; g++) jn++;
+  for (uint32_t step = 0; step < fd.n_chunks; step++) {
+    const uint32_t jn = next_accepted(cs, j + 1, c1);
     if (jn >= c1) break;
-    const uint64_t L = cs[j].len;
-    const uint16_t *Dj = pool + chunks[j].sym_off;
+    // the chunk after jn, whose tail is loaded while jn's window is resolved
+    const uint32_t jnn = next_accepted(cs, jn + 1, c1);
+    if (jnn < c1) load_tail(pool + chunks[jn].sym_off, cs[jn].len, tid, tn);
     uint8_t *wo = wins + (uint64_t)jn * WINDOW;
-    for (int k = tid; k < (int)WINDOW; k += blockDim.x) {
-      const uint64_t q = L + (uint64_t)k;
-      const uint32_t t = q < WINDOW ? (0x8000u | (uint32_t)q) : (uint32_t)Dj[q - WINDOW];
-      const uint8_t b = t < 256u ? (uint8_t)t : wbuf[cur][t & 0x7FFFu];
+#pragma unroll
+    for (int i = 0; i < PROP_PER; i++) {
+      const int k = i * PROP_THREADS + tid;
+      const uint32_t x = t[i];
+      const uint8_t b = x < 256u ? (uint8_t)x : wbuf[cur][x & 0x7FFFu];
       wbuf[cur ^ 1][k] = b;
       wo[k] = b;
     }
     __syncthreads();
     cur ^= 1;
     j = jn;
+#pragma unroll
+    for (int i = 0; i < PROP_PER; i++) t[i] = tn[i];
   }
 }
 
@@ -964,11 +1149,26 @@ hipError_t gzk_scan(const FileDesc *files, const ChunkDesc *chunks, ChunkState *
   return hipGetLastError();
 }
 
-#define GZ_WIN_SWITCH(win, CALL) \
-  {                              \
-    (void)(win);                 \
-    constexpr int W = 32768;     \
-    CALL;                        \
+#define GZ_WIN_SWITCH(win, CALL)   \
+  switch (win) {                   \
+    case 4096: {                   \
+      constexpr int W = 4096;      \
+      CALL;                        \
+    } break;                       \
+    case 8192: {                   \
+      constexpr int W = 8192;      \
+      CALL;                        \
+    } break;                       \
+    case 16384: {                  \
+      constexpr int W = 16384;     \
+      CALL;                        \
+    } break;                       \
+    case 32768: {                  \
+      constexpr int W = 32768;     \
+      CALL;                        \
+    } break;                       \
+    default:                       \
+      return hipErrorInvalidValue; \
   }
 
 hipError_t gzk_inflate(int win, uint32_t grid, const FileDesc *files, const ChunkDesc *chunks, ChunkState *cs,
@@ -998,7 +1198,7 @@ hipError_t gzk_tilescan(const ChunkDesc *chunks, const ChunkState *cs, const Fil
 
 hipError_t gzk_propagate(uint32_t n_files, const FileDesc *files, const ChunkDesc *chunks, const ChunkState *cs,
                          const FileState *fs, uint8_t *wins, const uint16_t *pool, hipStream_t st) {
-  hipLaunchKernelGGL(k_propagate, dim3(n_files), dim3(1024), 0, st, files, chunks, cs, fs, wins, pool);
+  hipLaunchKernelGGL(k_propagate, dim3(n_files), dim3(PROP_THREADS), 0, st, files, chunks, cs, fs, wins, pool);
   return hipGetLastError();
 }
 

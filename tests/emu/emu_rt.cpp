@@ -86,6 +86,16 @@ void resolve_wave(unsigned w) {
         break;
       }
       case EMU_FIRSTLANE: f.res = B.f[t0].val; break;
+      case EMU_WRITELANE: {
+        if (f.aux != B.f[t0].aux) die("writelane with a value or lane index that differs between lanes", w);
+        f.res = (t - t0) == (unsigned)(f.aux & 63) ? (f.aux >> 32) : f.val;
+        break;
+      }
+      case EMU_SHFL: {
+        unsigned src = t0 + ((unsigned)f.aux & 63);
+        f.res = src < t1 ? B.f[src].val : 0;
+        break;
+      }
       case EMU_SHFL_XOR: {
         unsigned src = t0 + (((t - t0) ^ (unsigned)f.aux) & 63);
         f.res = src < t1 ? B.f[src].val : f.val;

@@ -53,7 +53,8 @@ unsigned emu_gdim(void);
 void emu_run_grid(void (*fn)(void *), void *arg, unsigned grid, unsigned block);
 int emu_n_cu(void);
 }
-enum { EMU_BALLOT = 1, EMU_READLANE = 2, EMU_FIRSTLANE = 3, EMU_SHFL_XOR = 4, EMU_WAVEBAR = 5 };
+enum { EMU_BALLOT = 1, EMU_READLANE = 2, EMU_FIRSTLANE = 3, EMU_SHFL_XOR = 4, EMU_WAVEBAR = 5, EMU_WRITELANE = 6,
+       EMU_SHFL = 7 };
 
 template <typename F>
 static void emu_tramp(void *p) {
@@ -78,6 +79,18 @@ static inline int __ffsll(unsigned long long x) { return __builtin_ffsll((long l
 template <typename T>
 static inline T __shfl_xor(T v, int o) {
   return (T)emu_wave_sync(EMU_SHFL_XOR, (uint64_t)v, (uint64_t)o);
+}
+template <typename T>
+static inline T __shfl(T v, int src) {
+  return (T)emu_wave_sync(EMU_SHFL, (uint64_t)(uint32_t)v, (uint64_t)(uint32_t)src);
+}
+// writelane(value, lane, old): lane `lane` takes the (uniform) value, the others keep old
+static inline int emu_writelane(uint32_t val, uint32_t l, uint32_t old) {
+  return (int)emu_wave_sync(EMU_WRITELANE, old, ((uint64_t)val << 32) | (l & 63u));
+}
+#define __builtin_amdgcn_writelane(v, l, o) emu_writelane((uint32_t)(v), (uint32_t)(l), (uint32_t)(o))
+static inline uint32_t __builtin_amdgcn_alignbit(uint32_t hi, uint32_t lo, uint32_t s) {
+  return (uint32_t)((((uint64_t)hi << 32) | lo) >> (s & 31u));
 }
 #define __builtin_amdgcn_readlane(v, l) ((int)emu_wave_sync(EMU_READLANE, (uint32_t)(v), (uint64_t)(l)))
 #define __builtin_amdgcn_readfirstlane(v) ((int)emu_wave_sync(EMU_FIRSTLANE, (uint32_t)(v), 0))

@@ -71,7 +71,7 @@ def test_emu_segmented_and_stored(orc):
 def test_emu_window_sizes(orc):
     raw = synth.fastq_like(100 << 10, 305)
     comp = synth.gzip_member(raw, 6)
-    for win in (8192, 32768):
+    for win in (4096, 8192, 16384, 32768):
         st, out, r, tab = E.run(comp, 3, out_cap=len(raw) + 64, window_syms=win)
         assert st == 0 and out == raw
 
@@ -89,3 +89,20 @@ def test_emu_errors(orc):
     assert st == -4
     st, out, r, tab = E.run(bytes(comp), 2, out_cap=100)
     assert st == -5 and r.out_needed == len(raw)
+
+
+def test_emu_short_distances(orc):
+    # matches whose source lies in the same 64-symbol batch (distances 1..63,
+    # lengths up to 258): runs, short periods, and periods just under and over 64
+    rng = np.random.default_rng(307)
+    parts = [b"A" * 5000, b"ab" * 3000, b"xyz" * 2000]
+    for period in (5, 17, 63, 64, 65, 130):
+        unit = bytes(rng.integers(97, 123, period, dtype=np.uint8))
+        parts.append(unit * (4000 // period))
+        parts.append(bytes(rng.integers(32, 127, 300, dtype=np.uint8)))
+    raw = b"".join(parts)
+    for level in (1, 6, 9):
+        comp = synth.gzip_member(raw, level)
+        # far more symbols per compressed byte than the default capacity factor
+        st, out, r, tab = E.run(comp, 1, out_cap=len(raw) + 64, sym_factor=4096)
+        assert st == 0 and out == raw, level
