@@ -28,26 +28,54 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(sample_mib: int):
-    """The CPU oracle (single-threaded, bit-serial RFC 1951 inflate) on a bounded
-    sample of the same generator, in decompressed GB/s."""
+def cpu_baseline(sample_mib: int, chunk_bytes: int):
+    """The CPU oracle's two-pass decompression (single-threaded: block-start
+    search, symbolic pass, window propagation, translation, all bit-serial) on
+    a bounded sample of the same generator, cut into chunks of the same
+    compressed size, in decompressed GB/s."""
     import oracle
     import synth
 
     raw, gz = synth.make("fastq", sample_mib << 20, 2, 6, read_lens=(100, 150))
+    n = max(1, (len(gz) + chunk_bytes - 1) // chunk_bytes)
     oracle.lib()
     t0 = time.perf_counter()
-    r = oracle.gunzip(gz)
+    r = oracle.pugz(gz, n)
     dt = time.perf_counter() - t0
-    ok = r.status == 0 and len(r.out) == len(raw)
+    ok = r.status == 0 and r.out.tobytes() == raw
     return {
         "value": round(len(raw) / dt / 1e9, 6),
         "unit": "GB/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": f"{len(raw)} bytes of FASTQ-like text (same generator, 100/150 bp), gzip -6, "
-                  f"sequential CPU oracle on one host core, {dt:.1f} s, ok={ok}",
+        "sample": f"{len(raw)} bytes of FASTQ-like text (same generator, 100/150 bp), gzip -6, {n} chunks of "
+                  f"{chunk_bytes} compressed bytes; two-pass CPU oracle on one host core, {dt:.1f} s, "
+                  f"bytes equal to the source: {ok}",
     }
+
+
+def recorded_traffic(kernel: str, workload: str, chunk_bytes: int, window: int):
+    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE/WRITE_SIZE
+    summary, or None when that summary was taken on other kernel sources or
+    another configuration."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", f"hbm_k_inflate_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if " = " in line and not line.startswith(("|", " ")):
+            k, v = line.strip().split(" = ", 1)
+            kv[k] = v
+    h = hashlib.sha256()
+    for f in ("gz_kernels.hip", "gz_device.h", "gz_internal.h"):
+        with open(os.path.join(ROOT, "paper_1905_07224_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    same = (kv.get("source_sha256") == h.hexdigest() and kv.get("kernel", "").endswith(kernel)
+            and kv.get("workload") == workload and kv.get("chunk_bytes") == str(chunk_bytes)
+            and kv.get("window_syms") == str(window))
+    return int(kv["traffic_bytes"]) if same else None
 
 
 def main():
@@ -56,11 +84,13 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="fastq_1GiB_L6")
-    ap.add_argument("--chunk-bytes", type=int, default=1 << 20)
+    ap.add_argument("--chunk-bytes", type=int, default=0, help="compressed bytes per chunk (0: library default)")
     ap.add_argument("--waves-per-chunk", type=int, default=1)
     ap.add_argument("--window", type=int, default=0, help="LDS history ring per decoding wave (0: library default)")
     ap.add_argument("--cpu-sample-mib", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="after warmup, one device-to-device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -83,8 +113,10 @@ def main():
     dev = torch.device("cuda:0")
     d_comp = torch.frombuffer(bytearray(comp), dtype=torch.uint8).to(dev)
     out = torch.empty(len(raw), dtype=torch.uint8, device=dev)
-    plan = gz.Plan(d_comp, 0, chunk_bytes=args.chunk_bytes, waves_per_chunk=args.waves_per_chunk,
-                   window_syms=args.window, timing=1)
+    chunk_bytes = args.chunk_bytes or gz.DEFAULT_CHUNK_BYTES
+    window = args.window or gz.DEFAULT_WINDOW
+    plan = gz.Plan(d_comp, 0, chunk_bytes=chunk_bytes, waves_per_chunk=args.waves_per_chunk,
+                   window_syms=window, timing=1)
     log(f"plan: {plan.n_chunks} chunks, workspace {plan.info.ws_bytes / 2**30:.2f} GiB")
     stream = torch.cuda.current_stream()
 
@@ -101,6 +133,18 @@ def main():
             log(f"warmup: status {r.status}, byte-exact {exact}, passes {plan.pass_times()}")
             if not exact:
                 raise SystemExit("output differs from the source text")
+
+    if args.calib_copy_mib:
+        # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE readings scale
+        # the counters of the decompression kernels to bytes
+        n = args.calib_copy_mib << 18
+        src = torch.ones(n, dtype=torch.int32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {n * 4} bytes read and written")
+        del src, dst
 
     # timed steps
     passes = []
@@ -130,14 +174,15 @@ def main():
     # write one 16-bit symbol per decompressed byte
     inflate_bytes = len(comp) + 2 * len(raw)
     achieved = inflate_bytes / (inflate_ms / 1e3) / 1e9
+    kname = f"k_inflate<{window}>"
     roofline = {
-        "kernel": "k_inflate",
+        "kernel": kname,
         "bound": "hbm",
         "achieved": round(achieved, 3),
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 6),
-        "traffic": None,
+        "traffic": recorded_traffic(kname, args.workload, chunk_bytes, window),
         "algorithmic_bytes": inflate_bytes,
         "avg_ms": round(inflate_ms, 4),
     }
@@ -145,7 +190,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle on a {args.cpu_sample_mib} MiB sample")
-        cpu = cpu_baseline(args.cpu_sample_mib)
+        cpu = cpu_baseline(args.cpu_sample_mib, chunk_bytes)
         log(f"cpu baseline: {cpu['value']} GB/s")
 
     line = {
@@ -167,10 +212,10 @@ def main():
             "uncompressed_bytes": len(raw),
             "compressed_bytes": len(comp),
             "ratio": round(len(raw) / len(comp), 4),
-            "chunk_bytes": args.chunk_bytes,
+            "chunk_bytes": chunk_bytes,
             "waves_per_chunk": args.waves_per_chunk,
             "n_chunks": plan.n_chunks,
-            "window_syms": args.window,
+            "window_syms": window,
             "compressed_MBps": round(len(comp) * args.steps / dt / 1e6, 1),
         },
         "passes_ms": {k: round(v, 4) for k, v in avg.items()},

@@ -49,10 +49,10 @@ extern "C" {
  * into n roughly equal parts; Section VI-A and Appendix A give the
  * block-start checks whose constants appear here.) */
 typedef struct gz_opts {
-  uint64_t chunk_bytes;   /* nominal compressed bytes per chunk when n_chunks == 0 (default 1 MiB) */
+  uint64_t chunk_bytes;   /* nominal compressed bytes per chunk when n_chunks == 0 (default 256 KiB) */
   uint32_t sym_factor;    /* symbol capacity per chunk = sym_factor * compressed bytes + slack (default 8) */
   uint32_t window_syms;   /* LDS history ring per decoding wave, in symbols: 4096, 8192, 16384 or 32768
-                             (default 8192); match sources further back are read from HBM.
+                             (default 4096); match sources further back are read from HBM.
                              Any other value: GZ_E_ARG */
   uint32_t scan_groups;   /* workgroups that search one chunk's start in parallel (default 8) */
   uint32_t inflate_waves_per_cu; /* persistent inflate grid = this * CU count (default: occupancy) */

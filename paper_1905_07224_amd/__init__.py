@@ -66,6 +66,9 @@ EXPORTS = ["gz_plan", "gz_plan_batch", "gz_plan_info", "gz_decompress", "gz_deco
            "gz_chunk_table", "gz_debug_layout", "gz_plan_destroy", "gz_strerror", "gz_device_info", "gz_pass_times",
            "gz_pass_name"]
 GZ_N_PASSES = N_PASSES = 10
+# defaults of gz_opts (include/gzgpu.h)
+DEFAULT_CHUNK_BYTES = 256 << 10
+DEFAULT_WINDOW = 4096
 
 
 def lib():

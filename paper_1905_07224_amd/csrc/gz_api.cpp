@@ -227,7 +227,7 @@ static int plan_common(gz_plan_t p) {
 
 static void fill_defaults(gz_plan_t p, const gz_opts *opts) {
   if (opts) p->opts = *opts;
-  if (p->opts.chunk_bytes == 0) p->opts.chunk_bytes = 1 << 20;
+  if (p->opts.chunk_bytes == 0) p->opts.chunk_bytes = DEFAULT_CHUNK_BYTES;
   if (p->opts.sym_factor == 0) p->opts.sym_factor = 8;
   // LDS history ring of each decoding wave: older match sources are read back
   // from HBM, so a smaller ring trades those reads for more waves per CU
