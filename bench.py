@@ -54,6 +54,153 @@ def cpu_baseline(sample_mib: int, chunk_bytes: int):
     }
 
 
+def batched_vs_plain(n_files: int, reps: int):
+    """Decompressed GB/s of n_files C1-like files (4 MiB FASTQ-like, gzip -6,
+    seeds 1..n_files): back-to-back one-file launches on one stream (plain),
+    one batched launch sequence (batched), and the batched sequence replayed
+    from its HIP graph (graph).  Median over reps; inputs and outputs stay in
+    HBM; every output is compared with its source text after the timing."""
+    import statistics
+
+    import torch
+
+    import paper_1905_07224_amd as gz
+    import synth
+
+    dev = torch.device("cuda:0")
+    raws, comps = [], []
+    for k in range(1, n_files + 1):
+        raw, comp = synth.make("fastq", 4 << 20, k, 6)
+        raws.append(raw)
+        comps.append(torch.frombuffer(bytearray(comp), dtype=torch.uint8).to(dev))
+    total = sum(len(r) for r in raws)
+    outs = [torch.empty(len(r), dtype=torch.uint8, device=dev) for r in raws]
+    s = torch.cuda.Stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(fn):
+        ms = []
+        for _ in range(reps + 1):
+            torch.cuda.synchronize()
+            with torch.cuda.stream(s):
+                e0.record(s)
+                fn()
+                e1.record(s)
+            s.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        return statistics.median(ms[1:])
+
+    def exact():
+        return all(torch.equal(o, torch.frombuffer(bytearray(r), dtype=torch.uint8).to(dev))
+                   for o, r in zip(outs, raws))
+
+    plans = [gz.Plan(c, 0) for c in comps]
+    for p_ in plans:
+        p_.workspace()
+
+    def plain():
+        for p_, o in zip(plans, outs):
+            p_.launch(o, s)
+
+    ms_plain = timed(plain)
+    ok_plain = all(p_.result().status == 0 for p_ in plans) and exact()
+    del plans
+    bp = gz.BatchPlan(comps, 0, outs=outs)
+    bp.workspace()
+    ms_batch = timed(lambda: bp.launch(s))
+    ok_batch = all(bp.result(i).status == 0 for i in range(n_files)) and exact()
+    ms_graph = timed(lambda: bp.launch_graph(s))
+    ok_graph = all(bp.result(i).status == 0 for i in range(n_files)) and exact()
+    return {
+        "files": n_files,
+        "uncompressed_bytes": total,
+        "compressed_bytes": sum(c.numel() for c in comps),
+        "reps": reps,
+        "plain_GBps": round(total / ms_plain / 1e6, 4),
+        "batched_GBps": round(total / ms_batch / 1e6, 4),
+        "graph_GBps": round(total / ms_graph / 1e6, 4),
+        "plain_ms": round(ms_plain, 3),
+        "batched_ms": round(ms_batch, 3),
+        "graph_ms": round(ms_graph, 3),
+        "bit_exact": bool(ok_plain and ok_batch and ok_graph),
+    }
+
+
+def serving(n_jobs: int, load: float, budget_gib: int):
+    """The serving loop under Poisson arrivals.  Job inputs are drawn
+    log-uniformly from a pool of 10 files of 64 KiB .. 32 MiB (FASTQ-like and
+    word-stream text alternating, levels 1/6/9 in turn, seeds 100..109);
+    capacity is first measured closed-loop (all jobs at once), then jobs
+    arrive at load x capacity.  Latency = completion seen by the poll - the
+    scheduled arrival; GB/s = all bytes / (last completion - first arrival).
+    Every output is compared with its source text afterwards."""
+    import numpy as np
+    import torch
+
+    import paper_1905_07224_amd as gz
+    import synth
+
+    dev = torch.device("cuda:0")
+    pool = []
+    for i in range(10):
+        kind = "fastq" if i % 2 == 0 else "words"
+        raw, comp = synth.make(kind, (64 << 10) << i, 100 + i, (1, 6, 9)[i % 3])
+        pool.append((torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(dev),
+                     torch.frombuffer(bytearray(comp), dtype=torch.uint8).to(dev)))
+    rng = np.random.default_rng(5)
+    pick = rng.integers(0, len(pool), n_jobs)
+    outs = [torch.empty(pool[k][0].numel(), dtype=torch.uint8, device=dev) for k in pick]
+    nbytes = [pool[k][0].numel() for k in pick]
+    budget = budget_gib << 30
+
+    def run(arrivals):
+        srv = gz.Server(budget_bytes=budget, max_inflight=4, max_batch=64)
+        t0 = srv.stats()["now"]
+        sched = [t0 + a for a in arrivals]
+        done, nxt = {}, 0
+        while len(done) < n_jobs:
+            now = srv.stats()["now"]
+            while nxt < n_jobs and sched[nxt] <= now:
+                srv.submit(pool[pick[nxt]][1], outs[nxt], nxt)
+                nxt += 1
+            for d in srv.poll():
+                done[d["tag"]] = d
+            if nxt == n_jobs and len(done) < n_jobs:
+                time.sleep(0.0002)
+            if srv.stats()["now"] - t0 > 120:
+                raise SystemExit("serving run did not finish within 120 s")
+        info = srv.stats()
+        srv.close()
+        return sched, done, info
+
+    sched, done, _ = run([0.0] * n_jobs)
+    span = max(d["t_end"] for d in done.values()) - sched[0]
+    capacity = sum(nbytes) / span
+    rate = load * capacity / (sum(nbytes) / n_jobs)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, n_jobs))
+    arrivals -= arrivals[0]
+    sched, done, info = run(list(arrivals))
+    lat = np.array([done[k]["t_end"] - sched[k] for k in range(n_jobs)]) * 1e3
+    span = max(d["t_end"] for d in done.values()) - sched[0]
+    ok = all(done[k]["status"] == 0 and done[k]["out_len"] == nbytes[k] for k in range(n_jobs))
+    ok = ok and all(torch.equal(outs[k], pool[pick[k]][0]) for k in range(n_jobs))
+    return {
+        "jobs": n_jobs,
+        "pool": "10 files, 64 KiB..32 MiB log-spaced, FASTQ-like/words alternating, levels 1/6/9",
+        "mean_job_bytes": int(sum(nbytes) / n_jobs),
+        "capacity_GBps": round(capacity / 1e9, 4),
+        "offered_load": load,
+        "arrival_rate_per_s": round(rate, 2),
+        "p50_ms": round(float(np.percentile(lat, 50)), 3),
+        "p99_ms": round(float(np.percentile(lat, 99)), 3),
+        "GBps": round(sum(nbytes) / span / 1e9, 4),
+        "batches": int(info["batches"]),
+        "budget_GiB": budget_gib,
+        "arena_peak_GiB": round(info["arena_peak"] / 2**30, 3),
+        "bit_exact": bool(ok),
+    }
+
+
 def recorded_traffic(kernel: str, workload: str, chunk_bytes: int, window: int):
     """HBM bytes per launch of `kernel` from the committed FETCH_SIZE/WRITE_SIZE
     summary, or None when that summary was taken on other kernel sources or
@@ -89,6 +236,9 @@ def main():
     ap.add_argument("--window", type=int, default=0, help="LDS history ring per decoding wave (0: library default)")
     ap.add_argument("--cpu-sample-mib", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch-files", type=int, default=32, help="files of the batched-vs-plain set (0: skip)")
+    ap.add_argument("--serve-jobs", type=int, default=400, help="jobs of the serving run (0: skip)")
+    ap.add_argument("--serve-load", type=float, default=0.7, help="offered load, fraction of measured capacity")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after warmup, one device-to-device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -117,7 +267,8 @@ def main():
     window = args.window or gz.DEFAULT_WINDOW
     plan = gz.Plan(d_comp, 0, chunk_bytes=chunk_bytes, waves_per_chunk=args.waves_per_chunk,
                    window_syms=window, timing=1)
-    log(f"plan: {plan.n_chunks} chunks, workspace {plan.info.ws_bytes / 2**30:.2f} GiB")
+    n_chunks = plan.n_chunks
+    log(f"plan: {n_chunks} chunks, workspace {plan.info.ws_bytes / 2**30:.2f} GiB")
     stream = torch.cuda.current_stream()
 
     # warmup, with a byte-exact check of the output against the source text
@@ -187,6 +338,21 @@ def main():
         "avg_ms": round(inflate_ms, 4),
     }
 
+    batched = None
+    if args.batch_files:
+        del plan, out
+        torch.cuda.empty_cache()
+        log(f"batched vs plain: {args.batch_files} C1-like files")
+        batched = batched_vs_plain(args.batch_files, 5)
+        log(f"batched vs plain: {batched}")
+
+    served = None
+    if args.serve_jobs:
+        torch.cuda.empty_cache()
+        log(f"serving: {args.serve_jobs} jobs at load {args.serve_load}")
+        served = serving(args.serve_jobs, args.serve_load, 96)
+        log(f"serving: {served}")
+
     cpu = None
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle on a {args.cpu_sample_mib} MiB sample")
@@ -214,7 +380,7 @@ def main():
             "ratio": round(len(raw) / len(comp), 4),
             "chunk_bytes": chunk_bytes,
             "waves_per_chunk": args.waves_per_chunk,
-            "n_chunks": plan.n_chunks,
+            "n_chunks": n_chunks,
             "window_syms": window,
             "compressed_MBps": round(len(comp) * args.steps / dt / 1e6, 1),
         },
@@ -222,6 +388,8 @@ def main():
         "stats": {k: stats[k] for k in ("n_nonempty", "n_repairs", "n_extended", "n_retries", "n_syms",
                                          "n_placeholders", "n_blocks")},
         "roofline": roofline,
+        "batched_vs_plain": batched,
+        "serving": served,
         "cpu_baseline": cpu,
         "bit_exact": True,
     }

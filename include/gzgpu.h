@@ -58,7 +58,9 @@ typedef struct gz_opts {
   uint32_t inflate_waves_per_cu; /* persistent inflate grid = this * CU count (default: occupancy) */
   uint32_t waves_per_chunk; /* each nominal chunk is split into this many sub-chunks, one wave each (default 1) */
   uint32_t timing;        /* nonzero: record a HIP event at every pass boundary (see gz_pass_times) */
-  uint32_t reserved[6];
+  uint32_t confirm_decode; /* nonzero: confirmation blocks a chunk owes past its stop are always decoded
+                              on their own instead of taken from the next chunks (same result; tests) */
+  uint32_t reserved[5];
 } gz_opts;
 
 /* One file of a batch. */
@@ -125,6 +127,29 @@ int gz_decompress(gz_plan_t plan, void *d_out, size_t out_cap, void *d_ws, size_
  * d_out.  One launch per pass covers all files and chunks. */
 int gz_decompress_batch(gz_plan_t plan, void *d_ws, size_t ws_bytes, void *stream);
 
+/* Enqueue the same path as gz_decompress_batch (or as the last gz_decompress
+ * of a one-file plan, with its output) as one HIP graph: the first call, and
+ * any call whose workspace or outputs differ from the captured ones, captures
+ * the launch sequence on `stream` (which must not be NULL) and instantiates
+ * it; later calls replay it.  The graph holds no memset nodes; the job table
+ * is a copy from the plan's pinned buffer.  Not with opts.timing (GZ_E_ARG).
+ * Errors as gz_decompress_batch. */
+int gz_decompress_graph(gz_plan_t plan, void *d_ws, size_t ws_bytes, void *stream);
+
+/* Choose opts.chunk_bytes (64 KiB .. 4 MiB; below 256 KiB only for inputs
+ * up to 64 MiB compressed) and opts.window_syms (4096,
+ * 8192, 16384) for one file by timing each candidate on it (two runs each,
+ * the second timed with HIP events on `stream`), and cache the choice per
+ * (device, compressed-size class, compression-ratio class) for the process;
+ * a cached choice returns at once.  *best: in, the other options; out, the
+ * tuned options.  *ws_max (may be NULL): the workspace the most demanding
+ * candidate needs.  d_ws == NULL: only *ws_max is computed.  Candidates whose
+ * workspace exceeds ws_bytes are skipped.  d_out/out_cap as gz_decompress.
+ * Errors: GZ_E_ARG, GZ_E_CAPACITY (no candidate fits), or the decompression
+ * status when every candidate fails. */
+int gz_autotune(const void *d_comp, size_t comp_len, void *d_out, size_t out_cap, void *d_ws, size_t ws_bytes,
+                void *stream, gz_opts *best, uint64_t *ws_max);
+
 /* Wait for the stream of the last gz_decompress* on this plan and read the
  * status and statistics of one file (file 0 for a one-file plan). */
 int gz_result_get(gz_plan_t plan, int file, gz_result *res);
@@ -145,9 +170,9 @@ int gz_debug_layout(gz_plan_t plan, int file, uint64_t *sym_off, uint64_t *win_i
                     void **win_base);
 
 /* Passes timed when opts.timing is set, in launch order. */
-#define GZ_N_PASSES 10
-/* Names: upload, init, scan, capacity, inflate, stitch, finalize, tilescan,
- * propagate, translate.  Waits for the last launch and writes the duration of
+#define GZ_N_PASSES 12
+/* Names: upload, init, scan, capacity, inflate, confirm, redo, stitch,
+ * finalize, tilescan, propagate, translate.  Waits for the last launch and writes the duration of
  * each pass in milliseconds (HIP events on the launch stream) into ms[0..n).
  * Returns the number written, or GZ_E_NOT_READY without timing. */
 int gz_pass_times(gz_plan_t plan, float *ms, int n);
@@ -158,6 +183,58 @@ const char *gz_strerror(int code);
 
 /* Device count and compute-unit count of device `dev` (for sizing). */
 int gz_device_info(int dev, int *n_cu, int *lds_bytes);
+
+/* ------------------------------------------------------------------------
+ * Serving loop (beyond the paper's one-file setting): jobs arrive one at a
+ * time, are admitted into batches while their workspaces fit in a device
+ * arena of budget_bytes allocated at creation (the HBM budget), and run as
+ * batched launch sequences on up to max_inflight streams at once; a finished
+ * batch frees its arena block for the jobs queued behind it (continuous
+ * batching).  Single-threaded: every call on one server comes from one host
+ * thread.  Inputs and outputs stay owned by the caller and must stay valid
+ * until the job is reported done.
+ * ------------------------------------------------------------------------ */
+typedef struct gz_server_s *gz_server_t;
+
+typedef struct gz_server_opts {
+  uint64_t budget_bytes;  /* device arena for workspaces (default 96 GiB) */
+  uint32_t max_inflight;  /* batches in flight, one non-blocking stream each (default 4) */
+  uint32_t max_batch;     /* jobs per batch (default 64) */
+  gz_opts opts;           /* decompression options of every job */
+} gz_server_opts;
+
+typedef struct gz_done {
+  uint64_t tag;           /* as given to gz_server_submit */
+  int32_t status;         /* GZ_OK or a GZ_E_* code (GZ_E_CAPACITY: output too small, or larger than the budget) */
+  uint32_t pad;
+  uint64_t out_len;       /* decompressed bytes written at d_out */
+  double t_submit;        /* seconds since the server was created: submission, */
+  double t_start;         /* launch of its batch, */
+  double t_end;           /* and the poll that saw the batch finished */
+} gz_done;
+
+typedef struct gz_server_info {
+  uint32_t queued, running, finished_unread, pad;
+  uint64_t batches;       /* batches launched so far */
+  uint64_t arena_bytes, arena_used, arena_peak;
+  double now;             /* seconds since creation */
+} gz_server_info;
+
+/* Errors: GZ_E_ARG, GZ_E_HIP (the arena or the streams could not be made). */
+int gz_server_create(gz_server_t *server, const gz_server_opts *opts);
+/* Queue one job (plans it alone to estimate its workspace: reads its gzip
+ * header and trailer).  Errors: GZ_E_ARG, GZ_E_HEADER, GZ_E_HIP. */
+int gz_server_submit(gz_server_t server, const void *d_comp, size_t comp_len, void *d_out, size_t out_cap,
+                     uint64_t tag);
+/* Reap finished batches (a job that ran out of symbol capacity is queued
+ * again, first, with 4x the capacity factor), admit queued jobs in order
+ * while a stream is free and their workspaces fit, and copy up to max_done
+ * finished jobs to done[].  Never waits for the GPU.  Returns the number
+ * copied, or a GZ_E_* code when a launch failed. */
+int gz_server_poll(gz_server_t server, gz_done *done, int max_done);
+int gz_server_stats(gz_server_t server, gz_server_info *info);
+/* Waits for the batches in flight, then frees everything. */
+void gz_server_destroy(gz_server_t server);
 
 #ifdef __cplusplus
 }

@@ -37,7 +37,7 @@ class GzError(RuntimeError):
 class Opts(C.Structure):
     _fields_ = [("chunk_bytes", C.c_uint64), ("sym_factor", C.c_uint32), ("window_syms", C.c_uint32),
                 ("scan_groups", C.c_uint32), ("inflate_waves_per_cu", C.c_uint32), ("waves_per_chunk", C.c_uint32),
-                ("timing", C.c_uint32), ("reserved", C.c_uint32 * 6)]
+                ("timing", C.c_uint32), ("confirm_decode", C.c_uint32), ("reserved", C.c_uint32 * 5)]
 
 
 class Job(C.Structure):
@@ -60,12 +60,35 @@ class Result(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class ServerOpts(C.Structure):
+    _fields_ = [("budget_bytes", C.c_uint64), ("max_inflight", C.c_uint32), ("max_batch", C.c_uint32),
+                ("opts", Opts)]
+
+
+class Done(C.Structure):
+    _fields_ = [("tag", C.c_uint64), ("status", C.c_int32), ("pad", C.c_uint32), ("out_len", C.c_uint64),
+                ("t_submit", C.c_double), ("t_start", C.c_double), ("t_end", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
+
+
+class ServerInfo(C.Structure):
+    _fields_ = [("queued", C.c_uint32), ("running", C.c_uint32), ("finished_unread", C.c_uint32),
+                ("pad", C.c_uint32), ("batches", C.c_uint64), ("arena_bytes", C.c_uint64),
+                ("arena_used", C.c_uint64), ("arena_peak", C.c_uint64), ("now", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
+
+
 _lib = None
 
 EXPORTS = ["gz_plan", "gz_plan_batch", "gz_plan_info", "gz_decompress", "gz_decompress_batch", "gz_result_get",
            "gz_chunk_table", "gz_debug_layout", "gz_plan_destroy", "gz_strerror", "gz_device_info", "gz_pass_times",
-           "gz_pass_name"]
-GZ_N_PASSES = N_PASSES = 10
+           "gz_pass_name", "gz_decompress_graph", "gz_autotune", "gz_server_create", "gz_server_submit",
+           "gz_server_poll", "gz_server_stats", "gz_server_destroy"]
+GZ_N_PASSES = N_PASSES = 12
 # defaults of gz_opts (include/gzgpu.h)
 DEFAULT_CHUNK_BYTES = 256 << 10
 DEFAULT_WINDOW = 4096
@@ -94,10 +117,19 @@ def lib():
         L.gz_strerror.restype = C.c_char_p
         L.gz_device_info.argtypes = [i32, C.POINTER(i32), C.POINTER(i32)]
         L.gz_pass_times.argtypes = [vp, C.POINTER(C.c_float), i32]
+        L.gz_decompress_graph.argtypes = [vp, vp, C.c_size_t, vp]
+        L.gz_autotune.argtypes = [vp, C.c_size_t, vp, C.c_size_t, vp, C.c_size_t, vp, C.POINTER(Opts),
+                                  C.POINTER(u64)]
+        L.gz_server_create.argtypes = [C.POINTER(vp), C.POINTER(ServerOpts)]
+        L.gz_server_submit.argtypes = [vp, vp, C.c_size_t, vp, C.c_size_t, u64]
+        L.gz_server_poll.argtypes = [vp, C.POINTER(Done), i32]
+        L.gz_server_stats.argtypes = [vp, C.POINTER(ServerInfo)]
+        L.gz_server_destroy.argtypes = [vp]
+        L.gz_server_destroy.restype = None
         L.gz_pass_name.argtypes = [i32]
         L.gz_pass_name.restype = C.c_char_p
         for name in EXPORTS:
-            if name not in ("gz_plan_destroy", "gz_strerror", "gz_pass_name"):
+            if name not in ("gz_plan_destroy", "gz_strerror", "gz_pass_name", "gz_server_destroy"):
                 getattr(L, name).restype = i32
         _lib = L
     return _lib
@@ -158,6 +190,7 @@ class Plan:
         self.info = Info()
         _check(lib().gz_plan_info(self._h, C.byref(self.info)))
         self.ws = None
+        self._graph_out = None
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -181,6 +214,19 @@ class Plan:
         with torch.cuda.device(self.device):
             _check(lib().gz_decompress(self._h, optr, ocap, C.c_void_p(ws.data_ptr()), ws.numel(),
                                        _stream_handle(stream)))
+
+    def launch_graph(self, out: torch.Tensor | None, stream):
+        """Like launch(), through the plan's captured HIP graph (captured again
+        when the output or the workspace changes); `stream` must not be the
+        null stream."""
+        ws = self.workspace()
+        if self._graph_out is not out:
+            # the output enters the plan through the eager entry point, once
+            self._graph_out = out
+            self.launch(out, stream)
+            self.result()
+        with torch.cuda.device(self.device):
+            _check(lib().gz_decompress_graph(self._h, C.c_void_p(ws.data_ptr()), ws.numel(), _stream_handle(stream)))
 
     def result(self, file: int = 0) -> Result:
         r = Result()
@@ -323,6 +369,13 @@ class BatchPlan:
         with torch.cuda.device(self.device):
             _check(lib().gz_decompress_batch(self._h, C.c_void_p(ws.data_ptr()), ws.numel(), _stream_handle(stream)))
 
+    def launch_graph(self, stream):
+        """Like launch(), through the plan's captured HIP graph; `stream` must
+        not be the null stream."""
+        ws = self.workspace()
+        with torch.cuda.device(self.device):
+            _check(lib().gz_decompress_graph(self._h, C.c_void_p(ws.data_ptr()), ws.numel(), _stream_handle(stream)))
+
     def result(self, file: int) -> Result:
         r = Result()
         _check(lib().gz_result_get(self._h, file, C.byref(r)))
@@ -360,3 +413,80 @@ def decompress_batch(comps, n_chunks=0, stream=None, **opts):
             _check(r.status)
         return [o[: r.out_len] for o, r in zip(outs, res)]
     raise GzError(GZ_E_CAPACITY, "capacity retries exhausted")
+
+
+def autotune(comp, out: torch.Tensor | None = None, stream=None, **opts) -> dict:
+    """Tuned options (chunk_bytes, window_syms) for this input, from
+    gz_autotune: every candidate is timed on the input itself, and the choice
+    is cached per device and input class for the process."""
+    comp = _as_device_bytes(comp)
+    base = _opts(**opts)
+    need = C.c_uint64(0)
+    with torch.cuda.device(comp.device):
+        _check(lib().gz_autotune(C.c_void_p(comp.data_ptr()), comp.numel(), None, 0, None, 0, None, C.byref(base),
+                                 C.byref(need)))
+        if out is None:
+            info_plan = Plan(comp, 0, **opts)
+            out = torch.empty(_out_guess(info_plan.info.isize, comp.numel()), dtype=torch.uint8, device=comp.device)
+            del info_plan
+        ws = torch.empty(int(need.value), dtype=torch.uint8, device=comp.device)
+        best = _opts(**opts)
+        _check(lib().gz_autotune(C.c_void_p(comp.data_ptr()), comp.numel(), C.c_void_p(out.data_ptr()), out.numel(),
+                                 C.c_void_p(ws.data_ptr()), ws.numel(), _stream_handle(stream), C.byref(best), None))
+    return {"chunk_bytes": int(best.chunk_bytes), "window_syms": int(best.window_syms)}
+
+
+class Server:
+    """The serving loop of gz_server_*: submit jobs (device tensors), poll for
+    finished ones.  The tensors of a job are held until it is reported done."""
+
+    def __init__(self, budget_bytes: int = 0, max_inflight: int = 0, max_batch: int = 0, device=None, **opts):
+        self.device = torch.device(device or "cuda:0")
+        o = ServerOpts()
+        o.budget_bytes = budget_bytes
+        o.max_inflight = max_inflight
+        o.max_batch = max_batch
+        o.opts = _opts(**opts)
+        self._h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib().gz_server_create(C.byref(self._h), C.byref(o)))
+        self._held = {}
+        self._buf = (Done * 256)()
+
+    def submit(self, comp: torch.Tensor, out: torch.Tensor, tag: int):
+        with torch.cuda.device(self.device):
+            _check(lib().gz_server_submit(self._h, C.c_void_p(comp.data_ptr()), comp.numel(),
+                                          C.c_void_p(out.data_ptr()), out.numel(), int(tag)))
+        self._held[int(tag)] = (comp, out)
+
+    def poll(self):
+        """Finished jobs (dicts of gz_done), possibly none; never waits."""
+        res = []
+        while True:
+            with torch.cuda.device(self.device):
+                n = lib().gz_server_poll(self._h, self._buf, len(self._buf))
+            if n < 0:
+                _check(n)
+            for i in range(n):
+                d = self._buf[i].as_dict()
+                self._held.pop(d["tag"], None)
+                res.append(d)
+            if n < len(self._buf):
+                return res
+
+    def stats(self) -> dict:
+        i = ServerInfo()
+        _check(lib().gz_server_stats(self._h, C.byref(i)))
+        return i.as_dict()
+
+    def close(self):
+        if self._h.value:
+            lib().gz_server_destroy(self._h)
+            self._h = C.c_void_p()
+        self._held.clear()
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.gz_server_destroy(h)
+            self._h = C.c_void_p()

@@ -5,8 +5,11 @@
 
 #include <algorithm>
 #include <chrono>
-#include <thread>
+#include <map>
+#include <mutex>
 #include <new>
+#include <thread>
+#include <tuple>
 #include <vector>
 
 #include "../../include/gzgpu.h"
@@ -21,13 +24,18 @@ hipError_t gzk_scan(const FileDesc *, const ChunkDesc *, ChunkState *, const uin
 hipError_t gzk_capacity(uint32_t, const FileDesc *, ChunkDesc *, const ChunkState *, uint32_t, hipStream_t);
 hipError_t gzk_inflate(int, uint32_t, const FileDesc *, const ChunkDesc *, ChunkState *, const uint32_t *, uint32_t,
                        Counters *, uint16_t *, hipStream_t);
+hipError_t gzk_confirm(int, uint32_t, const FileDesc *, const ChunkDesc *, ChunkState *, uint32_t, Counters *,
+                       uint16_t *, uint32_t, hipStream_t);
+hipError_t gzk_redo(int, uint32_t, const FileDesc *, const ChunkDesc *, ChunkState *, uint32_t, Counters *, uint16_t *,
+                    hipStream_t);
 hipError_t gzk_stitch(int, uint32_t, const FileDesc *, const ChunkDesc *, ChunkState *, uint32_t, Counters *,
                       uint16_t *, hipStream_t);
 hipError_t gzk_finalize(int, uint32_t, const FileDesc *, const ChunkDesc *, ChunkState *, FileState *, uint16_t *,
                         hipStream_t);
-hipError_t gzk_tilescan(const ChunkDesc *, const ChunkState *, const FileState *, uint32_t, uint64_t *, hipStream_t);
-hipError_t gzk_propagate(uint32_t, const FileDesc *, const ChunkDesc *, const ChunkState *, const FileState *,
-                         uint8_t *, const uint16_t *, hipStream_t);
+hipError_t gzk_tilescan(const ChunkDesc *, const ChunkState *, const FileState *, uint32_t, uint64_t *, uint32_t *,
+                        AccEntry *, hipStream_t);
+hipError_t gzk_propagate(uint32_t, const uint32_t *, const AccEntry *, uint8_t *, const uint16_t *, uint16_t *,
+                         uint8_t *, hipStream_t);
 hipError_t gzk_translate(uint32_t, const FileDesc *, const ChunkDesc *, const ChunkState *, FileState *,
                          const uint64_t *, uint32_t, const uint8_t *, const uint16_t *, Counters *, hipStream_t);
 }
@@ -107,6 +115,12 @@ struct gz_plan_s {
   bool upload_pending = false;
   hipEvent_t pass_ev[GZ_N_PASSES + 1] = {};
   bool timed = false;
+  // captured launch sequence (gz_decompress_graph)
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  uint8_t *graph_ws = nullptr;
+  std::vector<std::pair<uint8_t *, uint64_t>> graph_out;
+  bool capturing = false;
   // last launch
   uint8_t *ws = nullptr;
   hipStream_t stream = nullptr;
@@ -211,6 +225,14 @@ static int plan_common(gz_plan_t p) {
   o = align_up(o + sizeof(Counters), 256);
   L.tiles_off = o;
   o = align_up(o + ((uint64_t)N + 1) * 8, 256);
+  L.acc_off = o;
+  o = align_up(o + ((uint64_t)N + 1) * 4, 256);
+  o = align_up(o + (uint64_t)N * sizeof(AccEntry), 256);
+  const uint64_t nseg = (N + 63) / 64;
+  L.maps_off = o;
+  o = align_up(o + nseg * WINDOW * 2, 256);
+  L.segwin_off = o;
+  o = align_up(o + nseg * WINDOW, 256);
   L.win_off = o;
   o = align_up(o + (uint64_t)N * WINDOW, 256);
   L.sym_off = o;
@@ -301,6 +323,7 @@ static int launch(gz_plan_t p, uint8_t *ws, size_t ws_bytes, hipStream_t st) {
     (void)hipEventSynchronize(p->upload_done);
     p->upload_pending = false;
   }
+  if (p->capturing && p->opts.timing) return GZ_E_ARG;
   memcpy(p->pinned + L.files_off, p->files.data(), F * sizeof(FileDesc));
   memcpy(p->pinned + L.chunks_off, p->chunks.data(), (size_t)N * sizeof(ChunkDesc));
   memcpy(p->pinned + L.order_off, p->order.data(), (size_t)N * 4);
@@ -312,8 +335,11 @@ static int launch(gz_plan_t p, uint8_t *ws, size_t ws_bytes, hipStream_t st) {
   mark();
   hipError_t e = hipMemcpyAsync(ws, p->pinned, L.table_bytes, hipMemcpyHostToDevice, st);
   if (e != hipSuccess) return hip_fail(e, "job table upload");
-  (void)hipEventRecord(p->upload_done, st);
-  p->upload_pending = true;
+  if (!p->capturing) {
+    // the pinned table may be rewritten by the next call once this copy is done
+    (void)hipEventRecord(p->upload_done, st);
+    p->upload_pending = true;
+  }
 
   const FileDesc *files = (const FileDesc *)(ws + L.files_off);
   const ChunkDesc *chunks = (const ChunkDesc *)(ws + L.chunks_off);
@@ -323,6 +349,8 @@ static int launch(gz_plan_t p, uint8_t *ws, size_t ws_bytes, hipStream_t st) {
   FileState *fs = (FileState *)(ws + L.fstate_off);
   Counters *ctr = (Counters *)(ws + L.counters_off);
   uint64_t *tiles = (uint64_t *)(ws + L.tiles_off);
+  uint32_t *acc_pos = (uint32_t *)(ws + L.acc_off);
+  AccEntry *acc = (AccEntry *)(ws + align_up(L.acc_off + ((uint64_t)N + 1) * 4, 256));
   uint8_t *wins = ws + L.win_off;
   uint16_t *pool = (uint16_t *)(ws + L.sym_off);
 
@@ -345,25 +373,42 @@ static int launch(gz_plan_t p, uint8_t *ws, size_t ws_bytes, hipStream_t st) {
   if ((e = gzk_inflate((int)p->win, grid, files, chunks, cs, order, N, ctr, pool, st)) != hipSuccess)
     return hip_fail(e, "inflate");
   mark();
+  if ((e = gzk_confirm((int)p->win, grid, files, chunks, cs, N, ctr, pool, p->opts.confirm_decode, st)) != hipSuccess)
+    return hip_fail(e, "confirm");
+  mark();
+  if ((e = gzk_redo((int)p->win, grid, files, chunks, cs, N, ctr, pool, st)) != hipSuccess) return hip_fail(e, "redo");
+  mark();
   if ((e = gzk_stitch((int)p->win, grid, files, chunks, cs, N, ctr, pool, st)) != hipSuccess)
     return hip_fail(e, "stitch");
   mark();
   if ((e = gzk_finalize((int)p->win, F, files, chunks, cs, fs, pool, st)) != hipSuccess) return hip_fail(e, "finalize");
   mark();
-  if ((e = gzk_tilescan(chunks, cs, fs, N, tiles, st)) != hipSuccess) return hip_fail(e, "tilescan");
+  if ((e = gzk_tilescan(chunks, cs, fs, N, tiles, acc_pos, acc, st)) != hipSuccess) return hip_fail(e, "tilescan");
   mark();
-  if ((e = gzk_propagate(F, files, chunks, cs, fs, wins, pool, st)) != hipSuccess) return hip_fail(e, "propagate");
+  if ((e = gzk_propagate(N, acc_pos, acc, wins, pool, (uint16_t *)(ws + L.maps_off), ws + L.segwin_off, st)) !=
+      hipSuccess)
+    return hip_fail(e, "propagate");
   mark();
   if ((e = gzk_translate((uint32_t)p->n_cu * 8, files, chunks, cs, fs, tiles, N, wins, pool, ctr, st)) !=
       hipSuccess)
     return hip_fail(e, "translate");
   mark();
+  if (p->capturing) return GZ_OK;
   p->timed = p->opts.timing != 0;
   p->ws = ws;
   p->stream = st;
   p->launched = true;
   p->fetched = false;
   return GZ_OK;
+}
+
+static void drop_graph(gz_plan_t p) {
+  if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  p->graph_exec = nullptr;
+  p->graph = nullptr;
+  p->graph_ws = nullptr;
+  p->graph_out.clear();
 }
 
 int gz_decompress(gz_plan_t p, void *d_out, size_t out_cap, void *d_ws, size_t ws_bytes, void *stream) {
@@ -377,6 +422,54 @@ int gz_decompress(gz_plan_t p, void *d_out, size_t out_cap, void *d_ws, size_t w
 int gz_decompress_batch(gz_plan_t p, void *d_ws, size_t ws_bytes, void *stream) {
   if (!p) return GZ_E_ARG;
   return launch(p, (uint8_t *)d_ws, ws_bytes, (hipStream_t)stream);
+}
+
+int gz_decompress_graph(gz_plan_t p, void *d_ws, size_t ws_bytes, void *stream) {
+  if (!p || !stream || p->opts.timing) return GZ_E_ARG;
+  if (!d_ws || ws_bytes < p->lay.total || ((uintptr_t)d_ws & 255u)) {
+    snprintf(g_err, sizeof(g_err), "workspace needs %llu bytes, 256-byte aligned",
+             (unsigned long long)p->lay.total);
+    return d_ws && ws_bytes < p->lay.total ? GZ_E_CAPACITY : GZ_E_ARG;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  std::vector<std::pair<uint8_t *, uint64_t>> outs;
+  for (const FileDesc &f : p->files) outs.emplace_back(f.out, f.out_cap);
+  if (!p->graph_exec || p->graph_ws != (uint8_t *)d_ws || p->graph_out != outs) {
+    drop_graph(p);
+    // the table is written once here and only read by the replays
+    if (p->upload_pending) {
+      (void)hipEventSynchronize(p->upload_done);
+      p->upload_pending = false;
+    }
+    hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "begin capture");
+    p->capturing = true;
+    const int r = launch(p, (uint8_t *)d_ws, ws_bytes, st);
+    p->capturing = false;
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(st, &g);
+    if (r != GZ_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return r;
+    }
+    if (e != hipSuccess) return hip_fail(e, "end capture");
+    p->graph = g;
+    e = hipGraphInstantiate(&p->graph_exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      drop_graph(p);
+      return hip_fail(e, "graph instantiate");
+    }
+    p->graph_ws = (uint8_t *)d_ws;
+    p->graph_out = outs;
+  }
+  hipError_t e = hipGraphLaunch(p->graph_exec, st);
+  if (e != hipSuccess) return hip_fail(e, "graph launch");
+  p->timed = false;
+  p->ws = (uint8_t *)d_ws;
+  p->stream = st;
+  p->launched = true;
+  p->fetched = false;
+  return GZ_OK;
 }
 
 static int fetch(gz_plan_t p) {
@@ -496,13 +589,14 @@ int gz_pass_times(gz_plan_t p, float *ms, int n) {
 }
 
 const char *gz_pass_name(int i) {
-  static const char *names[GZ_N_PASSES] = {"upload",   "init",     "scan",     "capacity",  "inflate",
-                                           "stitch",   "finalize", "tilescan", "propagate", "translate"};
+  static const char *names[GZ_N_PASSES] = {"upload", "init",     "scan",     "capacity",  "inflate",  "confirm",
+                                           "redo",   "stitch",   "finalize", "tilescan", "propagate", "translate"};
   return i >= 0 && i < GZ_N_PASSES ? names[i] : "";
 }
 
 void gz_plan_destroy(gz_plan_t p) {
   if (!p) return;
+  drop_graph(p);
   if (p->upload_pending) (void)hipEventSynchronize(p->upload_done);
   if (p->upload_done) (void)hipEventDestroy(p->upload_done);
   for (int i = 0; i <= GZ_N_PASSES; i++)
@@ -524,6 +618,112 @@ const char *gz_strerror(int code) {
     case GZ_E_NOT_READY: return "no decompression launched on this plan";
     default: return "unknown error";
   }
+}
+
+// Autotuner: candidate (chunk size, LDS ring) pairs timed on the caller's
+// input; the choice is cached per (device, size class, ratio class).
+namespace {
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int>, gz_opts> g_tune;
+const uint64_t k_tune_chunks[] = {64ull << 10, 128ull << 10, 256ull << 10, 512ull << 10,
+                                  1ull << 20,  2ull << 20,   4ull << 20};
+const uint32_t k_tune_rings[] = {4096, 8192, 16384};
+}  // namespace
+
+int gz_autotune(const void *d_comp, size_t comp_len, void *d_out, size_t out_cap, void *d_ws, size_t ws_bytes,
+                void *stream, gz_opts *best, uint64_t *ws_max) {
+  if (!d_comp || comp_len == 0 || !best) return GZ_E_ARG;
+  const gz_opts base = *best;
+  // candidates and the workspace the largest one needs
+  std::vector<gz_opts> cand;
+  uint64_t need = 0;
+  uint32_t isize = 0;
+  uint64_t payload = 0;
+  for (uint64_t cb : k_tune_chunks) {
+    for (uint32_t ring : k_tune_rings) {
+      gz_opts o = base;
+      o.chunk_bytes = cb;
+      o.window_syms = ring;
+      o.timing = 0;
+      gz_plan_t pl = nullptr;
+      int r = gz_plan(&pl, d_comp, comp_len, 0, &o);
+      if (r != GZ_OK) return r;
+      gz_info inf;
+      gz_plan_info(pl, &inf);
+      gz_plan_destroy(pl);
+      payload = inf.payload_end - inf.payload_start;
+      isize = inf.isize;
+      // at least two chunks, except for inputs below the smallest chunk size;
+      // chunks below 256 KiB only where they are needed for parallelism
+      // (the confirmation blocks past each chunk's stop then cost more than
+      // the chunk itself)
+      if (cb != k_tune_chunks[0] && cb * 2 > payload) continue;
+      if (cb < (256ull << 10) && payload > (64ull << 20)) continue;
+      need = std::max<uint64_t>(need, inf.ws_bytes);
+      cand.push_back(o);
+    }
+  }
+  if (ws_max) *ws_max = need;
+  if (!d_ws) return GZ_OK;  // query only
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  int size_class = 0;
+  while ((comp_len >> size_class) > 1) size_class++;
+  const int ratio_class = (int)std::min<double>(64.0, 4.0 * (double)isize / (double)std::max<uint64_t>(1, payload));
+  const auto key = std::make_tuple(dev, size_class, ratio_class);
+  {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) {
+      *best = it->second;
+      best->timing = base.timing;
+      return GZ_OK;
+    }
+  }
+  hipStream_t st = (hipStream_t)stream;
+  hipEvent_t e0, e1;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  float best_ms = -1.f;
+  int last = GZ_E_CAPACITY;
+  for (const gz_opts &o : cand) {
+    gz_plan_t pl = nullptr;
+    int r = gz_plan(&pl, d_comp, comp_len, 0, &o);
+    if (r != GZ_OK) {
+      last = r;
+      continue;
+    }
+    gz_info inf;
+    gz_plan_info(pl, &inf);
+    float ms = -1.f;
+    if (inf.ws_bytes <= ws_bytes) {
+      gz_result res;
+      r = gz_decompress(pl, d_out, out_cap, d_ws, ws_bytes, st);  // warm
+      if (r == GZ_OK) r = gz_result_get(pl, 0, &res);
+      if (r == GZ_OK && res.status == GZ_OK) {
+        (void)hipEventRecord(e0, st);
+        r = gz_decompress(pl, d_out, out_cap, d_ws, ws_bytes, st);
+        (void)hipEventRecord(e1, st);
+        if (r == GZ_OK) r = gz_result_get(pl, 0, &res);
+        if (r == GZ_OK && res.status == GZ_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) ms = -1.f;
+      } else if (r == GZ_OK) {
+        r = res.status;
+      }
+      last = r;
+    }
+    gz_plan_destroy(pl);
+    if (ms > 0.f && (best_ms < 0.f || ms < best_ms)) {
+      best_ms = ms;
+      *best = o;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (best_ms < 0.f) return last != GZ_OK ? last : GZ_E_CAPACITY;
+  best->timing = base.timing;
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  g_tune[key] = *best;
+  return GZ_OK;
 }
 
 int gz_device_info(int dev, int *n_cu, int *lds_bytes) {

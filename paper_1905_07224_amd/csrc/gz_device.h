@@ -163,21 +163,17 @@ struct WaveBits {
     refill();
     return peek();
   }
-  // 128 bits at pos as four dwords (q0 holds bits pos .. pos + 31)
-  __device__ __forceinline__ void view128(uint32_t &q0, uint32_t &q1, uint32_t &q2, uint32_t &q3) {
+  // 192 bits at pos as six dwords (q[0] holds bits pos .. pos + 31)
+  __device__ __forceinline__ void view192(uint32_t (&q)[6]) {
     refill();
     const uint64_t a = pos + 8ull * s.mis;
     const int64_t D = (int64_t)(a >> 5);
     const uint32_t sh = (uint32_t)(a & 31);
-    const uint32_t w0 = (uint32_t)__builtin_amdgcn_readlane((int)win, (int)(D & 63));
-    const uint32_t w1 = (uint32_t)__builtin_amdgcn_readlane((int)win, (int)((D + 1) & 63));
-    const uint32_t w2 = (uint32_t)__builtin_amdgcn_readlane((int)win, (int)((D + 2) & 63));
-    const uint32_t w3 = (uint32_t)__builtin_amdgcn_readlane((int)win, (int)((D + 3) & 63));
-    const uint32_t w4 = (uint32_t)__builtin_amdgcn_readlane((int)win, (int)((D + 4) & 63));
-    q0 = (uint32_t)((((uint64_t)w1 << 32) | w0) >> sh);
-    q1 = (uint32_t)((((uint64_t)w2 << 32) | w1) >> sh);
-    q2 = (uint32_t)((((uint64_t)w3 << 32) | w2) >> sh);
-    q3 = (uint32_t)((((uint64_t)w4 << 32) | w3) >> sh);
+    uint32_t w[7];
+#pragma unroll
+    for (int i = 0; i < 7; i++) w[i] = (uint32_t)__builtin_amdgcn_readlane((int)win, (int)((D + i) & 63));
+#pragma unroll
+    for (int i = 0; i < 6; i++) q[i] = (uint32_t)((((uint64_t)w[i + 1] << 32) | w[i]) >> sh);
   }
   __device__ __forceinline__ void skip(uint32_t n) { pos += n; }
   __device__ __forceinline__ bool past_end() const { return pos > s.end_bits; }
@@ -483,7 +479,7 @@ __device__ int read_dynamic_tables(WaveBits &br, TablesLDS &sh, bool strict, boo
   return D_OK;
 }
 
-__device__ void fixed_tables(TablesLDS &sh) {
+__device__ __forceinline__ void fixed_tables(TablesLDS &sh) {
   const int lane = lane_id();
   for (int s = lane; s < 288; s += 64) sh.lens[s] = (uint8_t)(s < 144 ? 8 : s < 256 ? 9 : s < 280 ? 7 : 8);
   wave_sync();
@@ -524,7 +520,7 @@ __device__ __forceinline__ bool start_stage2(const Src &s, uint64_t b, TablesLDS
 }
 
 // First candidate in [from, to) that passes the static checks, whole wave.
-__device__ uint64_t wave_find_start(const Src &s, uint64_t from, uint64_t to, TablesLDS &sh) {
+__device__ __forceinline__ uint64_t wave_find_start(const Src &s, uint64_t from, uint64_t to, TablesLDS &sh) {
   const int lane = lane_id();
   for (uint64_t b0 = from; b0 < to; b0 += 64) {
     uint64_t b = b0 + (uint64_t)lane;

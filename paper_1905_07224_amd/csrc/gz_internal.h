@@ -26,6 +26,7 @@ enum : uint32_t {
   CS_EXTENDED = 4u,     // continued past the first stop
   CS_REPAIRED = 8u,     // start replaced by the previous chunk's end
   CS_OVERFLOW = 16u,    // symbol capacity exceeded before the stop
+  CS_UNCONFIRMED = 32u, // its deferred confirmation blocks failed (redone by k_redo)
 };
 
 // device status codes (same numbers as the public GZ_E_*)
@@ -77,7 +78,15 @@ struct ChunkState {
   uint32_t n_blocks;
   uint32_t retries;
   uint32_t valid;          // real history bytes before the chunk, capped at 32768
-  uint32_t pad;
+  uint32_t pad;            // confirmation blocks owed past the stop (deferred), else 0
+};
+
+// A chunk with an accepted start, in chunk order (window propagation walks these).
+struct AccEntry {
+  uint64_t sym_off;
+  uint64_t len;            // |D_j|
+  uint32_t chunk;
+  uint32_t pad;            // 1: the first chunk of its file
 };
 
 struct FileState {
@@ -98,7 +107,9 @@ struct Counters {
   uint32_t inflate_next;   // persistent work queue head
   uint32_t stitch_next;
   uint32_t translate_next;
-  uint32_t pad[13];
+  uint32_t confirm_next;
+  uint32_t redo_next;
+  uint32_t pad[11];
 };
 
 // Workspace: offsets from the workspace base (all 256-byte aligned).
@@ -111,6 +122,9 @@ struct Layout {
   uint64_t fstate_off;     // FileState[F]
   uint64_t counters_off;   // Counters
   uint64_t tiles_off;      // uint64[N+1] translate tile prefix
+  uint64_t acc_off;        // uint32[N+1] accepted chunks before chunk j, then AccEntry[N] in chunk order
+  uint64_t maps_off;       // uint16[S][32768] propagation segment maps, S = ceil(N / 64)
+  uint64_t segwin_off;     // uint8[S][32768] input window of each propagation segment
   uint64_t win_off;        // uint8[N][32768] resolved windows
   uint64_t sym_off;        // uint16 symbol pool
   uint64_t sym_elems;

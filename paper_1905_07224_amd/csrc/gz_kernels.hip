@@ -40,6 +40,7 @@ struct DecodeResult {
   uint64_t end;      // stop bit
   uint64_t len;      // symbols up to the stop
   uint32_t blocks;
+  uint32_t pending;  // check blocks left for after the stop (deferred confirmation)
 };
 
 template <int WIN>
@@ -125,17 +126,26 @@ struct Inflater {
   // lane of this batch when >= 0, else a symbol produced before the batch.
   static constexpr int32_t REF_LIT = 0x10000;
 
-  // Resolve and store the j symbols of a batch.  Sources before the batch
-  // come from the ring, from HBM, or are the placeholders U_j before a chunk
-  // (a distance past the start of the first chunk is invalid data); sources
-  // in the batch are earlier lanes, followed by pointer jumping: a lane whose
-  // source is still open takes that lane's source, so after k rounds every
-  // chain of up to 2^k links is closed.
-  __device__ __forceinline__ int expand(int32_t ref, uint32_t j) {
+  // A batch is resolved in two steps so that its HBM reads overlap the
+  // decoding of the next one.  issue(): sources before the batch come from
+  // the ring, from HBM (loads left in flight), or are the placeholders U_j
+  // before a chunk (a distance past the start of the first chunk is invalid
+  // data); sources in the batch are earlier lanes.  finish(): pointer
+  // jumping over those (a lane whose source is still open takes that lane's
+  // source, so after k rounds every chain of up to 2^k links is closed), then
+  // the symbols go to the ring.  finish() of one batch always precedes
+  // issue() of the next, so every ring read sees all earlier symbols.
+  uint32_t pj;   // symbols of the pending batch (0: none)
+  uint32_t pval; // per lane: its symbol, or (pp != lane) not yet known
+  uint32_t plv;  // per lane: the HBM load in flight (used where pfar has the lane's bit)
+  uint64_t pfar;
+  int32_t pp;    // per lane: lane whose symbol this one copies, itself when known
+
+  __device__ __forceinline__ int issue(int32_t ref, uint32_t j) {
     const int lane = lane_id();
     const bool act = lane < (int)j;
     uint32_t val = 0;
-    int32_t p = lane;  // open lanes point at their source, closed lanes at themselves
+    int32_t p = lane;
     bool far = false, before = false;
     int64_t a = 0;
     wave_sync();
@@ -157,13 +167,30 @@ struct Inflater {
       }
     }
     if (first && __ballot(before)) return D_FAR;
-    if (WIN < 32768 && __ballot(far)) {
-      // past capacity nothing was stored: the chunk fails with a capacity
-      // status, so any value will do
-      if (far)
-        val = (uint64_t)a < cap ? (uint32_t)__hip_atomic_load(D + a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                                : 0u;
-    }
+    // every lane loads (element 0 where no HBM source is needed), so the load
+    // writes its register directly and is waited for only in finish()
+    // (past capacity nothing was stored: that chunk fails with a capacity
+    // status, so any value will do)
+    if (far && (uint64_t)a >= cap) far = false;
+    uint32_t lv = 0;
+    const uint64_t fm = WIN < 32768 ? __ballot(far) : 0ull;
+    // the aligned dword that holds the symbol (D is 4-byte aligned)
+    if (fm)
+      lv = __hip_atomic_load(reinterpret_cast<const uint32_t *>(D) + (far ? (a >> 1) : 0), __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+    pval = far ? (uint32_t)(a & 1) << 4 : val;  // far lanes: which half
+    plv = lv;
+    pfar = fm;
+    pp = p;
+    pj = j;
+    return D_OK;
+  }
+
+  __device__ __forceinline__ int finish() {
+    if (pj == 0) return D_OK;
+    const int lane = lane_id();
+    uint32_t val = (pfar >> lane) & 1ull ? (plv >> pval) & 0xFFFFu : pval;
+    int32_t p = pp;
     for (int it = 0; it < 8; it++) {
       if (__ballot(p != lane) == 0) break;
       const uint32_t vs = __shfl(val, p);
@@ -178,21 +205,25 @@ struct Inflater {
       }
     }
     if (__ballot(p != lane)) return D_BAD;  // unreachable: chains are shorter than 64
-    if (act) {
+    if (lane < (int)pj) {
       sh.ring[(pos + (uint32_t)lane) & RMASK] = (uint16_t)val;
       nph += val >> 15;
     }
-    pos += j;
+    pos += pj;
+    pj = 0;
     maybe_flush();
     return D_OK;
   }
 
+  // Output of one batch, pipelined (parse-only past the stop: counted only).
   __device__ __forceinline__ int put_batch(int32_t ref, uint32_t j) {
     if (!emit) {
       pos += j;
       return D_OK;
     }
-    return expand(ref, j);
+    const int r = finish();
+    if (r != D_OK) return r;
+    return issue(ref, j);
   }
 
   // A symbol whose code is longer than the lookup tables, decoded alone at
@@ -239,21 +270,45 @@ struct Inflater {
   static constexpr uint32_t TOK_SLOW = TOK_SPECIAL | (2u << 28);   // longer code, or invalid: decoded alone
   static constexpr uint32_t TOK_ASCII = TOK_SPECIAL | (3u << 28);  // non-ASCII literal in a checked block
 
+  // The token that would start at bit offset k of a lookup round, from the
+  // 64 stream bits at that offset (w0: bits k .. k + 31, w1: k + 32 .. k + 63).
+  template <bool CHECK>
+  __device__ __forceinline__ void token_at(uint32_t w0, uint32_t w1, uint32_t &info, int32_t &tval) const {
+    const uint32_t LMASK = (1u << LIT_BITS) - 1u, DMASK = (1u << DIST_BITS) - 1u;
+    const uint64_t w = ((uint64_t)w1 << 32) | w0;
+    const uint32_t e = sh_lit(w0 & LMASK);
+    const uint32_t kind = (e >> 4) & 15u, cl = e & 15u, ex = (e >> 8) & 15u;
+    const uint32_t u = cl + ex;
+    const uint32_t ed = sh_dist((uint32_t)(w >> u) & DMASK);
+    const uint32_t dl = ed & 15u, dex = (ed >> 8) & 15u;
+    const uint32_t len = (e >> 16) + ((w0 >> cl) & ((1u << ex) - 1u));
+    const uint32_t dist = (ed >> 16) + ((uint32_t)(w >> (u + dl)) & ((1u << dex) - 1u));
+    if ((kind & 7u) == K_LIT) {
+      info = (CHECK && kind == K_LITX) ? TOK_ASCII : (cl | (1u << 8));
+      tval = (int32_t)(REF_LIT | ((e >> 8) & 255u));
+    } else if (kind == K_LEN) {
+      info = ((ed >> 4) & 15u) == K_LEN ? (u + dl + dex) | (len << 8) : TOK_SLOW;
+      tval = -(int32_t)dist;
+    } else {
+      info = kind == K_EOB ? (TOK_EOB | cl) : TOK_SLOW;
+      tval = 0;
+    }
+  }
+
   // Huffman-coded block body until end-of-block (section 3.2.5), decoded in
-  // rounds of 64 bit offsets.  Lane k reads the 64 stream bits at offset k
-  // from br.pos and decodes the token that would start there: its
-  // literal/length code, extra length bits, distance code and extra
-  // distance bits (at most 48 bits, RFC 1951 section 3.2.5), with one lookup
-  // in each table.  The scalar walk then follows the real tokens from offset
-  // 0 (each one bit count further) while they start below offset 64, and
-  // turns them into batches of up to 64 output symbols.  CHECK: literals must
-  // be ASCII text (block-start trial and confirmation).
+  // rounds of 128 bit offsets.  Lane k reads the 64 stream bits at offsets k
+  // and k + 64 from br.pos and decodes the tokens that would start there:
+  // literal/length code, extra length bits, distance code and extra distance
+  // bits (at most 48 bits, RFC 1951 section 3.2.5), with one lookup in each
+  // table.  The scalar walk then follows the real tokens from offset 0 (each
+  // one bit count further) while they start below offset 128, and turns them
+  // into batches of up to 64 output symbols.  CHECK: literals must be ASCII
+  // text (block-start trial and confirmation).
   template <bool CHECK>
   __device__ int huffman(uint64_t size_cap, uint64_t blk0) {
     const int lane = lane_id();
-    const uint32_t LMASK = (1u << LIT_BITS) - 1u, DMASK = (1u << DIST_BITS) - 1u;
-    uint32_t info = 0;  // bits used | output symbols << 8, or a TOK_ kind
-    int32_t tval = 0;   // REF_LIT | literal, or -distance
+    uint32_t info0 = 0, info1 = 0;  // bits used | output symbols << 8, or a TOK_ kind
+    int32_t tval0 = 0, tval1 = 0;   // REF_LIT | literal, or -distance
     uint32_t off = 0;   // bit offset of the walk from br.pos, where the round was decoded
     bool need = true;   // a round to be decoded at br.pos + off
     uint32_t rem = 0, mdist = 0;  // part of a match still to be produced
@@ -264,30 +319,16 @@ struct Inflater {
       if (it > budget) return D_BAD;
       if (need) {
         br.pos += off;
-        uint32_t q0, q1, q2, q3;
-        br.view128(q0, q1, q2, q3);
+        uint32_t q[6];
+        br.view192(q);
         const bool lo_half = lane < 32;
-        const uint32_t a0 = lo_half ? q0 : q1, a1 = lo_half ? q1 : q2, a2 = lo_half ? q2 : q3;
         const uint32_t sh = (uint32_t)lane & 31u;
-        const uint32_t w0 = __builtin_amdgcn_alignbit(a1, a0, sh);
-        const uint32_t w1 = __builtin_amdgcn_alignbit(a2, a1, sh);
-        const uint64_t w = ((uint64_t)w1 << 32) | w0;
-        const uint32_t e = sh_lit(w0 & LMASK);
-        const uint32_t kind = (e >> 4) & 15u, cl = e & 15u, ex = (e >> 8) & 15u;
-        const uint32_t u = cl + ex;
-        const uint32_t ed = sh_dist((uint32_t)(w >> u) & DMASK);
-        const uint32_t dl = ed & 15u, dex = (ed >> 8) & 15u;
-        const uint32_t len = (e >> 16) + ((w0 >> cl) & ((1u << ex) - 1u));
-        const uint32_t dist = (ed >> 16) + ((uint32_t)(w >> (u + dl)) & ((1u << dex) - 1u));
-        if ((kind & 7u) == K_LIT) {
-          info = (CHECK && kind == K_LITX) ? TOK_ASCII : (cl | (1u << 8));
-          tval = (int32_t)(REF_LIT | ((e >> 8) & 255u));
-        } else if (kind == K_LEN) {
-          info = ((ed >> 4) & 15u) == K_LEN ? (u + dl + dex) | (len << 8) : TOK_SLOW;
-          tval = -(int32_t)dist;
-        } else {
-          info = kind == K_EOB ? (TOK_EOB | cl) : TOK_SLOW;
-        }
+        // offsets k (dwords 0..3) and k + 64 (dwords 2..5)
+        const uint32_t a0 = lo_half ? q[0] : q[1], a1 = lo_half ? q[1] : q[2], a2 = lo_half ? q[2] : q[3];
+        const uint32_t b2 = lo_half ? q[4] : q[5];
+        const uint32_t b0 = a2, b1 = lo_half ? q[3] : q[4];
+        token_at<CHECK>(__builtin_amdgcn_alignbit(a1, a0, sh), __builtin_amdgcn_alignbit(a2, a1, sh), info0, tval0);
+        token_at<CHECK>(__builtin_amdgcn_alignbit(b1, b0, sh), __builtin_amdgcn_alignbit(b2, b1, sh), info1, tval1);
         off = 0;
         need = false;
       }
@@ -300,10 +341,17 @@ struct Inflater {
         rem -= n;
       }
       uint32_t x = 0, ntok = 0;
-      while (j < 64u && off < 64u) {
-        x = (uint32_t)__builtin_amdgcn_readlane((int)info, (int)off);
+      while (j < 64u && off < 128u) {
+        // both halves read, one kept by a mask (straight-line code)
+        const uint32_t hm = 0u - (off >> 6);
+        const int ln = (int)(off & 63u);
+        const uint32_t x0 = (uint32_t)__builtin_amdgcn_readlane((int)info0, ln);
+        const uint32_t x1 = (uint32_t)__builtin_amdgcn_readlane((int)info1, ln);
+        x = x0 ^ ((x0 ^ x1) & hm);
         if (x & TOK_SPECIAL) break;
-        const int32_t v = __builtin_amdgcn_readlane(tval, (int)off);
+        const uint32_t v0 = (uint32_t)__builtin_amdgcn_readlane(tval0, ln);
+        const uint32_t v1 = (uint32_t)__builtin_amdgcn_readlane(tval1, ln);
+        const int32_t v = (int32_t)(v0 ^ ((v0 ^ v1) & hm));
         const uint32_t len = x >> 8;
         const uint32_t n = min(len, 64u - j);
         const int32_t add = v < 0 ? lane : 0;
@@ -325,6 +373,8 @@ struct Inflater {
         if ((x & ~255u) == TOK_EOB) {
           nsyms++;
           br.pos += off + (x & 255u);
+          const int r = finish();
+          if (r != D_OK) return r;
           return br.past_end() ? D_TRUNC : D_OK;
         }
         // TOK_SLOW: one symbol decoded alone, then a new round
@@ -334,7 +384,7 @@ struct Inflater {
         uint32_t c = 0, len = 0, dist = 0;
         const int r = slow_symbol(CHECK, &c, &len, &dist);
         if (r != D_OK) return r;
-        if (len == 0xFFFFFFFFu) return D_OK;
+        if (len == 0xFFFFFFFFu) return finish();
         if (len == 0) {
           const int r2 = put_batch(lane == 0 ? (int32_t)(REF_LIT | c) : 0, 1u);
           if (r2 != D_OK) return r2;
@@ -342,7 +392,7 @@ struct Inflater {
           rem = len;
           mdist = dist;
         }
-      } else if (off >= 64u) {
+      } else if (off >= 128u) {
         need = true;
       }
       if (br.pos + off > br.s.end_bits) return D_TRUNC;
@@ -353,7 +403,7 @@ struct Inflater {
   // One block.  check: ASCII literals (block-start confirmation); strict: the
   // candidate block itself (must be a non-final dynamic block with a complete
   // literal/length code and a size in (1 KiB, 4 MiB)).
-  __device__ int block(bool check, bool strict, bool *final_out) {
+  __device__ __forceinline__ int block(bool check, bool strict, bool *final_out) {
     const uint64_t v = br.next();
     const uint32_t bfinal = (uint32_t)(v & 1u), btype = (uint32_t)((v >> 1) & 3u);
     br.skip(3);
@@ -388,8 +438,12 @@ struct Inflater {
   // Decode whole blocks from bit `start`, with `pos` symbols already produced,
   // until the first block header at or past `stop` (or a final block).  The
   // first `check_blocks` blocks are the block-start trial and confirmation; if
-  // the stop comes first they are still decoded, then the stop is reported.
-  __device__ DecodeResult run(uint64_t start, uint64_t stop, uint32_t check_blocks) {
+  // the stop comes first they are still decoded (parsed and checked, not
+  // stored), then the stop is reported -- unless `defer`: then decoding ends
+  // at the stop and the check blocks still owed are returned in `pending`
+  // (the blocks after the stop are the next chunks' first blocks, which
+  // those chunks decode with the same checks).
+  __device__ __forceinline__ DecodeResult run(uint64_t start, uint64_t stop, uint32_t check_blocks, bool defer = false) {
     DecodeResult res;
     res.status = D_OK;
     res.confirmed = check_blocks == 0;
@@ -397,6 +451,7 @@ struct Inflater {
     res.end = NONE;
     res.len = 0;
     res.blocks = 0;
+    res.pending = 0;
     br.init(start);
     uint32_t nb = 0;
     // a block header is at least 3 bits: the remaining bits bound the blocks
@@ -410,6 +465,10 @@ struct Inflater {
         res.end = br.pos;
         res.len = pos;
         nph_stop = nph;
+        if (defer) {
+          res.pending = nb < check_blocks ? check_blocks - nb : 0u;
+          break;
+        }
         // the confirmation blocks still to come are not part of this chunk:
         // their symbols are checked and counted but not stored
         flush_all();
@@ -441,6 +500,22 @@ struct Inflater {
     if (emit) flush_all();
     return res;
   }
+
+  // Confirmation blocks decoded on their own: `need` blocks from bit `start`
+  // with the checks of the confirmation (ASCII literals; the trial block's
+  // stricter rules do not apply), parsed only; a final block ends them.
+  __device__ int confirm(uint64_t start, uint32_t need) {
+    emit = false;
+    first = false;
+    br.init(start);
+    for (uint32_t nb = 0; nb < need; nb++) {
+      bool fin = false;
+      const int r = block(true, false, &fin);
+      if (r != D_OK) return r;
+      if (fin) break;
+    }
+    return D_OK;
+  }
 };
 
 template <int WIN>
@@ -457,6 +532,7 @@ __device__ __forceinline__ void inflater_setup(Inflater<WIN> &inf, const FileDes
   inf.first = (cd.flags & CF_FIRST) != 0;
   inf.over = false;
   inf.emit = true;
+  inf.pj = 0;
 }
 
 // Next chunk of the same file that has a start (scan candidate or accepted).
@@ -480,9 +556,12 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
 }
 
 // Decode chunk c from scratch (pass 1 for one chunk).
+// defer: confirmation blocks past the stop are left to k_confirm.  from:
+// NONE to start at the scan candidate, else the first bit to search a
+// candidate from (a candidate rejected by k_confirm is redone from the next).
 template <int WIN>
-__device__ void inflate_chunk(InflateLDS<WIN> &sh, const FileDesc *files, const ChunkDesc *chunks, ChunkState *cs,
-                              uint16_t *pool, uint32_t c) {
+__device__ __forceinline__ void inflate_chunk(InflateLDS<WIN> &sh, const FileDesc *files, const ChunkDesc *chunks, ChunkState *cs,
+                              uint16_t *pool, uint32_t c, bool defer, uint64_t from) {
   const int lane = lane_id();
   const ChunkDesc cd = chunks[c];
   const FileDesc fd = files[cd.file];
@@ -490,10 +569,19 @@ __device__ void inflate_chunk(InflateLDS<WIN> &sh, const FileDesc *files, const 
   uint64_t b = first ? fd.payload_bit : uni64(cs[c].cand);
   const uint64_t stop = first || b != NONE ? uni64(next_start(fd, cs, c, false, nullptr)) : NONE;
   Inflater<WIN> inf(sh);
+  // search the next candidate from `search` at the top of an attempt (one
+  // call site of the search, for code size)
+  uint64_t search = !first && from != NONE ? from : NONE;
   uint32_t retries = 0;
   // each retry moves the candidate forward by at least one bit
   const uint64_t max_tries = cd.hi_bit - cd.lo_bit + 2;
   for (uint64_t tries = 0;; tries++) {
+    if (search != NONE) {
+      Src src;
+      src.init(fd.comp, fd.comp_len);
+      b = wave_find_start(src, search, cd.hi_bit, sh.t);
+      search = NONE;
+    }
     if (tries > max_tries) b = NONE;
     if (b == NONE || (!first && b >= cd.hi_bit)) {
       if (lane == 0) {
@@ -503,11 +591,12 @@ __device__ void inflate_chunk(InflateLDS<WIN> &sh, const FileDesc *files, const 
         cs[c].flags = CS_EMPTY;
         cs[c].retries = retries;
         cs[c].status = ST_OK;
+        cs[c].pad = 0;
       }
       return;
     }
     inflater_setup(inf, fd, cd, pool);
-    DecodeResult r = inf.run(b, stop, first ? 0u : 6u);
+    DecodeResult r = inf.run(b, stop, first ? 0u : 6u, defer);
     if (r.status != D_OK && (first || r.blocks >= 6u)) {
       if (lane == 0) {
         cs[c].start = b;
@@ -516,6 +605,7 @@ __device__ void inflate_chunk(InflateLDS<WIN> &sh, const FileDesc *files, const 
         cs[c].status = ST_DATA;
         cs[c].flags = 0;
         cs[c].retries = retries;
+        cs[c].pad = 0;
       }
       return;
     }
@@ -533,12 +623,13 @@ __device__ void inflate_chunk(InflateLDS<WIN> &sh, const FileDesc *files, const 
         cs[c].n_syms = inf.nsyms;
         cs[c].n_placeholders = ph;
         cs[c].retries = retries;
+        cs[c].pad = r.pending;
       }
       return;
     }
     // the candidate failed the trial decode or the confirmation: next one
     retries++;
-    b = wave_find_start(inf.br.s, b + 1, cd.hi_bit, sh.t);
+    search = b + 1;
   }
 }
 
@@ -694,7 +785,79 @@ __global__ __launch_bounds__(64) void k_inflate(const FileDesc *files, const Chu
     if (lane_id() == 0) item = atomicAdd(&ctr->inflate_next, 1u);
     item = uni(item);
     if (item >= n) break;
-    inflate_chunk<WIN>(sh, files, chunks, cs, pool, order[item]);
+    inflate_chunk<WIN>(sh, files, chunks, cs, pool, order[item], true, NONE);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// k_confirm: a chunk that reached its stop before its trial block and 5
+// confirmation blocks were all decoded (Appendix A) still owes the rest,
+// which are the blocks after its end.  When the next accepted chunk starts
+// exactly there and decoded them with the same checks, they are confirmed
+// (its first blocks are checked as its own trial and confirmation; the
+// trial's rules are stricter, and nothing checked depends on the history
+// before the blocks); the chain is followed while it keeps starting where the
+// last one ended.  Otherwise the owed blocks are decoded on their own,
+// parsed only.  A failure marks the chunk for k_redo.  Reads only what
+// k_inflate wrote (plus its own flag).
+// ---------------------------------------------------------------------------
+
+template <int WIN>
+__global__ __launch_bounds__(64) void k_confirm(const FileDesc *files, const ChunkDesc *chunks, ChunkState *cs,
+                                                uint32_t n, Counters *ctr, uint16_t *pool, uint32_t always_decode) {
+  __shared__ InflateLDS<WIN> sh;
+  for (uint32_t it = 0; it <= n; it++) {
+    uint32_t c = 0;
+    if (lane_id() == 0) c = atomicAdd(&ctr->confirm_next, 1u);
+    c = uni(c);
+    if (c >= n) break;
+    const uint32_t need0 = uni(cs[c].pad);
+    if (need0 == 0 || uni64(cs[c].start) == NONE || uni(cs[c].status) != ST_OK) continue;
+    const ChunkDesc cd = chunks[c];
+    const FileDesc fd = files[cd.file];
+    const uint32_t c1 = fd.first_chunk + fd.n_chunks;
+    uint32_t need = need0;
+    uint64_t at = uni64(cs[c].end);
+    uint32_t x = c;
+    bool ok = false;
+    for (uint32_t g = 0; g < fd.n_chunks && !ok && !always_decode; g++) {
+      uint32_t xn = x + 1;
+      for (uint32_t h = 0; h < fd.n_chunks && xn < c1 && uni64(cs[xn].start) == NONE; h++) xn++;
+      if (xn >= c1 || uni64(cs[xn].start) != at || uni(cs[xn].status) != ST_OK) break;
+      const uint32_t kx = uni(cs[xn].n_blocks);
+      if ((uni(cs[xn].flags) & CS_FINAL) || kx >= need) {
+        ok = true;
+        break;
+      }
+      need -= kx;
+      at = uni64(cs[xn].end);
+      x = xn;
+    }
+    if (!ok) {
+      Inflater<WIN> inf(sh);
+      inflater_setup(inf, fd, cd, pool);
+      ok = inf.confirm(at, need) == D_OK;
+    }
+    if (!ok && lane_id() == 0) cs[c].flags |= CS_UNCONFIRMED;
+  }
+}
+
+// k_redo: a chunk whose candidate failed its deferred confirmation searches
+// the next candidate and decodes it with the whole confirmation.
+template <int WIN>
+__global__ __launch_bounds__(64) void k_redo(const FileDesc *files, const ChunkDesc *chunks, ChunkState *cs, uint32_t n,
+                                             Counters *ctr, uint16_t *pool) {
+  __shared__ InflateLDS<WIN> sh;
+  for (uint32_t it = 0; it <= n; it++) {
+    uint32_t c = 0;
+    if (lane_id() == 0) c = atomicAdd(&ctr->redo_next, 1u);
+    c = uni(c);
+    if (c >= n) break;
+    if (!(uni(cs[c].flags) & CS_UNCONFIRMED)) continue;
+    const uint64_t s0 = uni64(cs[c].start);
+    const uint32_t r0 = uni(cs[c].retries);
+    inflate_chunk<WIN>(sh, files, chunks, cs, pool, c, false, s0 + 1);
+    if (lane_id() == 0) cs[c].retries += r0 + 1;
   }
 }
 
@@ -965,70 +1128,145 @@ __global__ __launch_bounds__(256) void k_finalize(const FileDesc *files, const C
 }
 
 // ---------------------------------------------------------------------------
-// k_propagate: one workgroup per file walks the accepted chunks in order.
-// w_next[k] = t < 256 ? t : w[t & 0x7FFF], t = symbol k of the last 32768
-// of (w_hat_i ++ D_i); the first chunk's window is unknown (zero).
+// Window propagation (pass 2a).  The window of the next accepted chunk is
+// w_next[k] = t < 256 ? t : w[t & 0x7FFF], t = symbol k of the last 32768 of
+// (w_hat_i ++ D_i); a file's first chunk has no history (its window, unused,
+// is zero).  The chain over all accepted chunks (the compacted list of the
+// size scan, files one after another) is cut into segments of PSEG chunks:
+//   k_prop_maps   each segment composes its steps into one map from its input
+//                 window to the next segment's (16-bit entries: a byte, or
+//                 0x8000 | position in the input window), all segments at once
+//   k_prop_chain  one workgroup applies the maps in order: every segment's
+//                 input window
+//   k_prop_apply  each segment runs its steps from its input window and
+//                 stores every chunk's window
+// so the sequential part is one step per segment, not per chunk.
+// Each step: every thread gathers 32 of the 32768 entries into registers,
+// then (after a barrier) writes them; the next chunk's tail is loaded while
+// the current one is resolved.
 // ---------------------------------------------------------------------------
 
-// The chain is sequential, so its cost is the latency of one step: each
-// thread holds 32 of the 32768 tail symbols of the chunk being resolved in
-// registers and loads the next chunk's while this one goes through LDS.
 constexpr int PROP_THREADS = 1024;
 constexpr int PROP_PER = WINDOW / PROP_THREADS;
+constexpr uint32_t PSEG = 64;
 
-__device__ __forceinline__ uint32_t next_accepted(const ChunkState *cs, uint32_t j, uint32_t c1) {
-  for (uint32_t g = 0; j < c1 && g < c1 && cs[j].start == NONE; g++) j++;
-  return j;
-}
-
-// symbols k = i * PROP_THREADS + tid of the last 32768 of (w_hat ++ D_j)
+// symbols k = i * PROP_THREADS + tid of the last 32768 of (w_hat ++ D_j),
+// two 16-bit symbols per register (i even: low half)
 __device__ __forceinline__ void load_tail(const uint16_t *__restrict__ Dj, uint64_t L, int tid,
-                                          uint32_t (&t)[PROP_PER]) {
+                                          uint32_t (&t)[PROP_PER / 2]) {
 #pragma unroll
   for (int i = 0; i < PROP_PER; i++) {
     const uint64_t q = L + (uint64_t)(i * PROP_THREADS + tid);
-    t[i] = q < WINDOW ? (0x8000u | (uint32_t)q) : (uint32_t)Dj[q - WINDOW];
+    const uint32_t x = q < WINDOW ? (0x8000u | (uint32_t)q) : (uint32_t)Dj[q - WINDOW];
+    if (i & 1) t[i >> 1] |= x << 16;
+    else t[i >> 1] = x;
   }
 }
 
-__global__ __launch_bounds__(PROP_THREADS) void k_propagate(const FileDesc *files, const ChunkDesc *chunks,
-                                                            const ChunkState *cs, const FileState *fs,
-                                                            uint8_t *__restrict__ wins,
-                                                            const uint16_t *__restrict__ pool) {
-  __shared__ uint8_t wbuf[2][WINDOW];
-  const uint32_t f = blockIdx.x;
-  const FileDesc fd = files[f];
-  if (fs[f].status != ST_OK) return;
+// One segment's steps over list positions q0 .. q1 - 1: T is uint16_t for
+// maps (k_prop_maps, `to_end`: the last step gives the window of position q1,
+// the next segment's first) or uint8_t for windows (k_prop_apply: windows of
+// q0 (store_first) .. q1 - 1 go to `wins`; position q1 may not exist).  `buf`
+// holds the window of position q0 on entry.
+template <typename T>
+__device__ __forceinline__ void prop_steps(T *buf, const AccEntry *acc, const uint16_t *__restrict__ pool, uint32_t q0,
+                                           uint32_t q1, uint8_t *__restrict__ wins, bool store_first, bool to_end) {
   const int tid = (int)threadIdx.x;
-  const uint32_t c0 = fd.first_chunk, c1 = fd.first_chunk + fd.n_chunks;
-  for (int k = tid; k < (int)WINDOW; k += PROP_THREADS) wbuf[0][k] = 0;
-  uint32_t j = next_accepted(cs, c0, c1);
-  if (j >= c1) return;
-  uint32_t t[PROP_PER], tn[PROP_PER];
-  load_tail(pool + chunks[j].sym_off, cs[j].len, tid, t);
-  __syncthreads();
-  int cur = 0;
-  for (uint32_t step = 0; step < fd.n_chunks; step++) {
-    const uint32_t jn = next_accepted(cs, j + 1, c1);
-    if (jn >= c1) break;
-    // the chunk after jn, whose tail is loaded while jn's window is resolved
-    const uint32_t jnn = next_accepted(cs, jn + 1, c1);
-    if (jnn < c1) load_tail(pool + chunks[jn].sym_off, cs[jn].len, tid, tn);
-    uint8_t *wo = wins + (uint64_t)jn * WINDOW;
+  uint32_t t[PROP_PER / 2], tn[PROP_PER / 2];
+  AccEntry e0 = acc[q0];
+  if (store_first && wins && !(e0.pad & 1u)) {
+    uint8_t *wo = wins + (uint64_t)e0.chunk * WINDOW;
+    for (int k = tid; k < (int)WINDOW; k += PROP_THREADS) wo[k] = (uint8_t)buf[k];
+  }
+  load_tail(pool + e0.sym_off, e0.len, tid, t);
+  AccEntry e1 = q0 + 1 < q1 ? acc[q0 + 1] : e0;
+  const uint32_t qend = to_end ? q1 : q1 - 1;
+  for (uint32_t q = q0; q < qend; q++) {
+    // window of position q + 1 from the tail of q (the next tail is loaded meanwhile)
+    const bool have_next = q + 1 < q1;
+    AccEntry e2 = e1;
+    if (have_next) {
+      if (q + 2 < q1) e2 = acc[q + 2];
+      load_tail(pool + e1.sym_off, e1.len, tid, tn);
+    }
+    // a file's first chunk starts without history
+    const bool reset = (q + 1 < q1 ? e1.pad : acc[q + 1].pad) & 1u;
+    uint32_t v[PROP_PER / 2];  // two results per register
 #pragma unroll
     for (int i = 0; i < PROP_PER; i++) {
-      const int k = i * PROP_THREADS + tid;
-      const uint32_t x = t[i];
-      const uint8_t b = x < 256u ? (uint8_t)x : wbuf[cur][x & 0x7FFFu];
-      wbuf[cur ^ 1][k] = b;
-      wo[k] = b;
+      const uint32_t x = (t[i >> 1] >> (16 * (i & 1))) & 0xFFFFu;
+      const uint32_t y = reset ? 0u : x < 256u ? x : (uint32_t)buf[x & 0x7FFFu];
+      if (i & 1) v[i >> 1] |= y << 16;
+      else v[i >> 1] = y;
     }
     __syncthreads();
-    cur ^= 1;
-    j = jn;
 #pragma unroll
-    for (int i = 0; i < PROP_PER; i++) t[i] = tn[i];
+    for (int i = 0; i < PROP_PER; i++) buf[i * PROP_THREADS + tid] = (T)(v[i >> 1] >> (16 * (i & 1)));
+    if (wins && have_next && !reset) {
+      uint8_t *wo = wins + (uint64_t)e1.chunk * WINDOW;
+#pragma unroll
+      for (int i = 0; i < PROP_PER; i++) wo[i * PROP_THREADS + tid] = (uint8_t)(v[i >> 1] >> (16 * (i & 1)));
+    }
+    __syncthreads();
+    e1 = e2;
+#pragma unroll
+    for (int i = 0; i < PROP_PER / 2; i++) t[i] = tn[i];
   }
+}
+
+__global__ __launch_bounds__(PROP_THREADS) void k_prop_maps(const uint32_t *acc_pos, uint32_t n, const AccEntry *acc,
+                                                            const uint16_t *__restrict__ pool, uint16_t *maps) {
+  __shared__ uint16_t m[WINDOW];
+  const uint32_t A = acc_pos[n], g = blockIdx.x;
+  const uint32_t q0 = g * PSEG;
+  if (q0 + PSEG >= A) return;  // the last segment has no successor
+  for (int k = threadIdx.x; k < (int)WINDOW; k += PROP_THREADS) m[k] = (uint16_t)(0x8000u | (uint32_t)k);
+  __syncthreads();
+  // map from the window of q0 to the window of q0 + PSEG
+  prop_steps<uint16_t>(m, acc, pool, q0, q0 + PSEG, nullptr, false, true);
+  uint16_t *mo = maps + (uint64_t)g * WINDOW;
+  for (int k = threadIdx.x; k < (int)WINDOW; k += PROP_THREADS) mo[k] = m[k];
+}
+
+__global__ __launch_bounds__(PROP_THREADS) void k_prop_chain(const uint32_t *acc_pos, uint32_t n,
+                                                             const uint16_t *__restrict__ maps,
+                                                             uint8_t *__restrict__ segwin) {
+  __shared__ uint8_t w[WINDOW];
+  const uint32_t A = acc_pos[n];
+  const int tid = (int)threadIdx.x;
+  for (int k = tid; k < (int)WINDOW; k += PROP_THREADS) w[k] = 0;
+  __syncthreads();
+  const uint32_t S = (A + PSEG - 1) / PSEG;
+  for (uint32_t g = 0; g < S; g++) {
+    uint8_t *wo = segwin + (uint64_t)g * WINDOW;
+    for (int k = tid; k < (int)WINDOW; k += PROP_THREADS) wo[k] = w[k];
+    if (g + 1 == S) break;
+    const uint16_t *mg = maps + (uint64_t)g * WINDOW;
+    uint32_t v[PROP_PER];
+#pragma unroll
+    for (int i = 0; i < PROP_PER; i++) {
+      const uint32_t x = mg[i * PROP_THREADS + tid];
+      v[i] = x < 256u ? x : (uint32_t)w[x & 0x7FFFu];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < PROP_PER; i++) w[i * PROP_THREADS + tid] = (uint8_t)v[i];
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(PROP_THREADS) void k_prop_apply(const uint32_t *acc_pos, uint32_t n, const AccEntry *acc,
+                                                             const uint16_t *__restrict__ pool,
+                                                             const uint8_t *__restrict__ segwin,
+                                                             uint8_t *__restrict__ wins) {
+  __shared__ uint8_t w[WINDOW];
+  const uint32_t A = acc_pos[n], g = blockIdx.x;
+  const uint32_t q0 = g * PSEG;
+  if (q0 >= A) return;
+  const uint8_t *wi = segwin + (uint64_t)g * WINDOW;
+  for (int k = threadIdx.x; k < (int)WINDOW; k += PROP_THREADS) w[k] = wi[k];
+  __syncthreads();
+  prop_steps<uint8_t>(w, acc, pool, q0, min(q0 + PSEG, A), wins, true, false);
 }
 
 // ---------------------------------------------------------------------------
@@ -1037,28 +1275,54 @@ __global__ __launch_bounds__(PROP_THREADS) void k_propagate(const FileDesc *file
 // ---------------------------------------------------------------------------
 
 __global__ __launch_bounds__(1024) void k_tilescan(const ChunkDesc *chunks, const ChunkState *cs, const FileState *fs,
-                                                   uint32_t n, uint64_t *tiles) {
+                                                   uint32_t n, uint64_t *tiles, uint32_t *acc_pos, AccEntry *acc) {
   __shared__ uint64_t part[1024];
+  __shared__ uint32_t apart[1024];
   const int tid = (int)threadIdx.x;
   uint64_t carry = 0;
+  uint32_t acarry = 0;
   for (uint32_t base = 0; base < n; base += 1024) {
     const uint32_t j = base + (uint32_t)tid;
     uint64_t T = 0;
-    if (j < n && cs[j].start != NONE && fs[chunks[j].file].status == ST_OK)
-      T = (cs[j].len + TRANSLATE_TILE - 1) / TRANSLATE_TILE;
+    uint32_t A = 0;
+    if (j < n && cs[j].start != NONE) {
+      A = 1;
+      if (fs[chunks[j].file].status == ST_OK) T = (cs[j].len + TRANSLATE_TILE - 1) / TRANSLATE_TILE;
+    }
     part[tid] = T;
+    apart[tid] = A;
     __syncthreads();
     for (int o = 1; o < 1024; o <<= 1) {
       uint64_t a = tid >= o ? part[tid - o] : 0;
+      uint32_t b = tid >= o ? apart[tid - o] : 0;
       __syncthreads();
       part[tid] += a;
+      apart[tid] += b;
       __syncthreads();
     }
-    if (j < n) tiles[j] = carry + part[tid] - T;
+    if (j < n) {
+      tiles[j] = carry + part[tid] - T;
+      const uint32_t ap = acarry + apart[tid] - A;
+      acc_pos[j] = ap;
+      if (A) {
+        AccEntry e;
+        e.sym_off = chunks[j].sym_off;
+        // a file that failed is not translated: its chunks' symbols are not
+        // read (their length may exceed what was stored)
+        e.len = fs[chunks[j].file].status == ST_OK ? cs[j].len : 0;
+        e.chunk = j;
+        e.pad = (chunks[j].flags & CF_FIRST) ? 1u : 0u;  // the chain restarts at a file's first chunk
+        acc[ap] = e;
+      }
+    }
     carry += part[1023];
+    acarry += apart[1023];
     __syncthreads();
   }
-  if (tid == 0) tiles[n] = carry;
+  if (tid == 0) {
+    tiles[n] = carry;
+    acc_pos[n] = acarry;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1178,6 +1442,19 @@ hipError_t gzk_inflate(int win, uint32_t grid, const FileDesc *files, const Chun
   return hipGetLastError();
 }
 
+hipError_t gzk_confirm(int win, uint32_t grid, const FileDesc *files, const ChunkDesc *chunks, ChunkState *cs,
+                       uint32_t n, Counters *ctr, uint16_t *pool, uint32_t always_decode, hipStream_t st) {
+  GZ_WIN_SWITCH(win, hipLaunchKernelGGL(k_confirm<W>, dim3(grid), dim3(64), 0, st, files, chunks, cs, n, ctr, pool,
+                                        always_decode));
+  return hipGetLastError();
+}
+
+hipError_t gzk_redo(int win, uint32_t grid, const FileDesc *files, const ChunkDesc *chunks, ChunkState *cs, uint32_t n,
+                    Counters *ctr, uint16_t *pool, hipStream_t st) {
+  GZ_WIN_SWITCH(win, hipLaunchKernelGGL(k_redo<W>, dim3(grid), dim3(64), 0, st, files, chunks, cs, n, ctr, pool));
+  return hipGetLastError();
+}
+
 hipError_t gzk_stitch(int win, uint32_t grid, const FileDesc *files, const ChunkDesc *chunks, ChunkState *cs,
                       uint32_t n, Counters *ctr, uint16_t *pool, hipStream_t st) {
   GZ_WIN_SWITCH(win, hipLaunchKernelGGL(k_stitch<W>, dim3(grid), dim3(64), 0, st, files, chunks, cs, n, ctr, pool));
@@ -1191,14 +1468,20 @@ hipError_t gzk_finalize(int win, uint32_t n_files, const FileDesc *files, const 
 }
 
 hipError_t gzk_tilescan(const ChunkDesc *chunks, const ChunkState *cs, const FileState *fs, uint32_t n, uint64_t *tiles,
-                        hipStream_t st) {
-  hipLaunchKernelGGL(k_tilescan, dim3(1), dim3(1024), 0, st, chunks, cs, fs, n, tiles);
+                        uint32_t *acc_pos, AccEntry *acc, hipStream_t st) {
+  hipLaunchKernelGGL(k_tilescan, dim3(1), dim3(1024), 0, st, chunks, cs, fs, n, tiles, acc_pos, acc);
   return hipGetLastError();
 }
 
-hipError_t gzk_propagate(uint32_t n_files, const FileDesc *files, const ChunkDesc *chunks, const ChunkState *cs,
-                         const FileState *fs, uint8_t *wins, const uint16_t *pool, hipStream_t st) {
-  hipLaunchKernelGGL(k_propagate, dim3(n_files), dim3(PROP_THREADS), 0, st, files, chunks, cs, fs, wins, pool);
+hipError_t gzk_propagate(uint32_t n, const uint32_t *acc_pos, const AccEntry *acc, uint8_t *wins, const uint16_t *pool,
+                         uint16_t *maps, uint8_t *segwin, hipStream_t st) {
+  const uint32_t smax = (n + PSEG - 1) / PSEG;
+  hipLaunchKernelGGL(k_prop_maps, dim3(smax), dim3(PROP_THREADS), 0, st, acc_pos, n, acc, pool, maps);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_prop_chain, dim3(1), dim3(PROP_THREADS), 0, st, acc_pos, n, maps, segwin);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_prop_apply, dim3(smax), dim3(PROP_THREADS), 0, st, acc_pos, n, acc, pool, segwin, wins);
   return hipGetLastError();
 }
 

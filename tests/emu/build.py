@@ -11,7 +11,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(os.path.dirname(HERE))
 CSRC = os.path.join(ROOT, "paper_1905_07224_amd", "csrc")
 LIB = os.path.join(HERE, "libgzemu.so")
-SRCS = [os.path.join(CSRC, "gz_kernels.hip"), os.path.join(CSRC, "gz_api.cpp"), os.path.join(HERE, "emu_rt.cpp")]
+SRCS = [os.path.join(CSRC, "gz_kernels.hip"), os.path.join(CSRC, "gz_api.cpp"), os.path.join(CSRC, "gz_serve.cpp"),
+        os.path.join(HERE, "emu_rt.cpp")]
 CXX = "/opt/rocm/lib/llvm/bin/clang++" if os.path.exists("/opt/rocm/lib/llvm/bin/clang++") else "clang++"
 
 

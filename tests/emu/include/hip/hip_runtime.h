@@ -34,6 +34,10 @@ typedef int hipError_t;
 enum { hipSuccess = 0, hipErrorInvalidValue = 1, hipErrorNotReady = 600 };
 typedef void *hipStream_t;
 typedef void *hipEvent_t;
+typedef void *hipGraph_t;
+typedef void *hipGraphExec_t;
+enum { hipStreamCaptureModeGlobal = 0, hipStreamCaptureModeThreadLocal = 1, hipStreamCaptureModeRelaxed = 2 };
+enum { hipErrorNotSupported = 801 };
 enum hipMemcpyKind { hipMemcpyHostToDevice, hipMemcpyDeviceToHost, hipMemcpyDeviceToDevice, hipMemcpyHostToHost };
 #define hipHostMallocDefault 0
 #define hipEventDisableTiming 0
@@ -164,3 +168,34 @@ static inline hipError_t hipGetDeviceProperties(hipDeviceProp_t *p, int) {
 }
 static inline const char *hipGetErrorString(hipError_t) { return "emulated"; }
 static inline hipError_t hipGetLastError() { return hipSuccess; }
+
+// graphs are not emulated: capture fails, so the graph entry point reports it
+static inline hipError_t hipStreamBeginCapture(hipStream_t, int) { return hipErrorNotSupported; }
+static inline hipError_t hipStreamEndCapture(hipStream_t, hipGraph_t *g) {
+  *g = nullptr;
+  return hipErrorNotSupported;
+}
+static inline hipError_t hipGraphInstantiate(hipGraphExec_t *, hipGraph_t, void *, char *, size_t) {
+  return hipErrorNotSupported;
+}
+static inline hipError_t hipGraphLaunch(hipGraphExec_t, hipStream_t) { return hipErrorNotSupported; }
+static inline hipError_t hipGraphDestroy(hipGraph_t) { return hipSuccess; }
+static inline hipError_t hipGraphExecDestroy(hipGraphExec_t) { return hipSuccess; }
+
+// streams and events of the serving loop: work runs synchronously at launch,
+// so every stream is idle and every event has passed
+#define hipStreamNonBlocking 1
+static inline hipError_t hipStreamCreateWithFlags(hipStream_t *s, unsigned) {
+  *s = (void *)1;
+  return hipSuccess;
+}
+static inline hipError_t hipStreamDestroy(hipStream_t) { return hipSuccess; }
+static inline hipError_t hipEventQuery(hipEvent_t) { return hipSuccess; }
+static inline hipError_t hipMalloc(void **p, size_t n) {
+  *p = aligned_alloc(256, (n + 255) / 256 * 256);
+  return *p ? hipSuccess : hipErrorInvalidValue;
+}
+static inline hipError_t hipFree(void *p) {
+  free(p);
+  return hipSuccess;
+}

@@ -15,7 +15,7 @@ if ROOT not in sys.path:
 class Opts(C.Structure):
     _fields_ = [("chunk_bytes", C.c_uint64), ("sym_factor", C.c_uint32), ("window_syms", C.c_uint32),
                 ("scan_groups", C.c_uint32), ("inflate_waves_per_cu", C.c_uint32), ("waves_per_chunk", C.c_uint32),
-                ("timing", C.c_uint32), ("reserved", C.c_uint32 * 6)]
+                ("timing", C.c_uint32), ("confirm_decode", C.c_uint32), ("reserved", C.c_uint32 * 5)]
 
 
 class Info(C.Structure):
@@ -91,3 +91,38 @@ def run(comp: bytes, n_chunks: int, out_cap=None, sync_limit=0, **opts):
     tab["status"], tab["flags"] = sts, fl
     L.gz_plan_destroy(h)
     return r.status, out[: r.out_len].tobytes(), r, tab
+
+
+class ServerOpts(C.Structure):
+    _fields_ = [("budget_bytes", C.c_uint64), ("max_inflight", C.c_uint32), ("max_batch", C.c_uint32),
+                ("opts", Opts)]
+
+
+class Done(C.Structure):
+    _fields_ = [("tag", C.c_uint64), ("status", C.c_int32), ("pad", C.c_uint32), ("out_len", C.c_uint64),
+                ("t_submit", C.c_double), ("t_start", C.c_double), ("t_end", C.c_double)]
+
+
+class ServerInfo(C.Structure):
+    _fields_ = [("queued", C.c_uint32), ("running", C.c_uint32), ("finished_unread", C.c_uint32),
+                ("pad", C.c_uint32), ("batches", C.c_uint64), ("arena_bytes", C.c_uint64),
+                ("arena_used", C.c_uint64), ("arena_peak", C.c_uint64), ("now", C.c_double)]
+
+
+def server_lib():
+    L = lib()
+    vp = C.c_void_p
+    L.gz_server_create.argtypes = [C.POINTER(vp), C.POINTER(ServerOpts)]
+    L.gz_server_submit.argtypes = [vp, vp, C.c_size_t, vp, C.c_size_t, C.c_uint64]
+    L.gz_server_poll.argtypes = [vp, C.POINTER(Done), C.c_int]
+    L.gz_server_stats.argtypes = [vp, C.POINTER(ServerInfo)]
+    L.gz_server_destroy.argtypes = [vp]
+    L.gz_server_destroy.restype = None
+    return L
+
+
+def padded(comp: bytes):
+    """Host copy of a compressed input, padded so whole-dword reads stay inside."""
+    store = np.zeros(len(comp) + (-len(comp)) % 8 + 8, dtype=np.uint8)
+    store[: len(comp)] = np.frombuffer(bytes(comp), dtype=np.uint8)
+    return store

@@ -60,7 +60,7 @@ def test_struct_sizes_match_header(libpath):
     import paper_1905_07224_amd as gz
 
     # field layout of the public structs, as the C compiler sees it
-    assert ctypes.sizeof(gz.Opts) == 8 + 4 * 6 + 4 * 6
+    assert ctypes.sizeof(gz.Opts) == 8 + 4 * 7 + 4 * 5
     assert ctypes.sizeof(gz.Job) == 8 + 8 + 4 + 4 + 8 + 8
     assert ctypes.sizeof(gz.Info) == 8 * 3 + 4 * 4
     assert ctypes.sizeof(gz.Result) == 4 + 4 + 8 * 3 + 4 * 4 + 8 * 3

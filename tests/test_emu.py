@@ -106,3 +106,82 @@ def test_emu_short_distances(orc):
         # far more symbols per compressed byte than the default capacity factor
         st, out, r, tab = E.run(comp, 1, out_cap=len(raw) + 64, sym_factor=4096)
         assert st == 0 and out == raw, level
+
+
+def test_emu_serving_loop_budget_and_order():
+    """The serving loop on the CPU executor: jobs queue while the workspace
+    arena is full, are admitted FIFO as batches finish, and every output equals
+    its source text; the arena never holds more than its budget."""
+    import ctypes as C
+
+    L = E.server_lib()
+    raws = [synth.fastq_like(20 << 10, 310 + k) if k % 2 == 0 else synth.word_stream(24 << 10, 310 + k)
+            for k in range(6)]
+    comps = [E.padded(synth.gzip_member(r, 6)) for r in raws]
+    outs = [np.zeros(len(r) + 64, dtype=np.uint8) for r in raws]
+    # budget: room for about two of these jobs' workspaces at a time
+    o = E.ServerOpts()
+    o.opts.chunk_bytes = 4096
+    probe = C.c_void_p()
+    L.gz_plan(C.byref(probe), C.c_void_p(comps[0].ctypes.data), len(synth.gzip_member(raws[0], 6)), 0,
+              C.byref(o.opts))
+    info = E.Info()
+    L.gz_plan_info(probe, C.byref(info))
+    L.gz_plan_destroy(probe)
+    o.budget_bytes = int(info.ws_bytes * 2.6)
+    o.max_inflight = 2
+    o.max_batch = 2
+    h = C.c_void_p()
+    assert L.gz_server_create(C.byref(h), C.byref(o)) == 0
+    for k, (r, c) in enumerate(zip(raws, comps)):
+        n = len(synth.gzip_member(r, 6))
+        assert L.gz_server_submit(h, C.c_void_p(c.ctypes.data), n, C.c_void_p(outs[k].ctypes.data),
+                                  outs[k].size, 100 + k) == 0
+    st = E.ServerInfo()
+    L.gz_server_stats(h, C.byref(st))
+    assert st.queued == 6
+    buf = (E.Done * 16)()
+    done = []
+    for _ in range(50):
+        n = L.gz_server_poll(h, buf, 16)
+        assert n >= 0
+        done += [(buf[i].tag, buf[i].status, buf[i].out_len, buf[i].t_start) for i in range(n)]
+        if len(done) == 6:
+            break
+    L.gz_server_stats(h, C.byref(st))
+    L.gz_server_destroy(h)
+    assert sorted(t for t, *_ in done) == list(range(100, 106))
+    for tag, status, out_len, _ in done:
+        k = tag - 100
+        assert status == 0 and out_len == len(raws[k])
+        assert outs[k][:out_len].tobytes() == raws[k]
+    # admitted in submission order, never more workspace than the budget
+    starts = [t for _, _, _, t in sorted(done)]
+    assert starts == sorted(starts)
+    assert st.arena_peak <= o.budget_bytes and st.batches >= 3
+
+
+@pytest.mark.parametrize("decode", [0, 1])
+def test_emu_deferred_confirmation_paths(orc, decode):
+    """Chunks much smaller than a block owe most of their confirmation blocks
+    past their stop; they are settled from the next chunks' checked blocks, or
+    (decode=1) by decoding them on their own.  Starts and bytes equal the
+    oracle's either way, also with a bit flipped in the middle of the stream."""
+    raw = synth.word_stream(90 << 10, 308)
+    comp = synth.gzip_member(raw, 6)
+    for flip in (None, len(comp) // 2, len(comp) // 3):
+        c = bytearray(comp)
+        if flip is not None:
+            c[flip] ^= 0x10
+        c = bytes(c)
+        ref = orc.pugz(c, 24)
+        st, out, r, tab = E.run(c, 24, out_cap=len(raw) + 64, confirm_decode=decode)
+        if ref.status == orc.OK or ref.reason == "CRC":
+            # the device path checks the length against ISIZE, not the CRC
+            want = 0 if ref.status == orc.OK or (len(ref.out) & 0xFFFFFFFF) == ref.isize_trailer else -7
+            assert st == want, (flip, st, ref.reason)
+            if want == 0:
+                assert out == ref.out.tobytes()
+            assert np.array_equal(_starts(tab), ref.start)
+        else:
+            assert st != 0, (flip, ref.reason)

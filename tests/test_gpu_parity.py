@@ -235,3 +235,12 @@ def test_window_sizes(orc, c1, win):
     raw, comp = c1
     _say("LDS window", win)
     _check_against_oracle(orc, comp, 8, raw, window_syms=win)
+
+
+@pytest.mark.parametrize("n", [64, 200])
+def test_deferred_confirmation_decoded_alone(orc, c1, n):
+    """Confirmation blocks owed past a chunk's stop, decoded on their own
+    instead of taken from the next chunks: same starts and bytes."""
+    raw, comp = c1
+    _say("deferred confirmation decoded alone,", n, "chunks")
+    _check_against_oracle(orc, comp, n, raw, confirm_decode=1)
