@@ -196,6 +196,8 @@ static int plan_common(gz_plan_t p) {
     p->files.push_back(fd);
   }
   const uint32_t N = (uint32_t)p->chunks.size();
+  // workgroups per chunk search: enough for some 4096 in all
+  if (!p->opts.scan_groups) p->groups = std::max<uint32_t>(1, std::min<uint32_t>(64, 4096 / std::max<uint32_t>(1, N)));
   // inflate order: longest compressed range first
   p->order.resize(N);
   for (uint32_t i = 0; i < N; i++) p->order[i] = i;
@@ -254,7 +256,7 @@ static void fill_defaults(gz_plan_t p, const gz_opts *opts) {
   // LDS history ring of each decoding wave: older match sources are read back
   // from HBM, so a smaller ring trades those reads for more waves per CU
   p->win = p->opts.window_syms ? p->opts.window_syms : DEFAULT_RING;
-  p->groups = p->opts.scan_groups ? p->opts.scan_groups : 8;
+  p->groups = p->opts.scan_groups;
   (void)hipGetDevice(&p->device);
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, p->device) == hipSuccess) p->n_cu = prop.multiProcessorCount;
@@ -625,9 +627,8 @@ const char *gz_strerror(int code) {
 namespace {
 std::mutex g_tune_mu;
 std::map<std::tuple<int, int, int>, gz_opts> g_tune;
-const uint64_t k_tune_chunks[] = {64ull << 10, 128ull << 10, 256ull << 10, 512ull << 10,
-                                  1ull << 20,  2ull << 20,   4ull << 20};
-const uint32_t k_tune_rings[] = {4096, 8192, 16384};
+const uint64_t k_tune_chunks[] = {32ull << 10, 64ull << 10, 128ull << 10, 256ull << 10, 512ull << 10, 1ull << 20};
+const uint32_t k_tune_rings[] = {4096, 8192};
 }  // namespace
 
 int gz_autotune(const void *d_comp, size_t comp_len, void *d_out, size_t out_cap, void *d_ws, size_t ws_bytes,
@@ -653,12 +654,8 @@ int gz_autotune(const void *d_comp, size_t comp_len, void *d_out, size_t out_cap
       gz_plan_destroy(pl);
       payload = inf.payload_end - inf.payload_start;
       isize = inf.isize;
-      // at least two chunks, except for inputs below the smallest chunk size;
-      // chunks below 256 KiB only where they are needed for parallelism
-      // (the confirmation blocks past each chunk's stop then cost more than
-      // the chunk itself)
+      // at least two chunks, except for inputs below the smallest chunk size
       if (cb != k_tune_chunks[0] && cb * 2 > payload) continue;
-      if (cb < (256ull << 10) && payload > (64ull << 20)) continue;
       need = std::max<uint64_t>(need, inf.ws_bytes);
       cand.push_back(o);
     }

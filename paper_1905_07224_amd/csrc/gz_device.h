@@ -510,6 +510,40 @@ __device__ __forceinline__ bool start_stage1(const Src &s, uint64_t b) {
   return left == 0;
 }
 
+// The cheap stage for the 32 candidates of one aligned dword at once: bit k
+// of the result is start_stage1 of bit 32 * W + k of the aligned view (file
+// bit 32 * W + k - 8 * mis).  x0..x3: dwords W .. W + 3 (zero past the
+// buffer).  The 3-bit header pattern is tested for all 32 positions with
+// word operations; the rest only where it holds (one position in eight).
+__device__ __forceinline__ uint32_t start_stage1_word(const Src &s, int64_t W, uint32_t x0, uint32_t x1, uint32_t x2,
+                                                      uint32_t x3) {
+  const uint64_t lo = ((uint64_t)x1 << 32) | x0;
+  uint32_t pat = (uint32_t)(~lo & ~(lo >> 1) & (lo >> 2));  // BFINAL = 0, BTYPE = 10
+  uint32_t pass = 0;
+  for (int g = 0; g < 32 && pat; g++) {
+    const uint32_t k = (uint32_t)__builtin_ctz(pat);
+    pat &= pat - 1;
+    // file bit of this candidate must leave room for the 17 header bits
+    const int64_t b = 32 * W + (int64_t)k - 8 * (int64_t)s.mis;
+    if (b < 0 || (uint64_t)b + 17 > s.end_bits) continue;
+    const uint32_t w0 = __builtin_amdgcn_alignbit(x1, x0, k);
+    const uint32_t w1 = __builtin_amdgcn_alignbit(x2, x1, k);
+    const uint32_t w2 = __builtin_amdgcn_alignbit(x3, x2, k);
+    if (((w0 >> 3) & 31u) > 29u || ((w0 >> 8) & 31u) > 29u) continue;
+    const uint32_t hclen = ((w0 >> 13) & 15u) + 4u;
+    // code-length code lengths: 3 bits each from bit 17
+    const uint64_t cl = (uint64_t)(w0 >> 17) | ((uint64_t)w1 << 15) | ((uint64_t)w2 << 47);
+    int left = 128;
+#pragma unroll
+    for (uint32_t i = 0; i < 19; i++) {
+      const uint32_t L = (uint32_t)(cl >> (3 * i)) & 7u;
+      if (i < hclen && L) left -= 128 >> L;
+    }
+    if (left == 0) pass |= 1u << k;
+  }
+  return pass;
+}
+
 // Full static check, whole wave: the dynamic tables at b + 3 are valid.
 __device__ __forceinline__ bool start_stage2(const Src &s, uint64_t b, TablesLDS &sh) {
   WaveBits br;

@@ -666,9 +666,12 @@ __global__ void k_init(ChunkState *cs, uint32_t n_chunks, FileState *fs, uint32_
 
 // ---------------------------------------------------------------------------
 // k_scan: for every chunk after the first of its file, the smallest bit in
-// [lo_bit, hi_bit) passing the static checks.  `groups` workgroups share one
-// chunk and sweep 256-bit tiles in an interleaved order; a tile is skipped
-// once a passing candidate before it is known.
+// [lo_bit, hi_bit) passing the static checks.  A wave covers 2048 candidate
+// bits per step, one aligned dword per lane (the cheap stage for all 32 bits
+// of it at once); the survivors, rare, then get the full static check in bit
+// order by the whole wave.  `groups` workgroups share one chunk and its
+// 4 waves each take steps in an interleaved order; a step is skipped once a
+// passing candidate before it is known.
 // ---------------------------------------------------------------------------
 
 __global__ __launch_bounds__(256) void k_scan(const FileDesc *files, const ChunkDesc *chunks, ChunkState *cs,
@@ -680,25 +683,49 @@ __global__ __launch_bounds__(256) void k_scan(const FileDesc *files, const Chunk
   const ChunkDesc cd = chunks[c];
   Src s;
   s.init(files[cd.file].comp, files[cd.file].comp_len);
-  const int wave = (int)uni32(threadIdx.x >> 6), lane = lane_id();
+  const uint32_t wave = uni32(threadIdx.x >> 6);
+  const int lane = lane_id();
   unsigned long long *cand = (unsigned long long *)&cs[c].cand;
-  for (uint64_t t = g;; t += groups) {
-    const uint64_t tile = cd.lo_bit + t * 256u;
-    if (tile >= cd.hi_bit) break;
+  // aligned-view dwords holding the range
+  const int64_t mb = 8 * (int64_t)s.mis;
+  const int64_t W0 = ((int64_t)cd.lo_bit + mb) >> 5;
+  const int64_t W1 = ((int64_t)cd.hi_bit + mb + 31) >> 5;
+  const uint64_t steps = (uint64_t)(W1 - W0 + 63) / 64;
+  for (uint64_t t = (uint64_t)g + (uint64_t)groups * wave; t < steps; t += (uint64_t)groups * 4u) {
+    const int64_t Wt = W0 + 64 * (int64_t)t;
+    const uint64_t first_bit = (uint64_t)std::max<int64_t>(32 * Wt - mb, (int64_t)cd.lo_bit);
     const uint64_t cur = uni64(__hip_atomic_load(cand, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-    if (cur <= tile) break;
-    const uint64_t b0 = tile + 64u * (uint64_t)wave;
-    const uint64_t b = b0 + (uint64_t)lane;
-    const bool p = b < cd.hi_bit && start_stage1(s, b);
-    uint64_t m = __ballot(p);
-    while (m) {
+    if (cur <= first_bit) break;
+    const int64_t W = Wt + lane;
+    uint32_t surv = 0;
+    if (W < W1) {
+      surv = start_stage1_word(s, W, s.dw(W), s.dw(W + 1), s.dw(W + 2), s.dw(W + 3));
+      // only candidates in [lo_bit, hi_bit): bits [klo, khi) of this dword
+      const int64_t b0 = 32 * W - mb;
+      const int64_t klo = std::min<int64_t>(32, std::max<int64_t>(0, (int64_t)cd.lo_bit - b0));
+      const int64_t khi = std::min<int64_t>(32, std::max<int64_t>(0, (int64_t)cd.hi_bit - b0));
+      const uint64_t keep = khi > klo ? (((1ull << (khi - klo)) - 1ull) << klo) : 0ull;
+      surv &= (uint32_t)keep;
+    }
+    uint64_t m = __ballot(surv != 0);
+    bool done = false;
+    for (int q = 0; q < 64 && m && !done; q++) {
       const int l = __ffsll((unsigned long long)m) - 1;
       m &= m - 1;
-      const uint64_t bb = b0 + (uint64_t)l;
-      if (bb >= uni64(__hip_atomic_load(cand, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) break;
-      if (start_stage2(s, bb, sh[wave])) {
-        if (lane == 0) atomicMin(cand, (unsigned long long)bb);
-        break;
+      uint32_t sl = (uint32_t)__builtin_amdgcn_readlane((int)surv, l);
+      for (int r = 0; r < 32 && sl; r++) {
+        const uint32_t k = (uint32_t)__builtin_ctz(sl);
+        sl &= sl - 1;
+        const uint64_t bb = (uint64_t)(32 * (Wt + l) - mb) + k;
+        if (bb >= uni64(__hip_atomic_load(cand, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+          done = true;
+          break;
+        }
+        if (start_stage2(s, bb, sh[wave])) {
+          if (lane == 0) atomicMin(cand, (unsigned long long)bb);
+          done = true;
+          break;
+        }
       }
     }
   }
