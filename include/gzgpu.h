@@ -41,7 +41,8 @@ extern "C" {
 #define GZ_E_UNSUPPORTED (-3) /* bytes after the first member (multi-member input) */
 #define GZ_E_DATA (-4)        /* invalid DEFLATE data, truncation, distance too far back */
 #define GZ_E_CAPACITY (-5)    /* output or workspace too small; gz_result gives the sizes needed */
-#define GZ_E_SIZE (-7)        /* decoded length differs from the trailer's ISIZE (mod 2^32) */
+#define GZ_E_CRC (-6)         /* CRC-32 of the output differs from the trailer's (RFC 1952 section 8) */
+#define GZ_E_SIZE (-7)        /* CRC matches but the length differs from the trailer's ISIZE (mod 2^32) */
 #define GZ_E_HIP (-9)         /* HIP runtime error */
 #define GZ_E_NOT_READY (-10)  /* gz_result before any gz_decompress on this plan */
 
@@ -96,6 +97,8 @@ typedef struct gz_result {
   uint64_t n_syms;         /* Huffman literal/length symbols decoded (end-of-block included) */
   uint64_t n_placeholders; /* symbols that referenced a chunk's unknown window */
   uint64_t n_blocks;
+  uint32_t crc32;          /* CRC-32 of the output, computed on the device (when the decode succeeded) */
+  uint32_t pad;
 } gz_result;
 
 typedef struct gz_plan_s *gz_plan_t;
@@ -169,9 +172,9 @@ int gz_debug_layout(gz_plan_t plan, int file, uint64_t *sym_off, uint64_t *win_i
                     void **win_base);
 
 /* Passes timed when opts.timing is set, in launch order. */
-#define GZ_N_PASSES 12
+#define GZ_N_PASSES 13
 /* Names: upload, init, scan, capacity, inflate, confirm, redo, stitch,
- * finalize, tilescan, propagate, translate.  Waits for the last launch and writes the duration of
+ * finalize, tilescan, propagate, translate, crc.  Waits for the last launch and writes the duration of
  * each pass in milliseconds (HIP events on the launch stream) into ms[0..n).
  * Returns the number written, or GZ_E_NOT_READY without timing. */
 int gz_pass_times(gz_plan_t plan, float *ms, int n);

@@ -24,7 +24,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgzgpu.so")
 
 GZ_OK, GZ_E_ARG, GZ_E_HEADER, GZ_E_UNSUPPORTED, GZ_E_DATA, GZ_E_CAPACITY = 0, -1, -2, -3, -4, -5
-GZ_E_SIZE, GZ_E_HIP, GZ_E_NOT_READY = -7, -9, -10
+GZ_E_CRC, GZ_E_SIZE, GZ_E_HIP, GZ_E_NOT_READY = -6, -7, -9, -10
 NONE = (1 << 64) - 1
 
 
@@ -54,7 +54,8 @@ class Result(C.Structure):
     _fields_ = [("status", C.c_int32), ("n_chunks", C.c_uint32), ("out_len", C.c_uint64),
                 ("out_needed", C.c_uint64), ("ws_needed", C.c_uint64), ("n_nonempty", C.c_uint32),
                 ("n_repairs", C.c_uint32), ("n_extended", C.c_uint32), ("n_retries", C.c_uint32),
-                ("n_syms", C.c_uint64), ("n_placeholders", C.c_uint64), ("n_blocks", C.c_uint64)]
+                ("n_syms", C.c_uint64), ("n_placeholders", C.c_uint64), ("n_blocks", C.c_uint64),
+                ("crc32", C.c_uint32), ("pad", C.c_uint32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -88,7 +89,7 @@ EXPORTS = ["gz_plan", "gz_plan_batch", "gz_plan_info", "gz_decompress", "gz_deco
            "gz_chunk_table", "gz_debug_layout", "gz_plan_destroy", "gz_strerror", "gz_device_info", "gz_pass_times",
            "gz_pass_name", "gz_decompress_graph", "gz_autotune", "gz_server_create", "gz_server_submit",
            "gz_server_poll", "gz_server_stats", "gz_server_destroy"]
-GZ_N_PASSES = N_PASSES = 12
+GZ_N_PASSES = N_PASSES = 13
 # defaults of gz_opts (include/gzgpu.h)
 DEFAULT_CHUNK_BYTES = 32 << 10
 DEFAULT_WINDOW = 4096

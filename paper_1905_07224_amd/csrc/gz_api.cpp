@@ -32,6 +32,7 @@ hipError_t gzk_stitch(int, uint32_t, const FileDesc *, const ChunkDesc *, ChunkS
                       uint16_t *, hipStream_t);
 hipError_t gzk_finalize(int, uint32_t, const FileDesc *, const ChunkDesc *, ChunkState *, FileState *, uint16_t *,
                         hipStream_t);
+hipError_t gzk_crc(uint32_t, const FileDesc *, FileState *, const uint32_t *, uint64_t, hipStream_t);
 hipError_t gzk_tilescan(const ChunkDesc *, const ChunkState *, const FileState *, uint32_t, uint64_t *, uint32_t *,
                         AccEntry *, hipStream_t);
 hipError_t gzk_propagate(uint32_t, const uint32_t *, const AccEntry *, uint8_t *, const uint16_t *, uint16_t *,
@@ -89,6 +90,33 @@ int64_t parse_gzip_header(const uint8_t *h, size_t n) {
     p += 2;
   }
   return (int64_t)p;
+}
+
+// x^(8 * 2^k) mod P for the device CRC combine (reflected representation:
+// bit 31 is x^0; multiplying by x is a right shift that folds bit 0 back
+// through the polynomial 0xEDB88320)
+uint32_t gf_mulx_host(uint32_t a) { return (a >> 1) ^ (0xEDB88320u & (0u - (a & 1u))); }
+uint32_t gf_mul_host(uint32_t a, uint32_t b) {
+  uint32_t p = 0;
+  for (int i = 0; i < 32; i++) {
+    if ((a >> (31 - i)) & 1u) p ^= b;
+    b = gf_mulx_host(b);
+  }
+  return p;
+}
+void crc_xpow_table(uint32_t *t) {
+  uint32_t x = 0x80000000u;
+  for (int i = 0; i < 8; i++) x = gf_mulx_host(x);
+  t[0] = x;
+  for (int k = 1; k < CRC_XPOW; k++) t[k] = gf_mul_host(t[k - 1], t[k - 1]);
+  // x^(8 * CRC_LANE * m): CRC_LANE is a power of two
+  int lg = 0;
+  while ((1u << lg) < CRC_LANE) lg++;
+  uint32_t step = t[lg], acc = 0x80000000u;
+  for (int m = 0; m < 64; m++) {
+    t[CRC_XPOW + m] = acc;
+    acc = gf_mul_host(acc, step);
+  }
 }
 
 int hip_fail(hipError_t e, const char *what) {
@@ -218,6 +246,8 @@ static int plan_common(gz_plan_t p) {
   o = align_up(o + (uint64_t)N * 4, 256);
   p->scan_off = o;
   o = align_up(o + (uint64_t)p->scan_list.size() * 4 + 4, 256);
+  L.crc_off = o;
+  o = align_up(o + CRC_CONSTS * 4, 256);
   L.table_bytes = o;
   L.cstate_off = o;
   o = align_up(o + (uint64_t)N * sizeof(ChunkState), 256);
@@ -326,10 +356,17 @@ static int launch(gz_plan_t p, uint8_t *ws, size_t ws_bytes, hipStream_t st) {
     p->upload_pending = false;
   }
   if (p->capturing && p->opts.timing) return GZ_E_ARG;
+  // CRC units of each file's output capacity, in file order
+  uint64_t crc_units = 0;
+  for (FileDesc &fd : p->files) {
+    fd.crc_unit0 = crc_units;
+    crc_units += fd.out ? (fd.out_cap + CRC_UNIT - 1) / CRC_UNIT : 0;
+  }
   memcpy(p->pinned + L.files_off, p->files.data(), F * sizeof(FileDesc));
   memcpy(p->pinned + L.chunks_off, p->chunks.data(), (size_t)N * sizeof(ChunkDesc));
   memcpy(p->pinned + L.order_off, p->order.data(), (size_t)N * 4);
   if (!p->scan_list.empty()) memcpy(p->pinned + p->scan_off, p->scan_list.data(), p->scan_list.size() * 4);
+  crc_xpow_table((uint32_t *)(p->pinned + L.crc_off));
   int ev = 0;
   auto mark = [&]() {
     if (p->opts.timing && ev <= GZ_N_PASSES) (void)hipEventRecord(p->pass_ev[ev++], st);
@@ -394,6 +431,9 @@ static int launch(gz_plan_t p, uint8_t *ws, size_t ws_bytes, hipStream_t st) {
   if ((e = gzk_translate((uint32_t)p->n_cu * 8, files, chunks, cs, fs, tiles, N, wins, pool, ctr, st)) !=
       hipSuccess)
     return hip_fail(e, "translate");
+  mark();
+  if ((e = gzk_crc(F, files, fs, (const uint32_t *)(ws + L.crc_off), crc_units, st)) != hipSuccess)
+    return hip_fail(e, "crc");
   mark();
   if (p->capturing) return GZ_OK;
   p->timed = p->opts.timing != 0;
@@ -526,6 +566,7 @@ int gz_result_get(gz_plan_t p, int file, gz_result *res) {
   res->n_syms = s.n_syms;
   res->n_placeholders = s.n_placeholders;
   res->n_blocks = s.n_blocks;
+  res->crc32 = s.crc_out;
   if (s.overflow) {
     // the workspace of a plan whose symbol factor covers the worst chunk
     double worst = 0;
@@ -591,8 +632,9 @@ int gz_pass_times(gz_plan_t p, float *ms, int n) {
 }
 
 const char *gz_pass_name(int i) {
-  static const char *names[GZ_N_PASSES] = {"upload", "init",     "scan",     "capacity",  "inflate",  "confirm",
-                                           "redo",   "stitch",   "finalize", "tilescan", "propagate", "translate"};
+  static const char *names[GZ_N_PASSES] = {"upload",   "init",     "scan",      "capacity",  "inflate",
+                                           "confirm",  "redo",     "stitch",    "finalize",  "tilescan",
+                                           "propagate", "translate", "crc"};
   return i >= 0 && i < GZ_N_PASSES ? names[i] : "";
 }
 
@@ -616,6 +658,7 @@ const char *gz_strerror(int code) {
     case GZ_E_DATA: return "invalid compressed data";
     case GZ_E_CAPACITY: return "output or workspace too small";
     case GZ_E_SIZE: return "decompressed size does not match the trailer";
+    case GZ_E_CRC: return "CRC-32 of the output does not match the trailer";
     case GZ_E_HIP: return g_err[0] ? g_err : "HIP runtime error";
     case GZ_E_NOT_READY: return "no decompression launched on this plan";
     default: return "unknown error";

@@ -35,8 +35,19 @@ enum : int32_t {
   ST_UNSUPPORTED = -3,
   ST_DATA = -4,
   ST_CAPACITY = -5,
+  ST_CRC = -6,
   ST_SIZE = -7,
 };
+
+// CRC-32 of the output (RFC 1952 section 8) on the device: units of
+// CRC_UNIT bytes, CRC_LANE bytes per lane.  Constants set by the host, in the
+// reflected representation (x^0 = 0x80000000): xpow[k] = x^(8 * 2^k) mod P
+// (k < CRC_XPOW), then lanepow[m] = x^(8 * CRC_LANE * m) mod P (m < 64).
+constexpr uint32_t CRC_UNIT = 65536;
+constexpr uint32_t CRC_LANE = CRC_UNIT / 64;
+constexpr int CRC_XPOW = 48;
+constexpr int CRC_CONSTS = CRC_XPOW + 64;
+constexpr uint32_t CRC_POLY = 0xEDB88320u;
 
 struct FileDesc {
   const uint8_t *comp;     // device address of the .gz bytes
@@ -51,6 +62,7 @@ struct FileDesc {
   uint32_t crc;
   uint64_t pool_base;      // this file's part of the symbol pool (elements)
   uint64_t pool_elems;
+  uint64_t crc_unit0;      // first CRC unit of this file (units of all earlier files' out_cap)
 };
 
 struct ChunkDesc {
@@ -101,6 +113,10 @@ struct FileState {
   uint32_t n_nonempty;
   uint32_t n_retries;
   uint32_t overflow;
+  uint32_t size_bad;       // length differs from ISIZE (reported after the CRC, as RFC 1952 checks it first)
+  uint32_t crc_acc;        // XOR of the units' shifted raw CRCs
+  uint32_t crc_out;        // CRC-32 of the output
+  uint32_t pad;
 };
 
 struct Counters {
@@ -117,7 +133,8 @@ struct Layout {
   uint64_t files_off;      // FileDesc[F]
   uint64_t chunks_off;     // ChunkDesc[N]
   uint64_t order_off;      // uint32[N]: inflate work order
-  uint64_t table_bytes;    // bytes uploaded from the host (files + chunks + order)
+  uint64_t crc_off;        // uint32[CRC_XPOW] powers of x for the CRC combine (in the uploaded table)
+  uint64_t table_bytes;    // bytes uploaded from the host (files + chunks + order + scan list + crc)
   uint64_t cstate_off;     // ChunkState[N]
   uint64_t fstate_off;     // FileState[F]
   uint64_t counters_off;   // Counters

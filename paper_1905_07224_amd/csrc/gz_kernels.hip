@@ -1139,8 +1139,9 @@ __global__ __launch_bounds__(256) void k_finalize(const FileDesc *files, const C
       else if (((last_end + 7) >> 3) + 8 != fd.comp_len) st = ST_UNSUPPORTED;
       else if (ovf) st = ST_CAPACITY;
       else if (carry > fd.out_cap) st = ST_CAPACITY;
-      else if ((uint32_t)carry != fd.isize) st = ST_SIZE;
     }
+    // a length that differs from ISIZE is reported after the CRC check
+    fs[f].size_bad = (uint32_t)carry != fd.isize ? 1u : 0u;
     fs[f].status = st;
     fs[f].out_len = carry;
     fs[f].out_needed = carry;
@@ -1410,6 +1411,124 @@ __global__ __launch_bounds__(256) void k_translate(const FileDesc *files, const 
 }
 
 // ---------------------------------------------------------------------------
+// k_crc: CRC-32 of every file's output (RFC 1952 section 8), on the device.
+// The CRC register without its preset and final inversion is linear over
+// GF(2): for a message cut into pieces, raw(M) is the XOR over the pieces of
+// raw(piece) * x^(8 * bytes after the piece) mod P.  Each lane takes 256
+// bytes (four table lookups per 4 bytes: the slicing technique with tables
+// of a byte followed by 0..3 zero bytes), multiplies its raw CRC by the
+// power of x for the bytes after it, and the wave's XOR goes to the file's
+// accumulator with one atomic XOR, so units need no order.  k_crc_final adds
+// the preset (0xFFFFFFFF * x^(8 L)) and the final inversion, then checks the
+// trailer; a length differing from ISIZE is reported only when the CRC
+// matches, the order in which RFC 1952 lists the two checks.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ uint32_t gf_mulx(uint32_t a) { return (a >> 1) ^ (CRC_POLY & (0u - (a & 1u))); }
+
+// a * b mod P, reflected representation (bit 31 is x^0)
+__device__ __forceinline__ uint32_t gf_mul(uint32_t a, uint32_t b) {
+  uint32_t p = 0;
+#pragma unroll
+  for (int i = 0; i < 32; i++) {
+    p ^= b & (0u - ((a >> (31 - i)) & 1u));
+    b = gf_mulx(b);
+  }
+  return p;
+}
+
+// x^(8 n) mod P
+__device__ __forceinline__ uint32_t gf_xpow8(uint64_t n, const uint32_t *xpow) {
+  uint32_t r = 0x80000000u;
+  for (int k = 0; k < CRC_XPOW && (n >> k); k++)
+    if ((n >> k) & 1u) r = gf_mul(r, xpow[k]);
+  return r;
+}
+
+// x^(8 n) mod P for a wave-uniform n: lane k holds the factor of bit k,
+// multiplied together in a butterfly (every lane ends with the product)
+__device__ __forceinline__ uint32_t gf_xpow8_wave(uint64_t n, const uint32_t *xpow) {
+  const int lane = lane_id();
+  uint32_t f = (lane < CRC_XPOW && ((n >> lane) & 1u)) ? xpow[lane] : 0x80000000u;
+  for (int o = 1; o < 64; o <<= 1) f = gf_mul(f, __shfl_xor(f, o));
+  return f;
+}
+
+__global__ __launch_bounds__(256) void k_crc(const FileDesc *files, uint32_t n_files, FileState *fs,
+                                             const uint32_t *consts, uint64_t total_units) {
+  __shared__ uint32_t S[4][256];
+  const int tid = (int)threadIdx.x;
+  {
+    uint32_t r = (uint32_t)tid;
+#pragma unroll
+    for (int k = 0; k < 8; k++) r = (r >> 1) ^ (CRC_POLY & (0u - (r & 1u)));
+    S[0][tid] = r;
+  }
+  __syncthreads();
+  for (int k = 1; k < 4; k++) {
+    const uint32_t p = S[k - 1][tid];
+    S[k][tid] = (p >> 8) ^ S[0][p & 0xFFu];
+    __syncthreads();
+  }
+  const uint64_t unit = (uint64_t)blockIdx.x * 4u + (uint64_t)uni32((uint32_t)tid >> 6);
+  if (unit >= total_units) return;
+  // file: the last one whose first unit is at or before this one
+  uint32_t lo = 0, hi = n_files;
+  for (int it = 0; it < 32 && hi - lo > 1; it++) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (files[mid].crc_unit0 <= unit) lo = mid;
+    else hi = mid;
+  }
+  const uint32_t f = uni32(lo);
+  if (uni(fs[f].status) != ST_OK) return;
+  const uint64_t L = uni64(fs[f].out_len);
+  const uint64_t start = (unit - files[f].crc_unit0) * CRC_UNIT;
+  if (start >= L) return;
+  const uint8_t *out = files[f].out;
+  const int lane = lane_id();
+  const uint64_t a = start + (uint64_t)lane * CRC_LANE;
+  const uint64_t b = a + CRC_LANE < L ? a + CRC_LANE : L;
+  uint32_t r = 0;
+  uint64_t p = a;
+  if (((uintptr_t)out & 15u) == 0) {
+    for (; p + 16 <= b; p += 16) {
+      const uint4 q = *reinterpret_cast<const uint4 *>(out + p);
+      const uint32_t w4[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+      for (int h = 0; h < 4; h++) {
+        const uint32_t w = r ^ w4[h];
+        r = S[3][w & 0xFFu] ^ S[2][(w >> 8) & 0xFFu] ^ S[1][(w >> 16) & 0xFFu] ^ S[0][w >> 24];
+      }
+    }
+  }
+  for (; p < b; p++) r = S[0][(r ^ out[p]) & 0xFFu] ^ (r >> 8);
+  uint32_t v;
+  if (start + CRC_UNIT <= L) {
+    // full unit: lane m is followed by (63 - m) lanes of the unit, then the rest of the file
+    v = gf_mul(r, consts[CRC_XPOW + 63 - lane]);
+    for (int o = 32; o > 0; o >>= 1) v ^= __shfl_xor(v, o);
+    v = gf_mul(v, gf_xpow8_wave(L - (start + CRC_UNIT), consts));
+  } else {
+    // the file's last unit: each lane's own distance to the end
+    v = a < b ? gf_mul(r, gf_xpow8(L - b, consts)) : 0u;
+    for (int o = 32; o > 0; o >>= 1) v ^= __shfl_xor(v, o);
+  }
+  if (lane == 0 && v) atomicXor(&fs[f].crc_acc, v);
+}
+
+__global__ __launch_bounds__(256) void k_crc_final(const FileDesc *files, uint32_t n_files, FileState *fs,
+                                                   const uint32_t *xpow) {
+  for (uint32_t f = threadIdx.x; f < n_files; f += blockDim.x) {
+    if (fs[f].status != ST_OK) continue;
+    const uint64_t L = fs[f].out_len;
+    const uint32_t crc = fs[f].crc_acc ^ gf_mul(0xFFFFFFFFu, gf_xpow8(L, xpow)) ^ 0xFFFFFFFFu;
+    fs[f].crc_out = crc;
+    if (crc != files[f].crc) fs[f].status = ST_CRC;
+    else if (fs[f].size_bad) fs[f].status = ST_SIZE;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Host-callable launchers
 // ---------------------------------------------------------------------------
 
@@ -1491,6 +1610,18 @@ hipError_t gzk_stitch(int win, uint32_t grid, const FileDesc *files, const Chunk
 hipError_t gzk_finalize(int win, uint32_t n_files, const FileDesc *files, const ChunkDesc *chunks, ChunkState *cs,
                         FileState *fs, uint16_t *pool, hipStream_t st) {
   GZ_WIN_SWITCH(win, hipLaunchKernelGGL(k_finalize<W>, dim3(n_files), dim3(256), 0, st, files, chunks, cs, fs, pool));
+  return hipGetLastError();
+}
+
+hipError_t gzk_crc(uint32_t n_files, const FileDesc *files, FileState *fs, const uint32_t *xpow, uint64_t total_units,
+                   hipStream_t st) {
+  if (total_units) {
+    hipLaunchKernelGGL(k_crc, dim3((uint32_t)((total_units + 3) / 4)), dim3(256), 0, st, files, n_files, fs, xpow,
+                       total_units);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_crc_final, dim3(1), dim3(256), 0, st, files, n_files, fs, xpow);
   return hipGetLastError();
 }
 

@@ -113,6 +113,12 @@ static inline T atomicMin(T *p, T v) {
   if (v < o) *p = v;
   return o;
 }
+template <typename T>
+static inline T atomicXor(T *p, T v) {
+  T o = *p;
+  *p = o ^ v;
+  return o;
+}
 template <typename T, typename U, typename V>
 static inline T atomicCAS(T *p, U c, V v) {
   T o = *p;

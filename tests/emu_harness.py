@@ -27,7 +27,8 @@ class Result(C.Structure):
     _fields_ = [("status", C.c_int32), ("n_chunks", C.c_uint32), ("out_len", C.c_uint64),
                 ("out_needed", C.c_uint64), ("ws_needed", C.c_uint64), ("n_nonempty", C.c_uint32),
                 ("n_repairs", C.c_uint32), ("n_extended", C.c_uint32), ("n_retries", C.c_uint32),
-                ("n_syms", C.c_uint64), ("n_placeholders", C.c_uint64), ("n_blocks", C.c_uint64)]
+                ("n_syms", C.c_uint64), ("n_placeholders", C.c_uint64), ("n_blocks", C.c_uint64),
+                ("crc32", C.c_uint32), ("pad", C.c_uint32)]
 
 
 _lib = None

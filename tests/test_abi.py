@@ -63,7 +63,7 @@ def test_struct_sizes_match_header(libpath):
     assert ctypes.sizeof(gz.Opts) == 8 + 4 * 7 + 4 * 5
     assert ctypes.sizeof(gz.Job) == 8 + 8 + 4 + 4 + 8 + 8
     assert ctypes.sizeof(gz.Info) == 8 * 3 + 4 * 4
-    assert ctypes.sizeof(gz.Result) == 4 + 4 + 8 * 3 + 4 * 4 + 8 * 3
+    assert ctypes.sizeof(gz.Result) == 4 + 4 + 8 * 3 + 4 * 4 + 8 * 3 + 4 + 4
 
 
 def test_output_size_guess_uses_isize_modulus():

@@ -6,6 +6,8 @@ stitching, window propagation, translation) is exercised here without a GPU.
 The executor also reports divergence bugs (lanes of one wave at different
 intrinsics) and deadlocks by aborting the run.
 """
+import zlib
+
 import numpy as np
 import pytest
 
@@ -33,6 +35,7 @@ def _check(orc, comp, n, raw):
     assert np.array_equal(tab["len"][ne].astype(np.int64), ref.len[ne])
     assert np.array_equal(tab["out_off"][ne].astype(np.int64), ref.off[ne])
     assert r.n_placeholders == int(ref.placeholders.sum())
+    assert r.crc32 == ref.crc_trailer == zlib.crc32(raw)
     return r, tab
 
 
@@ -176,11 +179,10 @@ def test_emu_deferred_confirmation_paths(orc, decode):
         c = bytes(c)
         ref = orc.pugz(c, 24)
         st, out, r, tab = E.run(c, 24, out_cap=len(raw) + 64, confirm_decode=decode)
-        if ref.status == orc.OK or ref.reason == "CRC":
-            # the device path checks the length against ISIZE, not the CRC
-            want = 0 if ref.status == orc.OK or (len(ref.out) & 0xFFFFFFFF) == ref.isize_trailer else -7
-            assert st == want, (flip, st, ref.reason)
-            if want == 0:
+        if ref.status == orc.OK or ref.reason in ("CRC", "ISIZE"):
+            # the device checks the CRC-32, then the length, as the oracle does
+            assert st == ref.status, (flip, st, ref.reason)
+            if st == 0:
                 assert out == ref.out.tobytes()
             assert np.array_equal(_starts(tab), ref.start)
         else:

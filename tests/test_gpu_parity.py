@@ -150,7 +150,7 @@ def test_negative_statuses(orc):
     cases = {}
     bad = bytearray(comp)
     bad[-8] ^= 1
-    cases["crc_not_checked_but_size_ok"] = (bytes(bad), None)
+    cases["crc"] = (bytes(bad), gz.GZ_E_CRC)
     bad = bytearray(comp)
     bad[-4] ^= 1
     cases["isize"] = (bytes(bad), gz.GZ_E_SIZE)
@@ -192,13 +192,9 @@ def test_corrupt_bits_match_oracle_status(orc):
         if ref.status == orc.OK:
             assert r.status == 0
             assert out[: r.out_len].cpu().numpy().tobytes() == ref.out.tobytes()
-        elif ref.reason == "CRC":
-            # the device does not compute the CRC: it decodes what the oracle
-            # decoded and checks only the length against ISIZE
-            want = 0 if (len(ref.out) & 0xFFFFFFFF) == ref.isize_trailer else gz.GZ_E_SIZE
-            assert r.status == want, (k, r.status)
-            if want == 0:
-                assert out[: r.out_len].cpu().numpy().tobytes() == ref.out.tobytes()
+        elif ref.reason in ("CRC", "ISIZE"):
+            # the device checks the CRC-32, then the length, as the oracle does
+            assert r.status == ref.status, (k, r.status, ref.reason)
         else:
             assert r.status != 0, (k, ref.reason)
 
@@ -244,3 +240,53 @@ def test_deferred_confirmation_decoded_alone(orc, c1, n):
     raw, comp = c1
     _say("deferred confirmation decoded alone,", n, "chunks")
     _check_against_oracle(orc, comp, n, raw, confirm_decode=1)
+
+
+@pytest.mark.parametrize("size", [0, 1, 3, 16383, 16384, 16385, 200_003, 1 << 20])
+def test_device_crc32(size):
+    """The CRC-32 computed on the device equals zlib's, for outputs within one
+    16 KiB unit, on unit edges, and over many units; the second run writes to
+    an output at an odd address (byte-wise loads)."""
+    import zlib
+
+    gz = _gz()
+    raw = synth.fastq_like(size, 500 + size % 97)[:size]
+    comp = synth.gzip_member(raw, 6)
+    _say("device crc", size)
+    for shift in (0, 1):
+        plan = gz.Plan(_dev(comp), 3 if size > 100000 else 1)
+        buf = torch.zeros(len(raw) + 64, dtype=torch.uint8, device="cuda:0")
+        out = buf[shift:]
+        plan.launch(out)
+        r = plan.result()
+        assert r.status == 0 and r.out_len == len(raw)
+        assert r.crc32 == zlib.crc32(raw), (size, shift)
+        assert out[: r.out_len].cpu().numpy().tobytes() == raw
+
+
+def test_device_crc32_batch_and_mismatch(orc):
+    """Every file of a batch gets its own CRC; a corrupted trailer CRC is
+    reported as a CRC error, a corrupted ISIZE (CRC intact) as a size error."""
+    import zlib
+
+    gz = _gz()
+    raws = [synth.word_stream(n, 600 + n % 11) for n in (5000, 70000, 300000)]
+    comps = [synth.gzip_member(x, 6) for x in raws]
+    outs = gz.decompress_batch([_dev(c) for c in comps], n_chunks=2)
+    for x, o in zip(raws, outs):
+        assert o.cpu().numpy().tobytes() == x
+    bp = gz.BatchPlan([_dev(c) for c in comps], 2, outs=[torch.empty(len(x) + 8, dtype=torch.uint8, device="cuda:0")
+                                                         for x in raws])
+    bp.launch()
+    for i, x in enumerate(raws):
+        assert bp.result(i).crc32 == zlib.crc32(x)
+    bad_crc = bytearray(comps[1])
+    bad_crc[-8] ^= 0x40
+    bad_len = bytearray(comps[1])
+    bad_len[-4] ^= 0x01
+    for b, want in ((bytes(bad_crc), gz.GZ_E_CRC), (bytes(bad_len), gz.GZ_E_SIZE)):
+        ref = orc.pugz(b, 2)
+        assert ref.status == want
+        plan = gz.Plan(_dev(b), 2)
+        plan.launch(torch.empty(2 * len(raws[1]) + 64, dtype=torch.uint8, device="cuda:0"))
+        assert plan.result().status == want
