@@ -91,8 +91,8 @@ EXPORTS = ["gz_plan", "gz_plan_batch", "gz_plan_info", "gz_decompress", "gz_deco
            "gz_server_poll", "gz_server_stats", "gz_server_destroy"]
 GZ_N_PASSES = N_PASSES = 13
 # defaults of gz_opts (include/gzgpu.h)
-DEFAULT_CHUNK_BYTES = 32 << 10
-DEFAULT_WINDOW = 4096
+DEFAULT_CHUNK_BYTES = 48 << 10
+DEFAULT_WINDOW = 2048
 
 
 def lib():

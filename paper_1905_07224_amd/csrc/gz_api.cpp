@@ -298,7 +298,7 @@ static int make_plan(gz_plan_t *plan, const gz_job *jobs, int n, const gz_opts *
   gz_plan_t p = new (std::nothrow) gz_plan_s();
   if (!p) return GZ_E_ARG;
   fill_defaults(p, opts);
-  if (p->win != 4096 && p->win != 8192 && p->win != 16384 && p->win != 32768) {
+  if (p->win != 2048 && p->win != 4096 && p->win != 8192 && p->win != 16384 && p->win != 32768) {
     gz_plan_destroy(p);
     return GZ_E_ARG;
   }
@@ -670,8 +670,8 @@ const char *gz_strerror(int code) {
 namespace {
 std::mutex g_tune_mu;
 std::map<std::tuple<int, int, int>, gz_opts> g_tune;
-const uint64_t k_tune_chunks[] = {32ull << 10, 64ull << 10, 128ull << 10, 256ull << 10, 512ull << 10, 1ull << 20};
-const uint32_t k_tune_rings[] = {4096, 8192};
+const uint64_t k_tune_chunks[] = {32ull << 10, 48ull << 10, 64ull << 10, 128ull << 10, 256ull << 10, 1ull << 20};
+const uint32_t k_tune_rings[] = {2048, 4096, 8192};
 }  // namespace
 
 int gz_autotune(const void *d_comp, size_t comp_len, void *d_out, size_t out_cap, void *d_ws, size_t ws_bytes,

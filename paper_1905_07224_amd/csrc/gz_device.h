@@ -190,7 +190,7 @@ struct WaveBits {
 enum : uint32_t { K_LIT = 0, K_LEN = 1, K_EOB = 2, K_LONG = 3, K_BAD = 4, K_BADSYM = 5, K_LITX = 8 };
 
 constexpr int LIT_BITS = 10;
-constexpr int DIST_BITS = 10;
+constexpr int DIST_BITS = 9;
 constexpr int CL_BITS = 7;
 
 // lengths 3..258 (section 3.2.5): codes 257..264 carry no extra bits, then

@@ -28,7 +28,7 @@ struct InflateLDS {
   TablesLDS t;
   alignas(16) uint16_t ring[WIN];  // the last WIN symbols produced, by position mod WIN
 };
-static_assert(sizeof(InflateLDS<4096>) <= inflate_lds_bytes(4096) && sizeof(InflateLDS<8192>) <= inflate_lds_bytes(8192) &&
+static_assert(sizeof(InflateLDS<2048>) <= inflate_lds_bytes(2048) && sizeof(InflateLDS<4096>) <= inflate_lds_bytes(4096) && sizeof(InflateLDS<8192>) <= inflate_lds_bytes(8192) &&
                   sizeof(InflateLDS<16384>) <= inflate_lds_bytes(16384) &&
                   sizeof(InflateLDS<32768>) <= inflate_lds_bytes(32768),
               "decoder LDS larger than the occupancy estimate");
@@ -53,7 +53,7 @@ struct Inflater {
   // stores before it, so those are complete, and the read bypasses the L1,
   // which may still hold lines of an earlier attempt at this chunk.  The unit
   // being moved to HBM is never older than 512 + 64 symbols.
-  static_assert(WIN >= 4096 && WIN <= 32768 && (WIN & (WIN - 1)) == 0, "ring size");
+  static_assert(WIN >= 2048 && WIN <= 32768 && (WIN & (WIN - 1)) == 0, "ring size");
   static constexpr uint32_t RMASK = WIN - 1;
 
   InflateLDS<WIN> &sh;
@@ -816,6 +816,27 @@ __global__ __launch_bounds__(64) void k_inflate(const FileDesc *files, const Chu
   }
 }
 
+// Passes where few chunks have work: a wave takes 64 chunks per atomic,
+// tests them with one lane each, then works on the ones that need it one
+// after another (a single shared counter per chunk would serialise).
+template <typename Need, typename Work>
+__device__ __forceinline__ void sparse_chunks(uint32_t *counter, uint32_t n, Need need, Work work) {
+  const int lane = lane_id();
+  for (uint32_t it = 0; it <= n / 64u + 1u; it++) {
+    uint32_t base = 0;
+    if (lane == 0) base = atomicAdd(counter, 64u);
+    base = uni(base);
+    if (base >= n) break;
+    const uint32_t c = base + (uint32_t)lane;
+    uint64_t m = __ballot(c < n && need(c));
+    for (int q = 0; q < 64 && m; q++) {
+      const int l = __ffsll((unsigned long long)m) - 1;
+      m &= m - 1;
+      work(base + (uint32_t)l);
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // k_confirm: a chunk that reached its stop before its trial block and 5
 // confirmation blocks were all decoded (Appendix A) still owes the rest,
@@ -833,13 +854,9 @@ template <int WIN>
 __global__ __launch_bounds__(64) void k_confirm(const FileDesc *files, const ChunkDesc *chunks, ChunkState *cs,
                                                 uint32_t n, Counters *ctr, uint16_t *pool, uint32_t always_decode) {
   __shared__ InflateLDS<WIN> sh;
-  for (uint32_t it = 0; it <= n; it++) {
-    uint32_t c = 0;
-    if (lane_id() == 0) c = atomicAdd(&ctr->confirm_next, 1u);
-    c = uni(c);
-    if (c >= n) break;
+  auto owes = [&](uint32_t c) { return cs[c].pad != 0 && cs[c].start != NONE && cs[c].status == ST_OK; };
+  sparse_chunks(&ctr->confirm_next, n, owes, [&](uint32_t c) {
     const uint32_t need0 = uni(cs[c].pad);
-    if (need0 == 0 || uni64(cs[c].start) == NONE || uni(cs[c].status) != ST_OK) continue;
     const ChunkDesc cd = chunks[c];
     const FileDesc fd = files[cd.file];
     const uint32_t c1 = fd.first_chunk + fd.n_chunks;
@@ -866,7 +883,7 @@ __global__ __launch_bounds__(64) void k_confirm(const FileDesc *files, const Chu
       ok = inf.confirm(at, need) == D_OK;
     }
     if (!ok && lane_id() == 0) cs[c].flags |= CS_UNCONFIRMED;
-  }
+  });
 }
 
 // k_redo: a chunk whose candidate failed its deferred confirmation searches
@@ -875,17 +892,13 @@ template <int WIN>
 __global__ __launch_bounds__(64) void k_redo(const FileDesc *files, const ChunkDesc *chunks, ChunkState *cs, uint32_t n,
                                              Counters *ctr, uint16_t *pool) {
   __shared__ InflateLDS<WIN> sh;
-  for (uint32_t it = 0; it <= n; it++) {
-    uint32_t c = 0;
-    if (lane_id() == 0) c = atomicAdd(&ctr->redo_next, 1u);
-    c = uni(c);
-    if (c >= n) break;
-    if (!(uni(cs[c].flags) & CS_UNCONFIRMED)) continue;
+  auto rejected = [&](uint32_t c) { return (cs[c].flags & CS_UNCONFIRMED) != 0; };
+  sparse_chunks(&ctr->redo_next, n, rejected, [&](uint32_t c) {
     const uint64_t s0 = uni64(cs[c].start);
     const uint32_t r0 = uni(cs[c].retries);
     inflate_chunk<WIN>(sh, files, chunks, cs, pool, c, false, s0 + 1);
     if (lane_id() == 0) cs[c].retries += r0 + 1;
-  }
+  });
 }
 
 // Continue chunk c from its recorded end until the first block at or past `stop`.
@@ -955,18 +968,19 @@ template <int WIN>
 __global__ __launch_bounds__(64) void k_stitch(const FileDesc *files, const ChunkDesc *chunks, ChunkState *cs,
                                                uint32_t n, Counters *ctr, uint16_t *pool) {
   __shared__ InflateLDS<WIN> sh;
-  for (uint32_t it = 0; it <= n; it++) {
-    uint32_t c = 0;
-    if (lane_id() == 0) c = atomicAdd(&ctr->stitch_next, 1u);
-    c = uni(c);
-    if (c >= n) break;
+  // a chunk continues when the next accepted start lies past its end
+  auto short_of_next = [&](uint32_t c) {
+    if (cs[c].start == NONE || cs[c].status != ST_OK || (cs[c].flags & CS_FINAL)) return false;
+    const FileDesc &fd = files[chunks[c].file];
+    const uint64_t nf = next_start(fd, cs, c, true, nullptr);
+    return cs[c].end < nf || nf == NONE;
+  };
+  sparse_chunks(&ctr->stitch_next, n, short_of_next, [&](uint32_t c) {
     const ChunkDesc cd = chunks[c];
     const FileDesc fd = files[cd.file];
-    if (uni64(cs[c].start) == NONE || uni(cs[c].status) != ST_OK || (uni(cs[c].flags) & CS_FINAL)) continue;
     const uint64_t nf = uni64(next_start(fd, cs, c, true, nullptr));
-    const uint64_t e = uni64(cs[c].end);
-    if (e < nf || nf == NONE) extend_chunk<WIN>(sh, fd, cd, cs, pool, c, nf);
-  }
+    extend_chunk<WIN>(sh, fd, cd, cs, pool, c, nf);
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -1362,6 +1376,8 @@ __global__ __launch_bounds__(256) void k_translate(const FileDesc *files, const 
                                                    FileState *fs, const uint64_t *tiles, uint32_t n,
                                                    const uint8_t *wins, const uint16_t *pool, Counters *ctr) {
   __shared__ uint32_t s_item;
+  __shared__ uint4 tbw[(TRANSLATE_TILE + 32) / 16];  // 16-byte aligned staging
+  uint8_t *tb = reinterpret_cast<uint8_t *>(tbw);
   const uint64_t total = tiles[n];
   for (uint64_t it = 0; it <= total; it++) {
     if (threadIdx.x == 0) s_item = atomicAdd(&ctr->translate_next, 1u);
@@ -1385,14 +1401,20 @@ __global__ __launch_bounds__(256) void k_translate(const FileDesc *files, const 
     const uint8_t *wj = wins + (uint64_t)j * WINDOW;
     const uint32_t lim = 32768u - sj.valid;  // placeholders below this lie before the data start
     uint8_t *out = fd.out + sj.out_off;
+    // the tile's bytes are staged in LDS at the output's alignment, then
+    // stored as aligned 16-byte words (byte stores for the partial words at
+    // the two ends, which the neighbouring tiles share)
+    const uint64_t cnt = L - p0 < TRANSLATE_TILE ? L - p0 : TRANSLATE_TILE;
+    const uintptr_t ob = (uintptr_t)(out + p0);
+    const uint32_t sh = (uint32_t)(ob & 15u);
     int err = 0;
-    for (uint64_t g = p0 + 8ull * threadIdx.x; g < p0 + TRANSLATE_TILE && g < L; g += 8ull * blockDim.x) {
+    for (uint64_t g = p0 + 8ull * threadIdx.x; g < p0 + cnt; g += 8ull * blockDim.x) {
       const uint4 v = *reinterpret_cast<const uint4 *>(Dj + g);
       const uint32_t w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
       for (int h = 0; h < 8; h++) {
         const uint64_t p = g + h;
-        if (p < L) {
+        if (p < p0 + cnt) {
           const uint32_t t = (w[h >> 1] >> (16 * (h & 1))) & 0xFFFFu;
           uint32_t b;
           if (t < 256u) {
@@ -1402,10 +1424,24 @@ __global__ __launch_bounds__(256) void k_translate(const FileDesc *files, const 
             if (t < 0x8000u || m < lim) err = 1;
             b = wj[m];
           }
-          out[p] = (uint8_t)b;
+          tb[sh + (p - p0)] = (uint8_t)b;
         }
       }
     }
+    __syncthreads();
+    const uint32_t end = sh + (uint32_t)cnt;      // LDS bytes [sh, end) hold the tile
+    const uint32_t first = (sh + 15u) & ~15u;     // first whole 16-byte word
+    const uint32_t last = end & ~15u;             // end of the whole words
+    uint8_t *base = (uint8_t *)(ob - sh);         // 16-byte aligned
+    if (first <= last) {
+      for (uint32_t k = first + 16u * threadIdx.x; k < last; k += 16u * blockDim.x)
+        *reinterpret_cast<uint4 *>(base + k) = *reinterpret_cast<const uint4 *>(&tb[k]);
+      for (uint32_t k = sh + threadIdx.x; k < first; k += blockDim.x) base[k] = tb[k];
+      for (uint32_t k = last + threadIdx.x; k < end; k += blockDim.x) base[k] = tb[k];
+    } else {
+      for (uint32_t k = sh + threadIdx.x; k < end; k += blockDim.x) base[k] = tb[k];
+    }
+    __syncthreads();
     if (err) atomicCAS(&fs[chunks[j].file].status, ST_OK, ST_DATA);
   }
 }
@@ -1561,6 +1597,10 @@ hipError_t gzk_scan(const FileDesc *files, const ChunkDesc *chunks, ChunkState *
 
 #define GZ_WIN_SWITCH(win, CALL)   \
   switch (win) {                   \
+    case 2048: {                   \
+      constexpr int W = 2048;      \
+      CALL;                        \
+    } break;                       \
     case 4096: {                   \
       constexpr int W = 4096;      \
       CALL;                        \
