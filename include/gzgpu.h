@@ -12,8 +12,9 @@
  * Memory model
  *   - Every buffer handed to these calls is HIP device memory owned by the
  *     caller: compressed input, output and workspace.  The library allocates
- *     no device memory; it keeps a small pinned host copy of each plan's job
- *     table.
+ *     no device memory for plans; it keeps a small pinned host copy of each
+ *     plan's job table.  A stream holds a 32 KiB window buffer and a server
+ *     its arena (below).
  *   - The compressed input must stay alive and unmodified until the stream
  *     work of a gz_decompress* call has completed.
  *   - A plan is used by one stream at a time.  Distinct plans (with distinct
@@ -185,6 +186,93 @@ const char *gz_strerror(int code);
 
 /* Device count and compute-unit count of device `dev` (for sizing). */
 int gz_device_info(int dev, int *n_cu, int *lds_bytes);
+
+/* ------------------------------------------------------------------------
+ * Bounded-memory streaming.  Section VI-C decodes a whole member at once and
+ * holds all of its output; the paper remarks (end of Section VI-C, and in the
+ * Discussion) that memory could be bounded by processing one part of the
+ * file at a time.  A stream
+ * decodes the payload in segments of about segment_bytes compressed bytes,
+ * each one run of the whole two-pass path over its own chunks:
+ *   - its first chunk starts at the bit where the previous segment stopped, a
+ *     block boundary reached by decoding (no block-start search), with the
+ *     previous output's last 32 KiB as its context (Section IV-A's random
+ *     access: a block start and a known window give the exact output);
+ *   - its last chunk decodes until the first block header at or past
+ *     start + 8 * segment_bytes bits (or to the member's final block).
+ * Segment outputs, in order, are the member's gunzip.  The running CRC-32
+ * and length are carried on, and the trailer is checked after the final
+ * block.  (bit offset, window, CRC-32, length) is a checkpoint: a stream
+ * resumed from it produces the same bytes as one that got there itself.
+ *
+ * Memory: the caller provides, per segment, an output buffer and a workspace
+ * (gz_stream_get_info gives sizes that fit every segment at the options'
+ * symbol factor); the stream allocates one 32 KiB device buffer for the
+ * carried window.  The compressed input stays caller-owned and must stay
+ * valid while the stream is used.  One stream, one host thread.
+ * ------------------------------------------------------------------------ */
+typedef struct gz_stream_s *gz_stream_t;
+
+typedef struct gz_stream_info {
+  uint64_t ws_bytes;       /* workspace for any segment */
+  uint64_t out_bytes;      /* output capacity for any segment at the symbol factor (a segment that
+                              needs more reports GZ_E_CAPACITY with the size) */
+  uint64_t segment_bytes;  /* compressed bytes per segment, nominal */
+  uint64_t payload_start;  /* byte where the DEFLATE data begins */
+  uint64_t payload_end;    /* byte where the trailer begins */
+  uint32_t crc32;          /* trailer CRC-32 */
+  uint32_t isize;          /* trailer ISIZE */
+} gz_stream_info;
+
+typedef struct gz_segment_result {
+  int32_t status;          /* GZ_OK or GZ_E_*; after an error the stream stays where it was */
+  uint32_t done;           /* 1: the final block was decoded; CRC-32 and ISIZE are checked */
+  uint64_t out_len;        /* bytes this segment wrote at d_out */
+  uint64_t out_total;      /* bytes of the member decoded so far, this segment included */
+  uint64_t start_bit;      /* the segment decoded [start_bit, end_bit) of the .gz file */
+  uint64_t end_bit;
+  uint64_t out_needed;     /* GZ_E_CAPACITY: output bytes this segment needs */
+  uint64_t ws_needed;      /* GZ_E_CAPACITY: workspace a retry needs (gz_stream_get_info has it too) */
+  uint32_t crc32;          /* CRC-32 of the member's bytes so far */
+  uint32_t n_chunks;
+  uint32_t n_repairs;
+  uint32_t n_retries;
+} gz_segment_result;
+
+typedef struct gz_checkpoint {
+  uint64_t bit;            /* where the next segment starts, in bits from the start of the .gz file */
+  uint64_t out_total;      /* bytes decoded before it */
+  uint32_t crc32;          /* CRC-32 of those bytes */
+  uint32_t valid;          /* real history bytes at the end of window: min(out_total, 32768) */
+  uint32_t done;           /* the member is finished */
+  uint32_t pad;
+  uint8_t window[32768];   /* the 32768 bytes before `bit` (the first 32768 - valid are zero) */
+} gz_checkpoint;
+
+/* Reads the member header and trailer (small synchronous copies) and
+ * allocates the window buffer.  segment_bytes 0: 256 MiB.  Errors: GZ_E_ARG,
+ * GZ_E_HEADER, GZ_E_HIP. */
+int gz_stream_open(gz_stream_t *stream, const void *d_comp, size_t comp_len, uint64_t segment_bytes,
+                   const gz_opts *opts);
+int gz_stream_get_info(gz_stream_t stream, gz_stream_info *info);
+/* Enqueue the next segment on hip_stream; its output goes to d_out[0 ..).
+ * Then call gz_stream_wait before the next call.  Errors: GZ_E_ARG (also
+ * when the member is finished or a segment is still unread),
+ * GZ_E_CAPACITY (workspace too small), GZ_E_HIP. */
+int gz_stream_next(gz_stream_t stream, void *d_out, size_t out_cap, void *d_ws, size_t ws_bytes,
+                   void *hip_stream);
+/* Wait for the segment (with the same deadline as gz_result_get) and
+ * advance the stream if it succeeded.  After a capacity error the stream
+ * raises its symbol factor as needed; gz_stream_get_info then gives the
+ * larger sizes. */
+int gz_stream_wait(gz_stream_t stream, gz_segment_result *res);
+/* Copy the position after the last finished segment (synchronous). */
+int gz_stream_checkpoint(gz_stream_t stream, gz_checkpoint *cp);
+/* Continue from a checkpoint of a stream over the same input.  Errors:
+ * GZ_E_ARG (a bit outside the payload, valid > 32768, valid differing from
+ * min(out_total, 32768)), GZ_E_HIP. */
+int gz_stream_resume(gz_stream_t stream, const gz_checkpoint *cp);
+void gz_stream_destroy(gz_stream_t stream);
 
 /* ------------------------------------------------------------------------
  * Serving loop (beyond the paper's one-file setting): jobs arrive one at a

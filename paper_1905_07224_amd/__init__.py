@@ -83,12 +83,37 @@ class ServerInfo(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
 
 
+class StreamInfo(C.Structure):
+    _fields_ = [("ws_bytes", C.c_uint64), ("out_bytes", C.c_uint64), ("segment_bytes", C.c_uint64),
+                ("payload_start", C.c_uint64), ("payload_end", C.c_uint64), ("crc32", C.c_uint32),
+                ("isize", C.c_uint32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class SegmentResult(C.Structure):
+    _fields_ = [("status", C.c_int32), ("done", C.c_uint32), ("out_len", C.c_uint64), ("out_total", C.c_uint64),
+                ("start_bit", C.c_uint64), ("end_bit", C.c_uint64), ("out_needed", C.c_uint64),
+                ("ws_needed", C.c_uint64), ("crc32", C.c_uint32), ("n_chunks", C.c_uint32),
+                ("n_repairs", C.c_uint32), ("n_retries", C.c_uint32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Checkpoint(C.Structure):
+    _fields_ = [("bit", C.c_uint64), ("out_total", C.c_uint64), ("crc32", C.c_uint32), ("valid", C.c_uint32),
+                ("done", C.c_uint32), ("pad", C.c_uint32), ("window", C.c_uint8 * 32768)]
+
+
 _lib = None
 
 EXPORTS = ["gz_plan", "gz_plan_batch", "gz_plan_info", "gz_decompress", "gz_decompress_batch", "gz_result_get",
            "gz_chunk_table", "gz_debug_layout", "gz_plan_destroy", "gz_strerror", "gz_device_info", "gz_pass_times",
            "gz_pass_name", "gz_decompress_graph", "gz_autotune", "gz_server_create", "gz_server_submit",
-           "gz_server_poll", "gz_server_stats", "gz_server_destroy"]
+           "gz_server_poll", "gz_server_stats", "gz_server_destroy", "gz_stream_open", "gz_stream_get_info",
+           "gz_stream_next", "gz_stream_wait", "gz_stream_checkpoint", "gz_stream_resume", "gz_stream_destroy"]
 GZ_N_PASSES = N_PASSES = 13
 # defaults of gz_opts (include/gzgpu.h)
 DEFAULT_CHUNK_BYTES = 48 << 10
@@ -129,8 +154,17 @@ def lib():
         L.gz_server_destroy.restype = None
         L.gz_pass_name.argtypes = [i32]
         L.gz_pass_name.restype = C.c_char_p
+        L.gz_stream_open.argtypes = [C.POINTER(vp), vp, C.c_size_t, u64, C.POINTER(Opts)]
+        L.gz_stream_get_info.argtypes = [vp, C.POINTER(StreamInfo)]
+        L.gz_stream_next.argtypes = [vp, vp, C.c_size_t, vp, C.c_size_t, vp]
+        L.gz_stream_wait.argtypes = [vp, C.POINTER(SegmentResult)]
+        L.gz_stream_checkpoint.argtypes = [vp, C.POINTER(Checkpoint)]
+        L.gz_stream_resume.argtypes = [vp, C.POINTER(Checkpoint)]
+        L.gz_stream_destroy.argtypes = [vp]
+        L.gz_stream_destroy.restype = None
         for name in EXPORTS:
-            if name not in ("gz_plan_destroy", "gz_strerror", "gz_pass_name", "gz_server_destroy"):
+            if name not in ("gz_plan_destroy", "gz_strerror", "gz_pass_name", "gz_server_destroy",
+                            "gz_stream_destroy"):
                 getattr(L, name).restype = i32
         _lib = L
     return _lib
@@ -491,3 +525,100 @@ class Server:
         if h is not None and h.value and _lib is not None:
             _lib.gz_server_destroy(h)
             self._h = C.c_void_p()
+
+
+class Stream:
+    """Bounded-memory decoding of one gzip member in segments (gz_stream_*).
+
+    Each segment() call decodes the next segment into an output buffer that
+    is reused (a view of it is returned: copy it before the next call) and a
+    workspace sized for one segment; the carried window stays on the device.
+    checkpoint() / resume() save and restore the position."""
+
+    def __init__(self, comp, segment_bytes: int = 0, stream=None, **opts):
+        self.comp = _as_device_bytes(comp)
+        self.device = self.comp.device
+        self.stream = stream
+        self._h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib().gz_stream_open(C.byref(self._h), C.c_void_p(self.comp.data_ptr()), self.comp.numel(),
+                                        int(segment_bytes), C.byref(_opts(**opts))))
+        self._ws = None
+        self._out = None
+        self.done = False
+        self.last = None
+
+    def info(self) -> dict:
+        i = StreamInfo()
+        with torch.cuda.device(self.device):
+            _check(lib().gz_stream_get_info(self._h, C.byref(i)))
+        return i.as_dict()
+
+    def _buffers(self, ws_bytes: int, out_bytes: int):
+        if self._ws is None or self._ws.numel() < ws_bytes:
+            self._ws = None
+            self._ws = torch.empty(ws_bytes, dtype=torch.uint8, device=self.device)
+        if self._out is None or self._out.numel() < out_bytes:
+            self._out = None
+            self._out = torch.empty(max(out_bytes, 1), dtype=torch.uint8, device=self.device)
+
+    def segment(self, retries: int = 4) -> torch.Tensor:
+        """Decode the next segment; returns its bytes (a view of the reused
+        output buffer).  Raises GzError on a data error."""
+        if self.done:
+            raise GzError(GZ_E_ARG, "the member is finished")
+        for _ in range(retries + 1):
+            info = self.info()
+            out_need = info["out_bytes"]
+            if self.last is not None and self.last["status"] == GZ_E_CAPACITY:
+                out_need = max(out_need, self.last["out_needed"])
+            self._buffers(info["ws_bytes"], out_need)
+            with torch.cuda.device(self.device):
+                _check(lib().gz_stream_next(self._h, C.c_void_p(self._out.data_ptr()), self._out.numel(),
+                                            C.c_void_p(self._ws.data_ptr()), self._ws.numel(),
+                                            _stream_handle(self.stream)))
+                r = SegmentResult()
+                _check(lib().gz_stream_wait(self._h, C.byref(r)))
+            self.last = r.as_dict()
+            if r.status == GZ_OK:
+                self.done = bool(r.done)
+                return self._out[:r.out_len]
+            if r.status != GZ_E_CAPACITY:
+                _check(r.status)
+        _check(GZ_E_CAPACITY)
+
+    def __iter__(self):
+        while not self.done:
+            yield self.segment()
+
+    def checkpoint(self) -> Checkpoint:
+        cp = Checkpoint()
+        with torch.cuda.device(self.device):
+            _check(lib().gz_stream_checkpoint(self._h, C.byref(cp)))
+        return cp
+
+    def resume(self, cp: Checkpoint):
+        with torch.cuda.device(self.device):
+            _check(lib().gz_stream_resume(self._h, C.byref(cp)))
+        self.done = bool(cp.done)
+        self.last = None
+
+    def close(self):
+        if self._h.value:
+            lib().gz_stream_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.gz_stream_destroy(h)
+            self._h = C.c_void_p()
+
+
+def decompress_stream(comp, segment_bytes: int = 0, stream=None, **opts) -> torch.Tensor:
+    """The member decoded segment by segment, concatenated (for tests: the
+    bounded-memory use keeps only one segment at a time)."""
+    s = Stream(comp, segment_bytes, stream=stream, **opts)
+    parts = [seg.clone() for seg in s]
+    s.close()
+    return torch.cat(parts) if parts else torch.empty(0, dtype=torch.uint8, device=s.device)

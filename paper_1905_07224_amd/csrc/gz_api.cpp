@@ -39,6 +39,7 @@ hipError_t gzk_propagate(uint32_t, const uint32_t *, const AccEntry *, uint8_t *
                          uint8_t *, hipStream_t);
 hipError_t gzk_translate(uint32_t, const FileDesc *, const ChunkDesc *, const ChunkState *, FileState *,
                          const uint64_t *, uint32_t, const uint8_t *, const uint16_t *, Counters *, hipStream_t);
+hipError_t gzk_carry(const FileDesc *, const FileState *, const uint8_t *, uint8_t *, hipStream_t);
 }
 
 namespace {
@@ -158,38 +159,68 @@ struct gz_plan_s {
   std::vector<ChunkState> cst;
   std::vector<ChunkDesc> cdev;  // the device's chunk table after the run (capacities)
   std::vector<gz_job> jobs;
+  std::vector<uint64_t> span;   // per file: compressed bytes its pool was sized for
+  // a segment of a longer member (gz_stream_*): one file, decoded from
+  // start_bit (a block boundary) to the first block at or past stop_bit
+  // (NONE: to the final block), its first chunk with a carried window
+  struct Segment {
+    bool on = false;
+    uint64_t start_bit = 0, stop_bit = NONE, out_before = 0;
+    uint32_t crc_in = 0, win_valid = 0;
+    int64_t h = 0;        // payload start byte
+    uint32_t crc = 0, isize = 0;
+  } seg;
 };
+
+// Header and trailer of the member at j.d_comp: payload start, CRC-32, ISIZE.
+static int read_member(const gz_job &j, uint32_t f, int64_t *h_out, uint32_t *crc, uint32_t *isize) {
+  if (!j.d_comp || j.comp_len < 18) {
+    snprintf(g_err, sizeof(g_err), "file %u: input too short for a gzip member", f);
+    return j.d_comp ? GZ_E_HEADER : GZ_E_ARG;
+  }
+  // header bytes (grown if the optional fields are long) and the trailer
+  size_t hn = (size_t)std::min<uint64_t>(j.comp_len, 4096);
+  std::vector<uint8_t> hb;
+  int64_t h = -1;
+  for (;;) {
+    hb.resize(hn);
+    hipError_t e = hipMemcpy(hb.data(), j.d_comp, hn, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "reading the gzip header");
+    h = parse_gzip_header(hb.data(), hn);
+    if (h >= 0 || hn == j.comp_len) break;
+    hn = (size_t)std::min<uint64_t>(j.comp_len, (uint64_t)hn * 4);
+  }
+  if (h < 0 || (uint64_t)h + 8 >= j.comp_len) {
+    snprintf(g_err, sizeof(g_err), "file %u: invalid gzip member header", f);
+    return GZ_E_HEADER;
+  }
+  uint8_t tr[8];
+  hipError_t e = hipMemcpy(tr, (const uint8_t *)j.d_comp + j.comp_len - 8, 8, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "reading the gzip trailer");
+  *h_out = h;
+  *crc = (uint32_t)tr[0] | ((uint32_t)tr[1] << 8) | ((uint32_t)tr[2] << 16) | ((uint32_t)tr[3] << 24);
+  *isize = (uint32_t)tr[4] | ((uint32_t)tr[5] << 8) | ((uint32_t)tr[6] << 16) | ((uint32_t)tr[7] << 24);
+  return GZ_OK;
+}
 
 static int plan_common(gz_plan_t p) {
   const uint32_t F = (uint32_t)p->jobs.size();
   p->files.clear();
   p->chunks.clear();
+  p->span.clear();
   uint64_t sym_elems = 0;
   for (uint32_t f = 0; f < F; f++) {
     const gz_job &j = p->jobs[f];
-    if (!j.d_comp || j.comp_len < 18) {
-      snprintf(g_err, sizeof(g_err), "file %u: input too short for a gzip member", f);
-      return j.d_comp ? GZ_E_HEADER : GZ_E_ARG;
+    int64_t h = 0;
+    uint32_t crc = 0, isize = 0;
+    if (p->seg.on) {
+      h = p->seg.h;
+      crc = p->seg.crc;
+      isize = p->seg.isize;
+    } else {
+      const int r = read_member(j, f, &h, &crc, &isize);
+      if (r != GZ_OK) return r;
     }
-    // header bytes (grown if the optional fields are long) and the trailer
-    size_t hn = (size_t)std::min<uint64_t>(j.comp_len, 4096);
-    std::vector<uint8_t> hb;
-    int64_t h = -1;
-    for (;;) {
-      hb.resize(hn);
-      hipError_t e = hipMemcpy(hb.data(), j.d_comp, hn, hipMemcpyDeviceToHost);
-      if (e != hipSuccess) return hip_fail(e, "reading the gzip header");
-      h = parse_gzip_header(hb.data(), hn);
-      if (h >= 0 || hn == j.comp_len) break;
-      hn = (size_t)std::min<uint64_t>(j.comp_len, (uint64_t)hn * 4);
-    }
-    if (h < 0 || (uint64_t)h + 8 >= j.comp_len) {
-      snprintf(g_err, sizeof(g_err), "file %u: invalid gzip member header", f);
-      return GZ_E_HEADER;
-    }
-    uint8_t tr[8];
-    hipError_t e = hipMemcpy(tr, (const uint8_t *)j.d_comp + j.comp_len - 8, 8, hipMemcpyDeviceToHost);
-    if (e != hipSuccess) return hip_fail(e, "reading the gzip trailer");
     FileDesc fd{};
     fd.comp = (const uint8_t *)j.d_comp;
     fd.comp_len = j.comp_len;
@@ -197,9 +228,24 @@ static int plan_common(gz_plan_t p) {
     fd.trailer_byte = j.comp_len - 8;
     fd.out = (uint8_t *)j.d_out;
     fd.out_cap = j.out_cap;
-    fd.crc = (uint32_t)tr[0] | ((uint32_t)tr[1] << 8) | ((uint32_t)tr[2] << 16) | ((uint32_t)tr[3] << 24);
-    fd.isize = (uint32_t)tr[4] | ((uint32_t)tr[5] << 8) | ((uint32_t)tr[6] << 16) | ((uint32_t)tr[7] << 24);
-    const uint64_t P = fd.trailer_byte - (uint64_t)h;  // payload bytes
+    fd.crc = crc;
+    fd.isize = isize;
+    fd.stop_bit = NONE;
+    // chunks cut the bytes [lo, hi): the payload, or a segment's range
+    uint64_t lo = (uint64_t)h, hi = fd.trailer_byte, margin = 0;
+    if (p->seg.on) {
+      fd.payload_bit = p->seg.start_bit;
+      lo = (p->seg.start_bit + 7) / 8;
+      if (p->seg.stop_bit != NONE && p->seg.stop_bit < 8 * fd.trailer_byte) {
+        fd.stop_bit = p->seg.stop_bit;
+        hi = std::max<uint64_t>(lo + 1, p->seg.stop_bit / 8);
+        margin = STOP_MARGIN_BYTES;
+      }
+      fd.out_before = p->seg.out_before;
+      fd.crc_in = p->seg.crc_in;
+      fd.win_valid = p->seg.win_valid;
+    }
+    const uint64_t P = hi > lo ? hi - lo : 1;
     uint64_t N = j.n_chunks > 0 ? (uint64_t)j.n_chunks : (P + p->opts.chunk_bytes - 1) / p->opts.chunk_bytes;
     N *= std::max<uint32_t>(1, p->opts.waves_per_chunk);
     N = std::max<uint64_t>(1, std::min<uint64_t>(N, P));
@@ -207,19 +253,20 @@ static int plan_common(gz_plan_t p) {
     fd.n_chunks = (uint32_t)N;
     for (uint64_t i = 0; i < N; i++) {
       ChunkDesc cd{};
-      const uint64_t a = (uint64_t)h + (uint64_t)((unsigned __int128)i * P / N);
-      const uint64_t b = (uint64_t)h + (uint64_t)((unsigned __int128)(i + 1) * P / N);
-      cd.lo_bit = 8 * a;
+      const uint64_t a = lo + (uint64_t)((unsigned __int128)i * P / N);
+      const uint64_t b = lo + (uint64_t)((unsigned __int128)(i + 1) * P / N);
+      cd.lo_bit = i == 0 ? fd.payload_bit : 8 * a;
       cd.hi_bit = 8 * b;
       cd.file = f;
       cd.index = (uint32_t)i;
-      cd.flags = i == 0 ? CF_FIRST : 0u;
+      cd.flags = i == 0 ? (CF_FIRST | (p->seg.on && p->seg.win_valid ? CF_CARRIED : 0u)) : 0u;
       p->chunks.push_back(cd);
     }
     // the chunks' capacities are set on the device from their actual spans;
     // their sum is bounded by this
     fd.pool_base = sym_elems;
-    fd.pool_elems = (uint64_t)p->opts.sym_factor * (P + N) + N * (SYM_SLACK + FLUSH_UNIT);
+    fd.pool_elems = (uint64_t)p->opts.sym_factor * (P + margin + N) + N * (SYM_SLACK + FLUSH_UNIT);
+    p->span.push_back(P + margin + N);
     sym_elems += align_up(fd.pool_elems, FLUSH_UNIT);
     p->files.push_back(fd);
   }
@@ -548,6 +595,19 @@ static int fetch(gz_plan_t p) {
   return GZ_OK;
 }
 
+// Symbol factor that covers the worst overflowing chunk of a file, with room.
+static uint64_t needed_factor(gz_plan_t p, int file) {
+  const FileDesc &fd = p->files[file];
+  double worst = 0;
+  for (uint32_t c = fd.first_chunk; c < fd.first_chunk + fd.n_chunks; c++)
+    if (p->cst[c].flags & CS_OVERFLOW) {
+      const ChunkDesc &d = p->cdev[c];
+      const double span = d.sym_cap > SYM_SLACK ? (double)(d.sym_cap - SYM_SLACK) / p->opts.sym_factor : 1.0;
+      worst = std::max(worst, (double)p->cst[c].needed / span);
+    }
+  return (uint64_t)(worst * 1.25) + 1;
+}
+
 int gz_result_get(gz_plan_t p, int file, gz_result *res) {
   if (!p || !res || file < 0 || file >= (int)p->files.size()) return GZ_E_ARG;
   int r = fetch(p);
@@ -569,16 +629,8 @@ int gz_result_get(gz_plan_t p, int file, gz_result *res) {
   res->crc32 = s.crc_out;
   if (s.overflow) {
     // the workspace of a plan whose symbol factor covers the worst chunk
-    double worst = 0;
-    for (uint32_t c = fd.first_chunk; c < fd.first_chunk + fd.n_chunks; c++)
-      if (p->cst[c].flags & CS_OVERFLOW) {
-        const ChunkDesc &d = p->cdev[c];
-        const double span = d.sym_cap > SYM_SLACK ? (double)(d.sym_cap - SYM_SLACK) / p->opts.sym_factor : 1.0;
-        worst = std::max(worst, (double)p->cst[c].needed / span);
-      }
-    const uint64_t f2 = (uint64_t)(worst * 1.25) + 1;
-    res->ws_needed = p->lay.total + 2 * (f2 > p->opts.sym_factor ? f2 - p->opts.sym_factor : 1) *
-                                        (uint64_t)((fd.trailer_byte - fd.payload_bit / 8) + fd.n_chunks);
+    const uint64_t f2 = needed_factor(p, file);
+    res->ws_needed = p->lay.total + 2 * (f2 > p->opts.sym_factor ? f2 - p->opts.sym_factor : 1) * p->span[file];
   }
   return GZ_OK;
 }
@@ -773,6 +825,219 @@ int gz_device_info(int dev, int *n_cu, int *lds_bytes) {
   if (n_cu) *n_cu = prop.multiProcessorCount;
   if (lds_bytes) *lds_bytes = (int)prop.maxSharedMemoryPerMultiProcessor;
   return GZ_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Bounded-memory streaming: one plan per segment (see gz_stream_open).
+// ---------------------------------------------------------------------------
+
+struct gz_stream_s {
+  gz_job job{};
+  gz_opts opts{};
+  uint64_t seg_bytes = 0;
+  int64_t h = 0;
+  uint32_t crc = 0, isize = 0;
+  uint8_t *d_win = nullptr;  // carried window, 32 KiB of device memory
+  // position after the last finished segment
+  uint64_t bit = 0, out_total = 0;
+  uint32_t crc_run = 0, valid = 0;
+  bool done = false;
+  gz_plan_t cur = nullptr;   // plan of the segment in flight
+  bool pending = false;
+};
+
+static int segment_plan(gz_stream_t s, uint64_t start_bit, uint32_t win_valid, void *d_out, uint64_t out_cap,
+                        gz_plan_t *out) {
+  *out = nullptr;
+  gz_plan_t p = new (std::nothrow) gz_plan_s();
+  if (!p) return GZ_E_ARG;
+  fill_defaults(p, &s->opts);
+  p->seg.on = true;
+  p->seg.start_bit = start_bit;
+  p->seg.stop_bit = start_bit + 8 * s->seg_bytes;
+  p->seg.out_before = s->out_total;
+  p->seg.crc_in = s->crc_run;
+  p->seg.win_valid = win_valid;
+  p->seg.h = s->h;
+  p->seg.crc = s->crc;
+  p->seg.isize = s->isize;
+  gz_job j = s->job;
+  j.d_out = d_out;
+  j.out_cap = out_cap;
+  p->jobs.assign(1, j);
+  const int r = plan_common(p);
+  if (r != GZ_OK) {
+    gz_plan_destroy(p);
+    return r;
+  }
+  (void)hipEventCreateWithFlags(&p->upload_done, hipEventDisableTiming);
+  *out = p;
+  return GZ_OK;
+}
+
+extern "C" {
+
+int gz_stream_open(gz_stream_t *stream, const void *d_comp, size_t comp_len, uint64_t segment_bytes,
+                   const gz_opts *opts) {
+  if (!stream || !d_comp || comp_len == 0) return GZ_E_ARG;
+  *stream = nullptr;
+  gz_stream_t s = new (std::nothrow) gz_stream_s();
+  if (!s) return GZ_E_ARG;
+  if (opts) s->opts = *opts;
+  s->opts.timing = 0;
+  s->seg_bytes = segment_bytes ? segment_bytes : (256ull << 20);
+  s->job.d_comp = d_comp;
+  s->job.comp_len = comp_len;
+  int r = read_member(s->job, 0, &s->h, &s->crc, &s->isize);
+  if (r == GZ_OK) {
+    hipError_t e = hipMalloc((void **)&s->d_win, WINDOW);
+    if (e != hipSuccess) r = hip_fail(e, "stream window buffer");
+  }
+  if (r != GZ_OK) {
+    gz_stream_destroy(s);
+    return r;
+  }
+  s->bit = 8ull * (uint64_t)s->h;
+  *stream = s;
+  return GZ_OK;
+}
+
+int gz_stream_get_info(gz_stream_t s, gz_stream_info *info) {
+  if (!s || !info) return GZ_E_ARG;
+  memset(info, 0, sizeof(*info));
+  // a full segment that starts from a carried window has the largest layout
+  gz_plan_t p = nullptr;
+  const int r = segment_plan(s, 8ull * (uint64_t)s->h, WINDOW, nullptr, 0, &p);
+  if (r != GZ_OK) return r;
+  info->ws_bytes = p->lay.total;
+  info->out_bytes = p->files[0].pool_elems;
+  gz_plan_destroy(p);
+  info->segment_bytes = s->seg_bytes;
+  info->payload_start = (uint64_t)s->h;
+  info->payload_end = s->job.comp_len - 8;
+  info->crc32 = s->crc;
+  info->isize = s->isize;
+  return GZ_OK;
+}
+
+int gz_stream_next(gz_stream_t s, void *d_out, size_t out_cap, void *d_ws, size_t ws_bytes, void *hip_stream) {
+  if (!s || s->done || s->pending || !d_out || out_cap == 0) return GZ_E_ARG;
+  if (s->cur) gz_plan_destroy(s->cur);
+  s->cur = nullptr;
+  gz_plan_t p = nullptr;
+  const uint32_t wv = s->out_total > 0 ? (uint32_t)std::min<uint64_t>(s->out_total, WINDOW) : 0u;
+  int r = segment_plan(s, s->bit, wv, d_out, out_cap, &p);
+  if (r != GZ_OK) return r;
+  uint8_t *ws = (uint8_t *)d_ws;
+  hipStream_t st = (hipStream_t)hip_stream;
+  if (!ws || ws_bytes < p->lay.total || ((uintptr_t)ws & 255u)) {
+    snprintf(g_err, sizeof(g_err), "workspace needs %llu bytes, 256-byte aligned",
+             (unsigned long long)p->lay.total);
+    gz_plan_destroy(p);
+    return ws && ws_bytes < p->lay.total ? GZ_E_CAPACITY : GZ_E_ARG;
+  }
+  // the first chunk's window slot holds the carried window (nothing else
+  // writes that slot before window propagation reads it)
+  uint8_t *slot = ws + p->lay.win_off + (uint64_t)p->files[0].first_chunk * WINDOW;
+  hipError_t e;
+  if (wv > 0 && (e = hipMemcpyAsync(slot, s->d_win, WINDOW, hipMemcpyDeviceToDevice, st)) != hipSuccess) {
+    gz_plan_destroy(p);
+    return hip_fail(e, "carried window");
+  }
+  r = launch(p, ws, ws_bytes, st);
+  if (r == GZ_OK) {
+    // the next window: the last 32 KiB of (carried window ++ this output)
+    e = gzk_carry((const FileDesc *)(ws + p->lay.files_off), (const FileState *)(ws + p->lay.fstate_off), slot,
+                  s->d_win, st);
+    if (e != hipSuccess) r = hip_fail(e, "carry");
+  }
+  if (r != GZ_OK) {
+    gz_plan_destroy(p);
+    return r;
+  }
+  s->cur = p;
+  s->pending = true;
+  return GZ_OK;
+}
+
+int gz_stream_wait(gz_stream_t s, gz_segment_result *res) {
+  if (!s || !res || !s->cur || !s->pending) return GZ_E_ARG;
+  gz_result g;
+  int r = gz_result_get(s->cur, 0, &g);
+  if (r != GZ_OK) return r;
+  s->pending = false;
+  const FileState &fst = s->cur->fst[0];
+  memset(res, 0, sizeof(*res));
+  res->status = g.status;
+  res->out_len = g.out_len;
+  res->start_bit = s->bit;
+  res->end_bit = fst.end_bit;
+  res->n_chunks = g.n_chunks;
+  res->n_repairs = g.n_repairs;
+  res->n_retries = g.n_retries;
+  res->out_needed = g.out_needed;
+  if (g.status == GZ_OK) {
+    s->bit = fst.end_bit;
+    s->out_total += g.out_len;
+    s->crc_run = g.crc32;
+    s->valid = (uint32_t)std::min<uint64_t>(s->out_total, WINDOW);
+    s->done = fst.is_final != 0;
+  } else if (g.status == GZ_E_CAPACITY && fst.overflow) {
+    // symbols overflowed: later plans use a factor that covers them
+    const uint64_t f2 = needed_factor(s->cur, 0);
+    s->opts.sym_factor = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(f2, 2ull * s->opts.sym_factor), 1u << 20);
+    gz_stream_info info;
+    if (gz_stream_get_info(s, &info) == GZ_OK) res->ws_needed = info.ws_bytes;
+  }
+  res->done = s->done ? 1u : 0u;
+  res->out_total = s->out_total;
+  res->crc32 = s->crc_run;
+  return GZ_OK;
+}
+
+int gz_stream_checkpoint(gz_stream_t s, gz_checkpoint *cp) {
+  if (!s || !cp || s->pending) return GZ_E_ARG;
+  memset(cp, 0, sizeof(*cp));
+  cp->bit = s->bit;
+  cp->out_total = s->out_total;
+  cp->crc32 = s->crc_run;
+  cp->valid = s->valid;
+  cp->done = s->done ? 1u : 0u;
+  if (s->valid > 0) {
+    hipError_t e = hipMemcpy(cp->window, s->d_win, WINDOW, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "reading the window");
+  }
+  return GZ_OK;
+}
+
+int gz_stream_resume(gz_stream_t s, const gz_checkpoint *cp) {
+  if (!s || !cp || s->pending) return GZ_E_ARG;
+  const uint64_t lo = 8ull * (uint64_t)s->h, hi = 8ull * (s->job.comp_len - 8);
+  if (cp->bit < lo || cp->bit > hi || cp->valid > WINDOW ||
+      cp->valid != (uint32_t)std::min<uint64_t>(cp->out_total, WINDOW))
+    return GZ_E_ARG;
+  if (cp->valid > 0) {
+    hipError_t e = hipMemcpy(s->d_win, cp->window, WINDOW, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "writing the window");
+  }
+  s->bit = cp->bit;
+  s->out_total = cp->out_total;
+  s->crc_run = cp->crc32;
+  s->valid = cp->valid;
+  s->done = cp->done != 0;
+  return GZ_OK;
+}
+
+void gz_stream_destroy(gz_stream_t s) {
+  if (!s) return;
+  if (s->cur) {
+    if (s->pending) (void)hipStreamSynchronize(s->cur->stream);
+    gz_plan_destroy(s->cur);
+  }
+  if (s->d_win) (void)hipFree(s->d_win);
+  delete s;
 }
 
 }  // extern "C"

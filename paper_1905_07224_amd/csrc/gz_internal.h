@@ -17,7 +17,13 @@ constexpr uint32_t inflate_lds_bytes(uint32_t win) { return 7424u + 2u * win; }
 // chunk flags
 enum : uint32_t {
   CF_FIRST = 1u,        // first chunk of its file: starts at the payload, empty context
+  CF_CARRIED = 2u,      // (with CF_FIRST) a segment's first chunk: its context is the carried window
 };
+
+// Compressed bytes past a segment's stop that its last chunk may still decode
+// (the rest of the block that holds the stop).  The symbol capacity of that
+// chunk counts them; a longer block reports a capacity error.
+constexpr uint64_t STOP_MARGIN_BYTES = 128 << 10;
 
 // chunk state flags
 enum : uint32_t {
@@ -63,6 +69,13 @@ struct FileDesc {
   uint64_t pool_base;      // this file's part of the symbol pool (elements)
   uint64_t pool_elems;
   uint64_t crc_unit0;      // first CRC unit of this file (units of all earlier files' out_cap)
+  // a segment of a longer member (bounded-memory streaming): decoding starts
+  // at payload_bit, a proven block boundary, and the last chunk stops at the
+  // first block header at or past stop_bit; NONE: decode to the final block
+  uint64_t stop_bit;
+  uint64_t out_before;     // bytes of the member before this segment (ISIZE is checked on the sum)
+  uint32_t crc_in;         // CRC-32 of those bytes (0 for none)
+  uint32_t win_valid;      // real bytes in the carried window (the first chunk's window slot), 0: none
 };
 
 struct ChunkDesc {
@@ -98,7 +111,7 @@ struct AccEntry {
   uint64_t sym_off;
   uint64_t len;            // |D_j|
   uint32_t chunk;
-  uint32_t pad;            // 1: the first chunk of its file
+  uint32_t pad;            // bit 0: the first chunk of its file; bit 1: its window is carried in
 };
 
 struct FileState {
@@ -115,8 +128,9 @@ struct FileState {
   uint32_t overflow;
   uint32_t size_bad;       // length differs from ISIZE (reported after the CRC, as RFC 1952 checks it first)
   uint32_t crc_acc;        // XOR of the units' shifted raw CRCs
-  uint32_t crc_out;        // CRC-32 of the output
-  uint32_t pad;
+  uint32_t crc_out;        // CRC-32 of the output (with the bytes before the segment)
+  uint32_t is_final;       // the member's final block was decoded (the trailer is checked)
+  uint64_t end_bit;        // where the last accepted chunk stopped
 };
 
 struct Counters {

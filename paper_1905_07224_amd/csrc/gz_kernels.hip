@@ -529,13 +529,14 @@ __device__ __forceinline__ void inflater_setup(Inflater<WIN> &inf, const FileDes
   inf.nsyms = 0;
   inf.nph = 0;
   inf.nph_stop = 0;
-  inf.first = (cd.flags & CF_FIRST) != 0;
+  inf.first = (cd.flags & (CF_FIRST | CF_CARRIED)) == CF_FIRST;
   inf.over = false;
   inf.emit = true;
   inf.pj = 0;
 }
 
-// Next chunk of the same file that has a start (scan candidate or accepted).
+// Next chunk of the same file that has a start (scan candidate or accepted);
+// after the last one, the segment's stop (NONE for a whole member).
 __device__ __forceinline__ uint64_t next_start(const FileDesc &fd, const ChunkState *cs, uint32_t c, bool accepted,
                                                uint32_t *which) {
   const uint32_t endc = fd.first_chunk + fd.n_chunks;
@@ -547,7 +548,7 @@ __device__ __forceinline__ uint64_t next_start(const FileDesc &fd, const ChunkSt
     }
   }
   if (which) *which = endc;
-  return NONE;
+  return fd.stop_bit;
 }
 
 __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
@@ -747,7 +748,12 @@ __global__ __launch_bounds__(256) void k_capacity(const FileDesc *files, ChunkDe
   const FileDesc fd = files[f];
   const uint32_t c0 = fd.first_chunk, n = fd.n_chunks;
   const int tid = (int)threadIdx.x;
-  const uint64_t end_bit = 8ull * fd.trailer_byte;
+  // the last chunk decodes to the final block, or past a segment's stop to
+  // the end of the block holding it
+  const uint64_t tr_bit = 8ull * fd.trailer_byte;
+  const uint64_t end_bit = fd.stop_bit == NONE ? tr_bit
+                           : fd.stop_bit + 8 * STOP_MARGIN_BYTES < tr_bit ? fd.stop_bit + 8 * STOP_MARGIN_BYTES
+                                                                         : tr_bit;
   // pass 1, last tile first: next start after each chunk (suffix minimum)
   uint64_t later = end_bit;
   const uint32_t ntiles = (n + 255) / 256;
@@ -1060,7 +1066,7 @@ __global__ __launch_bounds__(256) void k_finalize(const FileDesc *files, const C
       cur = uni64(cs[j].end);
       fin = (uni(cs[j].flags) & CS_FINAL) != 0;
     }
-    if (st == ST_OK && !fin) st = ST_DATA;  // stream ends without a final block
+    if (st == ST_OK && !fin && fd.stop_bit == NONE) st = ST_DATA;  // stream ends without a final block
     if (tid == 0) {
       fs[f].status = st;
       fs[f].n_repairs = repairs;
@@ -1101,7 +1107,8 @@ __global__ __launch_bounds__(256) void k_finalize(const FileDesc *files, const C
     if (j < c1) {
       const uint64_t off = carry + part[tid] - L;
       cs[j].out_off = off;
-      cs[j].valid = (uint32_t)(off < WINDOW ? off : WINDOW);
+      const uint64_t hist = off + fd.win_valid;
+      cs[j].valid = (uint32_t)(hist < WINDOW ? hist : WINDOW);
     }
     carry += part[255];
     __syncthreads();
@@ -1148,14 +1155,18 @@ __global__ __launch_bounds__(256) void k_finalize(const FileDesc *files, const C
       }
     int32_t st = fs[f].status;
     const uint32_t ovf = (uint32_t)(packed >> 42);
+    const bool fin = (last_flags & CS_FINAL) != 0;
     if (st == ST_OK) {
-      if (!(last_flags & CS_FINAL)) st = ST_DATA;
-      else if (((last_end + 7) >> 3) + 8 != fd.comp_len) st = ST_UNSUPPORTED;
+      // a segment stops at a block boundary past its stop, or ends the member
+      if (!fin && (fd.stop_bit == NONE || last_end == NONE || last_end < fd.stop_bit)) st = ST_DATA;
+      else if (fin && ((last_end + 7) >> 3) + 8 != fd.comp_len) st = ST_UNSUPPORTED;
       else if (ovf) st = ST_CAPACITY;
       else if (carry > fd.out_cap) st = ST_CAPACITY;
     }
     // a length that differs from ISIZE is reported after the CRC check
-    fs[f].size_bad = (uint32_t)carry != fd.isize ? 1u : 0u;
+    fs[f].size_bad = fin && (uint32_t)(fd.out_before + carry) != fd.isize ? 1u : 0u;
+    fs[f].is_final = fin ? 1u : 0u;
+    fs[f].end_bit = last_end;
     fs[f].status = st;
     fs[f].out_len = carry;
     fs[f].out_needed = carry;
@@ -1173,7 +1184,9 @@ __global__ __launch_bounds__(256) void k_finalize(const FileDesc *files, const C
 // Window propagation (pass 2a).  The window of the next accepted chunk is
 // w_next[k] = t < 256 ? t : w[t & 0x7FFF], t = symbol k of the last 32768 of
 // (w_hat_i ++ D_i); a file's first chunk has no history (its window, unused,
-// is zero).  The chain over all accepted chunks (the compacted list of the
+// is zero), except the first chunk of a segment of a longer member, whose
+// window (the bytes before the segment) the host placed in its slot of
+// `wins`.  The chain over all accepted chunks (the compacted list of the
 // size scan, files one after another) is cut into segments of PSEG chunks:
 //   k_prop_maps   each segment composes its steps into one map from its input
 //                 window to the next segment's (16-bit entries: a byte, or
@@ -1209,10 +1222,12 @@ __device__ __forceinline__ void load_tail(const uint16_t *__restrict__ Dj, uint6
 // maps (k_prop_maps, `to_end`: the last step gives the window of position q1,
 // the next segment's first) or uint8_t for windows (k_prop_apply: windows of
 // q0 (store_first) .. q1 - 1 go to `wins`; position q1 may not exist).  `buf`
-// holds the window of position q0 on entry.
+// holds the window of position q0 on entry.  A carried window is read from
+// its slot in `seed` (slots that are never written here).
 template <typename T>
 __device__ __forceinline__ void prop_steps(T *buf, const AccEntry *acc, const uint16_t *__restrict__ pool, uint32_t q0,
-                                           uint32_t q1, uint8_t *__restrict__ wins, bool store_first, bool to_end) {
+                                           uint32_t q1, const uint8_t *seed, uint8_t *wins, bool store_first,
+                                           bool to_end) {
   const int tid = (int)threadIdx.x;
   uint32_t t[PROP_PER / 2], tn[PROP_PER / 2];
   AccEntry e0 = acc[q0];
@@ -1231,13 +1246,16 @@ __device__ __forceinline__ void prop_steps(T *buf, const AccEntry *acc, const ui
       if (q + 2 < q1) e2 = acc[q + 2];
       load_tail(pool + e1.sym_off, e1.len, tid, tn);
     }
-    // a file's first chunk starts without history
-    const bool reset = (q + 1 < q1 ? e1.pad : acc[q + 1].pad) & 1u;
+    // a file's first chunk starts without history, or from its carried window
+    const AccEntry en = q + 1 < q1 ? e1 : acc[q + 1];
+    const bool reset = en.pad & 1u;
+    const uint8_t *carried = (en.pad & 2u) ? seed + (uint64_t)en.chunk * WINDOW : nullptr;
     uint32_t v[PROP_PER / 2];  // two results per register
 #pragma unroll
     for (int i = 0; i < PROP_PER; i++) {
       const uint32_t x = (t[i >> 1] >> (16 * (i & 1))) & 0xFFFFu;
-      const uint32_t y = reset ? 0u : x < 256u ? x : (uint32_t)buf[x & 0x7FFFu];
+      uint32_t y = x < 256u ? x : (uint32_t)buf[x & 0x7FFFu];
+      if (reset) y = carried ? (uint32_t)carried[i * PROP_THREADS + tid] : 0u;
       if (i & 1) v[i >> 1] |= y << 16;
       else v[i >> 1] = y;
     }
@@ -1257,7 +1275,8 @@ __device__ __forceinline__ void prop_steps(T *buf, const AccEntry *acc, const ui
 }
 
 __global__ __launch_bounds__(PROP_THREADS) void k_prop_maps(const uint32_t *acc_pos, uint32_t n, const AccEntry *acc,
-                                                            const uint16_t *__restrict__ pool, uint16_t *maps) {
+                                                            const uint16_t *__restrict__ pool, const uint8_t *seed,
+                                                            uint16_t *maps) {
   __shared__ uint16_t m[WINDOW];
   const uint32_t A = acc_pos[n], g = blockIdx.x;
   const uint32_t q0 = g * PSEG;
@@ -1265,18 +1284,20 @@ __global__ __launch_bounds__(PROP_THREADS) void k_prop_maps(const uint32_t *acc_
   for (int k = threadIdx.x; k < (int)WINDOW; k += PROP_THREADS) m[k] = (uint16_t)(0x8000u | (uint32_t)k);
   __syncthreads();
   // map from the window of q0 to the window of q0 + PSEG
-  prop_steps<uint16_t>(m, acc, pool, q0, q0 + PSEG, nullptr, false, true);
+  prop_steps<uint16_t>(m, acc, pool, q0, q0 + PSEG, seed, nullptr, false, true);
   uint16_t *mo = maps + (uint64_t)g * WINDOW;
   for (int k = threadIdx.x; k < (int)WINDOW; k += PROP_THREADS) mo[k] = m[k];
 }
 
-__global__ __launch_bounds__(PROP_THREADS) void k_prop_chain(const uint32_t *acc_pos, uint32_t n,
-                                                             const uint16_t *__restrict__ maps,
+__global__ __launch_bounds__(PROP_THREADS) void k_prop_chain(const uint32_t *acc_pos, uint32_t n, const AccEntry *acc,
+                                                             const uint16_t *__restrict__ maps, const uint8_t *seed,
                                                              uint8_t *__restrict__ segwin) {
   __shared__ uint8_t w[WINDOW];
   const uint32_t A = acc_pos[n];
   const int tid = (int)threadIdx.x;
-  for (int k = tid; k < (int)WINDOW; k += PROP_THREADS) w[k] = 0;
+  // the first accepted chunk's window: carried in, or none
+  const uint8_t *w0 = A > 0 && (acc[0].pad & 2u) ? seed + (uint64_t)acc[0].chunk * WINDOW : nullptr;
+  for (int k = tid; k < (int)WINDOW; k += PROP_THREADS) w[k] = w0 ? w0[k] : (uint8_t)0;
   __syncthreads();
   const uint32_t S = (A + PSEG - 1) / PSEG;
   for (uint32_t g = 0; g < S; g++) {
@@ -1308,7 +1329,7 @@ __global__ __launch_bounds__(PROP_THREADS) void k_prop_apply(const uint32_t *acc
   const uint8_t *wi = segwin + (uint64_t)g * WINDOW;
   for (int k = threadIdx.x; k < (int)WINDOW; k += PROP_THREADS) w[k] = wi[k];
   __syncthreads();
-  prop_steps<uint8_t>(w, acc, pool, q0, min(q0 + PSEG, A), wins, true, false);
+  prop_steps<uint8_t>(w, acc, pool, q0, min(q0 + PSEG, A), wins, wins, true, false);
 }
 
 // ---------------------------------------------------------------------------
@@ -1353,7 +1374,9 @@ __global__ __launch_bounds__(1024) void k_tilescan(const ChunkDesc *chunks, cons
         // read (their length may exceed what was stored)
         e.len = fs[chunks[j].file].status == ST_OK ? cs[j].len : 0;
         e.chunk = j;
-        e.pad = (chunks[j].flags & CF_FIRST) ? 1u : 0u;  // the chain restarts at a file's first chunk
+        // the chain restarts at a file's first chunk, from the carried window
+        // of a segment or from nothing
+        e.pad = ((chunks[j].flags & CF_FIRST) ? 1u : 0u) | ((chunks[j].flags & CF_CARRIED) ? 2u : 0u);
         acc[ap] = e;
       }
     }
@@ -1557,10 +1580,35 @@ __global__ __launch_bounds__(256) void k_crc_final(const FileDesc *files, uint32
   for (uint32_t f = threadIdx.x; f < n_files; f += blockDim.x) {
     if (fs[f].status != ST_OK) continue;
     const uint64_t L = fs[f].out_len;
-    const uint32_t crc = fs[f].crc_acc ^ gf_mul(0xFFFFFFFFu, gf_xpow8(L, xpow)) ^ 0xFFFFFFFFu;
+    // the register after the earlier bytes is the complement of their CRC
+    // (all ones for none), carried over this segment's L bytes
+    const uint32_t crc = fs[f].crc_acc ^ gf_mul(~files[f].crc_in, gf_xpow8(L, xpow)) ^ 0xFFFFFFFFu;
     fs[f].crc_out = crc;
+    if (!fs[f].is_final) continue;
     if (crc != files[f].crc) fs[f].status = ST_CRC;
     else if (fs[f].size_bad) fs[f].status = ST_SIZE;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// k_carry: the window after a segment (bounded-memory streaming): the last
+// 32768 bytes of (the carried window ++ the segment's output), bytes before
+// the member's start as zero.  One workgroup; `dst` is not the carried slot.
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(1024) void k_carry(const FileDesc *files, const FileState *fs, const uint8_t *wins,
+                                                uint8_t *__restrict__ dst) {
+  const FileDesc fd = files[0];
+  if (fs[0].status != ST_OK) return;
+  const int64_t L = (int64_t)fs[0].out_len;
+  const uint8_t *old = wins + (uint64_t)fd.first_chunk * WINDOW;
+  const int64_t lim = (int64_t)WINDOW - (int64_t)fd.win_valid;
+  for (int k = threadIdx.x; k < (int)WINDOW; k += blockDim.x) {
+    const int64_t pos = L - (int64_t)WINDOW + k;  // position in the segment's output
+    uint8_t b = 0;
+    if (pos >= 0) b = fd.out[pos];
+    else if ((int64_t)WINDOW + pos >= lim) b = old[WINDOW + pos];
+    dst[k] = b;
   }
 }
 
@@ -1674,12 +1722,17 @@ hipError_t gzk_tilescan(const ChunkDesc *chunks, const ChunkState *cs, const Fil
 hipError_t gzk_propagate(uint32_t n, const uint32_t *acc_pos, const AccEntry *acc, uint8_t *wins, const uint16_t *pool,
                          uint16_t *maps, uint8_t *segwin, hipStream_t st) {
   const uint32_t smax = (n + PSEG - 1) / PSEG;
-  hipLaunchKernelGGL(k_prop_maps, dim3(smax), dim3(PROP_THREADS), 0, st, acc_pos, n, acc, pool, maps);
+  hipLaunchKernelGGL(k_prop_maps, dim3(smax), dim3(PROP_THREADS), 0, st, acc_pos, n, acc, pool, wins, maps);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_prop_chain, dim3(1), dim3(PROP_THREADS), 0, st, acc_pos, n, maps, segwin);
+  hipLaunchKernelGGL(k_prop_chain, dim3(1), dim3(PROP_THREADS), 0, st, acc_pos, n, acc, maps, wins, segwin);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(k_prop_apply, dim3(smax), dim3(PROP_THREADS), 0, st, acc_pos, n, acc, pool, segwin, wins);
+  return hipGetLastError();
+}
+
+hipError_t gzk_carry(const FileDesc *files, const FileState *fs, const uint8_t *wins, uint8_t *dst, hipStream_t st) {
+  hipLaunchKernelGGL(k_carry, dim3(1), dim3(1024), 0, st, files, fs, wins, dst);
   return hipGetLastError();
 }
 

@@ -127,3 +127,78 @@ def padded(comp: bytes):
     store = np.zeros(len(comp) + (-len(comp)) % 8 + 8, dtype=np.uint8)
     store[: len(comp)] = np.frombuffer(bytes(comp), dtype=np.uint8)
     return store
+
+
+class StreamInfo(C.Structure):
+    _fields_ = [("ws_bytes", C.c_uint64), ("out_bytes", C.c_uint64), ("segment_bytes", C.c_uint64),
+                ("payload_start", C.c_uint64), ("payload_end", C.c_uint64), ("crc32", C.c_uint32),
+                ("isize", C.c_uint32)]
+
+
+class SegmentResult(C.Structure):
+    _fields_ = [("status", C.c_int32), ("done", C.c_uint32), ("out_len", C.c_uint64), ("out_total", C.c_uint64),
+                ("start_bit", C.c_uint64), ("end_bit", C.c_uint64), ("out_needed", C.c_uint64),
+                ("ws_needed", C.c_uint64), ("crc32", C.c_uint32), ("n_chunks", C.c_uint32),
+                ("n_repairs", C.c_uint32), ("n_retries", C.c_uint32)]
+
+
+class Checkpoint(C.Structure):
+    _fields_ = [("bit", C.c_uint64), ("out_total", C.c_uint64), ("crc32", C.c_uint32), ("valid", C.c_uint32),
+                ("done", C.c_uint32), ("pad", C.c_uint32), ("window", C.c_uint8 * 32768)]
+
+
+def stream_lib():
+    L = lib()
+    vp = C.c_void_p
+    L.gz_stream_open.argtypes = [C.POINTER(vp), vp, C.c_size_t, C.c_uint64, C.POINTER(Opts)]
+    L.gz_stream_get_info.argtypes = [vp, C.POINTER(StreamInfo)]
+    L.gz_stream_next.argtypes = [vp, vp, C.c_size_t, vp, C.c_size_t, vp]
+    L.gz_stream_wait.argtypes = [vp, C.POINTER(SegmentResult)]
+    L.gz_stream_checkpoint.argtypes = [vp, C.POINTER(Checkpoint)]
+    L.gz_stream_resume.argtypes = [vp, C.POINTER(Checkpoint)]
+    L.gz_stream_destroy.argtypes = [vp]
+    L.gz_stream_destroy.restype = None
+    return L
+
+
+def stream_run(comp: bytes, segment_bytes: int, resume=None, stop_after=None, **opts):
+    """Decode through gz_stream_*: returns (segments: list of (SegmentResult
+    dict, bytes, Checkpoint after it)).  resume: a Checkpoint to start from;
+    stop_after: number of segments to run."""
+    L = stream_lib()
+    L.emu_set_sync_limit(3_000_000_000)
+    store = padded(comp)
+    buf = store[: len(comp)]
+    o = Opts()
+    for k, v in opts.items():
+        setattr(o, k, v)
+    h = C.c_void_p()
+    st = L.gz_stream_open(C.byref(h), C.c_void_p(buf.ctypes.data), buf.size, segment_bytes, C.byref(o))
+    assert st == 0, st
+    if resume is not None:
+        assert L.gz_stream_resume(h, C.byref(resume)) == 0
+    segs = []
+    try:
+        while stop_after is None or len(segs) < stop_after:
+            info = StreamInfo()
+            assert L.gz_stream_get_info(h, C.byref(info)) == 0
+            raw_ws = np.zeros(info.ws_bytes + 512, dtype=np.uint8)
+            off = (-raw_ws.ctypes.data) % 256
+            ws = raw_ws[off:off + info.ws_bytes]
+            out = np.zeros(max(1, info.out_bytes), dtype=np.uint8)
+            st = L.gz_stream_next(h, C.c_void_p(out.ctypes.data), out.size, C.c_void_p(ws.ctypes.data), ws.size,
+                                  None)
+            if st != 0:
+                segs.append(({"next_status": st}, b"", None))
+                break
+            r = SegmentResult()
+            assert L.gz_stream_wait(h, C.byref(r)) == 0
+            d = {k: getattr(r, k) for k, _ in r._fields_}
+            cp = Checkpoint()
+            assert L.gz_stream_checkpoint(h, C.byref(cp)) == 0
+            segs.append((d, out[: r.out_len].tobytes() if r.status == 0 else b"", cp))
+            if r.status != 0 or r.done:
+                break
+    finally:
+        L.gz_stream_destroy(h)
+    return segs

@@ -64,6 +64,45 @@ def test_struct_sizes_match_header(libpath):
     assert ctypes.sizeof(gz.Job) == 8 + 8 + 4 + 4 + 8 + 8
     assert ctypes.sizeof(gz.Info) == 8 * 3 + 4 * 4
     assert ctypes.sizeof(gz.Result) == 4 + 4 + 8 * 3 + 4 * 4 + 8 * 3 + 4 + 4
+    assert ctypes.sizeof(gz.StreamInfo) == 8 * 5 + 4 * 2
+    assert ctypes.sizeof(gz.SegmentResult) == 4 + 4 + 8 * 6 + 4 * 4
+    assert ctypes.sizeof(gz.Checkpoint) == 8 * 2 + 4 * 4 + 32768
+
+
+def test_struct_layout_matches_c_compiler(tmp_path):
+    """sizeof and every field offset of the public structs, as gcc lays them
+    out from the header, equal the ctypes declarations of the binding."""
+    import shutil
+    import subprocess
+
+    import paper_1905_07224_amd as gz
+
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"gz_opts": gz.Opts, "gz_job": gz.Job, "gz_info": gz.Info, "gz_result": gz.Result,
+               "gz_server_opts": gz.ServerOpts, "gz_done": gz.Done, "gz_server_info": gz.ServerInfo,
+               "gz_stream_info": gz.StreamInfo, "gz_segment_result": gz.SegmentResult,
+               "gz_checkpoint": gz.Checkpoint}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "gzgpu.h"', "int main(void) {"]
+    for cname, cls in structs.items():
+        lines.append(f'  printf("{cname} sizeof %zu\\n", sizeof({cname}));')
+        for f in cls._fields_:
+            lines.append(f'  printf("{cname} {f[0]} %zu\\n", offsetof({cname}, {f[0]}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = {}
+    for line in subprocess.check_output([str(exe)]).decode().split("\n"):
+        if line:
+            a, b, c = line.split()
+            got[(a, b)] = int(c)
+    for cname, cls in structs.items():
+        assert got[(cname, "sizeof")] == ctypes.sizeof(cls), cname
+        for f in cls._fields_:
+            assert got[(cname, f[0])] == getattr(cls, f[0]).offset, (cname, f[0])
 
 
 def test_output_size_guess_uses_isize_modulus():

@@ -187,3 +187,72 @@ def test_emu_deferred_confirmation_paths(orc, decode):
             assert np.array_equal(_starts(tab), ref.start)
         else:
             assert st != 0, (flip, ref.reason)
+
+
+def _stream_expect(g, start_bit, seg):
+    """From the oracle's block map: the block where a segment starting at
+    start_bit stops (the first block at or past start_bit + 8 * seg), as
+    (bit, output offset), or None for the end of the member."""
+    stop = start_bit + 8 * seg
+    later = np.nonzero(g.block_bit >= stop)[0]
+    if len(later) == 0:
+        return None
+    i = int(later[0])
+    return int(g.block_bit[i]), int(g.block_out_off[i])
+
+
+@pytest.mark.parametrize("seg", [9000, 23456])
+def test_emu_stream_segments(orc, seg):
+    raw = synth.fastq_like(200 << 10, 311)
+    comp = synth.gzip_member(raw, 6, segment_bytes=20 << 10)
+    g = orc.gunzip(comp)
+    assert g.status == orc.OK
+    segs = E.stream_run(comp, seg, chunk_bytes=4096)
+    assert len(segs) >= 2
+    got = b""
+    bit = 8 * g.payload_start
+    for i, (d, data, cp) in enumerate(segs):
+        assert d["status"] == 0, d
+        assert d["start_bit"] == bit
+        got += data
+        exp = _stream_expect(g, bit, seg)
+        if exp is None:
+            assert d["done"] == 1 and i == len(segs) - 1
+            assert d["end_bit"] == g.end_bit
+        else:
+            assert d["done"] == 0
+            assert (d["end_bit"], d["out_total"]) == exp
+        assert d["out_total"] == len(got)
+        assert d["crc32"] == zlib.crc32(raw[: len(got)])
+        # the checkpoint: position, running CRC, and the window before it
+        assert cp.bit == d["end_bit"] and cp.out_total == len(got) and cp.crc32 == d["crc32"]
+        v = min(len(got), 32768)
+        assert cp.valid == v
+        w = bytes(cp.window)
+        assert w[32768 - v:] == raw[len(got) - v: len(got)] and w[: 32768 - v] == bytes(32768 - v)
+        bit = d["end_bit"]
+    assert got == raw
+
+
+def test_emu_stream_resume_and_checks(orc):
+    raw = synth.word_stream(240 << 10, 312)
+    comp = synth.gzip_member(raw, 6)
+    full = E.stream_run(comp, 6000, chunk_bytes=2048)
+    assert len(full) >= 3
+    assert all(d["status"] == 0 for d, _, _ in full) and b"".join(x for _, x, _ in full) == raw
+    # resume from the checkpoint after the second segment in a new stream
+    cp = full[1][2]
+    assert not cp.done
+    rest = E.stream_run(comp, 6000, resume=cp, chunk_bytes=2048)
+    assert b"".join(x for _, x, _ in rest) == b"".join(x for _, x, _ in full[2:])
+    assert rest[-1][0]["crc32"] == zlib.crc32(raw) and rest[-1][0]["done"] == 1
+    # one segment covering the whole member equals the plain path
+    one = E.stream_run(comp, 1 << 30, chunk_bytes=4096)
+    assert len(one) == 1 and one[0][1] == raw and one[0][0]["done"] == 1
+    # a wrong trailer CRC fails only the last segment, as the oracle fails the member
+    bad = bytearray(comp)
+    bad[-8] ^= 1
+    assert orc.gunzip(bytes(bad)).status != orc.OK
+    segs = E.stream_run(bytes(bad), 6000, chunk_bytes=2048)
+    assert [d["status"] for d, _, _ in segs[:-1]] == [0] * (len(segs) - 1)
+    assert segs[-1][0]["status"] == -6
