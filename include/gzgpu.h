@@ -245,7 +245,7 @@ typedef struct gz_checkpoint {
   uint32_t crc32;          /* CRC-32 of those bytes */
   uint32_t valid;          /* real history bytes at the end of window: min(out_total, 32768) */
   uint32_t done;           /* the member is finished */
-  uint32_t pad;
+  uint32_t flags;          /* 1: a stream opened inside the member (gz_stream_open_at); valid is 32768 */
   uint8_t window[32768];   /* the 32768 bytes before `bit` (the first 32768 - valid are zero) */
 } gz_checkpoint;
 
@@ -273,6 +273,49 @@ int gz_stream_checkpoint(gz_stream_t stream, gz_checkpoint *cp);
  * min(out_total, 32768)), GZ_E_HIP. */
 int gz_stream_resume(gz_stream_t stream, const gz_checkpoint *cp);
 void gz_stream_destroy(gz_stream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Random access (Section IV).  Decoding from inside a member needs a block
+ * start and the 32 KiB context before it (Section IV-A).  The start is
+ * found by the block-start checks of Section VI-A and Appendix A; the
+ * context is taken as undetermined (Section IV-B): 32768 copies of a marker
+ * byte, which matches then copy forward exactly as they would copy the true
+ * bytes, so every output byte equal to the marker is undetermined (choose a
+ * marker absent from the data, e.g. 0 or 255 for text).  The share of
+ * markers per window of the output is the measurement of Section IV-C and
+ * Fig. 2.
+ * ------------------------------------------------------------------------ */
+
+/* Plan n_probes block-start searches in one gzip member: probe i looks for
+ * the first bit b in [bits[i], bits[i] + 8 * range_bytes) (clipped to the
+ * payload) that passes the static checks, the trial block and the five
+ * confirmation blocks (Appendix A).  bits are counted from the start of the
+ * .gz file and must lie in the payload.  range_bytes 0: 1 MiB.  The
+ * workspace size is gz_plan_info's ws_bytes.  Errors: GZ_E_ARG, GZ_E_HEADER,
+ * GZ_E_HIP. */
+int gz_plan_probes(gz_plan_t *plan, const void *d_comp, size_t comp_len, const uint64_t *bits, int n_probes,
+                   uint64_t range_bytes, const gz_opts *opts);
+/* Enqueue the searches of a probe plan (one wave per probe, all at once). */
+int gz_find_blocks(gz_plan_t plan, void *d_ws, size_t ws_bytes, void *stream);
+/* Wait and copy each probe's block start (all-ones where none passed in
+ * its range) and the candidates it rejected after the static checks. */
+int gz_probe_starts(gz_plan_t plan, uint64_t *start_bits, uint32_t *n_retries);
+
+/* A stream (see gz_stream_open) that starts at block_bit, a block start
+ * inside the member (e.g. from gz_probe_starts), with the undetermined
+ * context of `marker` bytes.  Its segments carry windows as any stream; the
+ * trailer's CRC-32 and ISIZE are not checked (the bytes before block_bit are
+ * not decoded).  Errors: as gz_stream_open, and GZ_E_ARG for a bit outside
+ * the payload or a marker above 255. */
+int gz_stream_open_at(gz_stream_t *stream, const void *d_comp, size_t comp_len, uint64_t block_bit, uint32_t marker,
+                      uint64_t segment_bytes, const gz_opts *opts);
+
+/* Enqueue: d_counts[(first + i) / window] += (d_buf[i] == value) for i < n,
+ * windows at or past n_counts not counted (device buffers; the counts are
+ * added to, so consecutive segments can share one array).  Errors: GZ_E_ARG
+ * (window 0, value above 255), GZ_E_HIP. */
+int gz_count_byte(const void *d_buf, uint64_t n, uint32_t value, uint64_t first, uint64_t window, uint64_t *d_counts,
+                  uint64_t n_counts, void *stream);
 
 /* ------------------------------------------------------------------------
  * Serving loop (beyond the paper's one-file setting): jobs arrive one at a

@@ -104,7 +104,7 @@ class SegmentResult(C.Structure):
 
 class Checkpoint(C.Structure):
     _fields_ = [("bit", C.c_uint64), ("out_total", C.c_uint64), ("crc32", C.c_uint32), ("valid", C.c_uint32),
-                ("done", C.c_uint32), ("pad", C.c_uint32), ("window", C.c_uint8 * 32768)]
+                ("done", C.c_uint32), ("flags", C.c_uint32), ("window", C.c_uint8 * 32768)]
 
 
 _lib = None
@@ -113,7 +113,8 @@ EXPORTS = ["gz_plan", "gz_plan_batch", "gz_plan_info", "gz_decompress", "gz_deco
            "gz_chunk_table", "gz_debug_layout", "gz_plan_destroy", "gz_strerror", "gz_device_info", "gz_pass_times",
            "gz_pass_name", "gz_decompress_graph", "gz_autotune", "gz_server_create", "gz_server_submit",
            "gz_server_poll", "gz_server_stats", "gz_server_destroy", "gz_stream_open", "gz_stream_get_info",
-           "gz_stream_next", "gz_stream_wait", "gz_stream_checkpoint", "gz_stream_resume", "gz_stream_destroy"]
+           "gz_stream_next", "gz_stream_wait", "gz_stream_checkpoint", "gz_stream_resume", "gz_stream_destroy",
+           "gz_plan_probes", "gz_find_blocks", "gz_probe_starts", "gz_stream_open_at", "gz_count_byte"]
 GZ_N_PASSES = N_PASSES = 13
 # defaults of gz_opts (include/gzgpu.h)
 DEFAULT_CHUNK_BYTES = 48 << 10
@@ -162,6 +163,11 @@ def lib():
         L.gz_stream_resume.argtypes = [vp, C.POINTER(Checkpoint)]
         L.gz_stream_destroy.argtypes = [vp]
         L.gz_stream_destroy.restype = None
+        L.gz_plan_probes.argtypes = [C.POINTER(vp), vp, C.c_size_t, vp, i32, u64, C.POINTER(Opts)]
+        L.gz_find_blocks.argtypes = [vp, vp, C.c_size_t, vp]
+        L.gz_probe_starts.argtypes = [vp, vp, vp]
+        L.gz_stream_open_at.argtypes = [C.POINTER(vp), vp, C.c_size_t, u64, C.c_uint32, u64, C.POINTER(Opts)]
+        L.gz_count_byte.argtypes = [vp, u64, C.c_uint32, u64, u64, vp, u64, vp]
         for name in EXPORTS:
             if name not in ("gz_plan_destroy", "gz_strerror", "gz_pass_name", "gz_server_destroy",
                             "gz_stream_destroy"):
@@ -535,14 +541,22 @@ class Stream:
     workspace sized for one segment; the carried window stays on the device.
     checkpoint() / resume() save and restore the position."""
 
-    def __init__(self, comp, segment_bytes: int = 0, stream=None, **opts):
+    def __init__(self, comp, segment_bytes: int = 0, stream=None, at_bit: int | None = None, marker: int = 0,
+                 **opts):
+        """at_bit: start at this block start inside the member (random access)
+        with an undetermined context of `marker` bytes."""
         self.comp = _as_device_bytes(comp)
         self.device = self.comp.device
         self.stream = stream
         self._h = C.c_void_p()
         with torch.cuda.device(self.device):
-            _check(lib().gz_stream_open(C.byref(self._h), C.c_void_p(self.comp.data_ptr()), self.comp.numel(),
-                                        int(segment_bytes), C.byref(_opts(**opts))))
+            if at_bit is None:
+                _check(lib().gz_stream_open(C.byref(self._h), C.c_void_p(self.comp.data_ptr()), self.comp.numel(),
+                                            int(segment_bytes), C.byref(_opts(**opts))))
+            else:
+                _check(lib().gz_stream_open_at(C.byref(self._h), C.c_void_p(self.comp.data_ptr()),
+                                               self.comp.numel(), int(at_bit), int(marker), int(segment_bytes),
+                                               C.byref(_opts(**opts))))
         self._ws = None
         self._out = None
         self.done = False
@@ -622,3 +636,73 @@ def decompress_stream(comp, segment_bytes: int = 0, stream=None, **opts) -> torc
     parts = [seg.clone() for seg in s]
     s.close()
     return torch.cat(parts) if parts else torch.empty(0, dtype=torch.uint8, device=s.device)
+
+
+def find_blocks(comp, bits, range_bytes: int = 0, stream=None, **opts):
+    """Block starts at or after each bit offset (gz_plan_probes /
+    gz_find_blocks): a list of ints, None where no start passed the checks
+    within range_bytes; and the candidates each probe rejected."""
+    import numpy as np
+
+    comp = _as_device_bytes(comp)
+    b = np.ascontiguousarray(np.asarray(bits, dtype=np.uint64))
+    h = C.c_void_p()
+    with torch.cuda.device(comp.device):
+        _check(lib().gz_plan_probes(C.byref(h), C.c_void_p(comp.data_ptr()), comp.numel(),
+                                    C.c_void_p(b.ctypes.data), int(b.size), int(range_bytes),
+                                    C.byref(_opts(**opts))))
+        try:
+            info = Info()
+            _check(lib().gz_plan_info(h, C.byref(info)))
+            ws = torch.empty(info.ws_bytes, dtype=torch.uint8, device=comp.device)
+            _check(lib().gz_find_blocks(h, C.c_void_p(ws.data_ptr()), ws.numel(), _stream_handle(stream)))
+            starts = np.zeros(b.size, dtype=np.uint64)
+            rej = np.zeros(b.size, dtype=np.uint32)
+            _check(lib().gz_probe_starts(h, C.c_void_p(starts.ctypes.data), C.c_void_p(rej.ctypes.data)))
+        finally:
+            lib().gz_plan_destroy(h)
+    return [None if int(x) == NONE else int(x) for x in starts], [int(x) for x in rej]
+
+
+def count_byte(buf: torch.Tensor, value: int, window: int, counts: torch.Tensor, first: int = 0, stream=None):
+    """counts[(first + i) // window] += (buf[i] == value) on the device (gz_count_byte);
+    counts is an int64 device tensor."""
+    if counts.dtype != torch.int64 or not counts.is_cuda or not counts.is_contiguous():
+        raise ValueError("counts must be a contiguous int64 device tensor")
+    with torch.cuda.device(buf.device):
+        _check(lib().gz_count_byte(C.c_void_p(buf.data_ptr()), buf.numel(), int(value), int(first), int(window),
+                                   C.c_void_p(counts.data_ptr()), counts.numel(), _stream_handle(stream)))
+
+
+def undetermined_profile(comp, bit: int, window: int, marker: int = 0, segment_bytes: int = 0,
+                         max_out: int | None = None, range_bytes: int = 0, **opts):
+    """Random access at `bit` (Section IV): the first block start at or after
+    it, then decoding to the end of the member (or max_out bytes) with an
+    undetermined context.  Returns (block start, decoded bytes, undetermined
+    bytes per window of `window` bytes as an int64 numpy array)."""
+    comp = _as_device_bytes(comp)
+    starts, _ = find_blocks(comp, [bit], range_bytes, **opts)
+    if starts[0] is None:
+        raise GzError(GZ_E_DATA, "no block start passed the checks in the probe's range")
+    s = Stream(comp, segment_bytes, at_bit=starts[0], marker=marker, **opts)
+    limit = max_out if max_out is not None else (1 << 62)
+    cap = 1 << 16
+    counts = torch.zeros(cap, dtype=torch.int64, device=comp.device)
+    total = 0
+    try:
+        for part in s:
+            part = part[: max(0, limit - total)]
+            need = (total + part.numel() + window - 1) // window
+            if need > counts.numel():
+                grown = torch.zeros(max(need, 2 * counts.numel()), dtype=torch.int64, device=comp.device)
+                grown[: counts.numel()] = counts
+                counts = grown
+            count_byte(part, marker, window, counts, first=total)
+            total += part.numel()
+            if total >= limit:
+                break
+    finally:
+        s.close()
+    torch.cuda.synchronize()
+    n_win = (total + window - 1) // window
+    return starts[0], total, counts[:n_win].cpu().numpy()

@@ -40,6 +40,8 @@ hipError_t gzk_propagate(uint32_t, const uint32_t *, const AccEntry *, uint8_t *
 hipError_t gzk_translate(uint32_t, const FileDesc *, const ChunkDesc *, const ChunkState *, FileState *,
                          const uint64_t *, uint32_t, const uint8_t *, const uint16_t *, Counters *, hipStream_t);
 hipError_t gzk_carry(const FileDesc *, const FileState *, const uint8_t *, uint8_t *, hipStream_t);
+hipError_t gzk_count_byte(const uint8_t *, uint64_t, uint32_t, uint64_t, uint64_t, unsigned long long *, uint64_t,
+                          hipStream_t);
 }
 
 namespace {
@@ -167,9 +169,13 @@ struct gz_plan_s {
     bool on = false;
     uint64_t start_bit = 0, stop_bit = NONE, out_before = 0;
     uint32_t crc_in = 0, win_valid = 0;
+    uint32_t mode = 0;    // FD_NOCHECK: the stream began inside the member
     int64_t h = 0;        // payload start byte
     uint32_t crc = 0, isize = 0;
   } seg;
+  // block-start probes (gz_plan_probes): file f searches [lo, hi) of the one input
+  bool probe = false;
+  std::vector<uint64_t> probe_lo, probe_hi;
 };
 
 // Header and trailer of the member at j.d_comp: payload start, CRC-32, ISIZE.
@@ -213,13 +219,16 @@ static int plan_common(gz_plan_t p) {
     const gz_job &j = p->jobs[f];
     int64_t h = 0;
     uint32_t crc = 0, isize = 0;
-    if (p->seg.on) {
+    if (p->seg.on || (p->probe && f > 0)) {
       h = p->seg.h;
       crc = p->seg.crc;
       isize = p->seg.isize;
     } else {
       const int r = read_member(j, f, &h, &crc, &isize);
       if (r != GZ_OK) return r;
+      p->seg.h = h;
+      p->seg.crc = crc;
+      p->seg.isize = isize;
     }
     FileDesc fd{};
     fd.comp = (const uint8_t *)j.d_comp;
@@ -233,6 +242,25 @@ static int plan_common(gz_plan_t p) {
     fd.stop_bit = NONE;
     // chunks cut the bytes [lo, hi): the payload, or a segment's range
     uint64_t lo = (uint64_t)h, hi = fd.trailer_byte, margin = 0;
+    if (p->probe) {
+      // one chunk searching [probe_lo, probe_hi) bits; it decodes one block
+      // and its confirmation
+      fd.mode = FD_PROBE;
+      fd.stop_bit = p->probe_hi[f];
+      fd.first_chunk = (uint32_t)p->chunks.size();
+      fd.n_chunks = 1;
+      ChunkDesc cd{};
+      cd.lo_bit = p->probe_lo[f];
+      cd.hi_bit = p->probe_hi[f];
+      cd.file = f;
+      p->chunks.push_back(cd);
+      fd.pool_base = sym_elems;
+      fd.pool_elems = (uint64_t)p->opts.sym_factor * (STOP_MARGIN_BYTES + 1) + SYM_SLACK + FLUSH_UNIT;
+      sym_elems += align_up(fd.pool_elems, FLUSH_UNIT);
+      p->span.push_back(STOP_MARGIN_BYTES + 1);
+      p->files.push_back(fd);
+      continue;
+    }
     if (p->seg.on) {
       fd.payload_bit = p->seg.start_bit;
       lo = (p->seg.start_bit + 7) / 8;
@@ -244,6 +272,7 @@ static int plan_common(gz_plan_t p) {
       fd.out_before = p->seg.out_before;
       fd.crc_in = p->seg.crc_in;
       fd.win_valid = p->seg.win_valid;
+      fd.mode = p->seg.mode;
     }
     const uint64_t P = hi > lo ? hi - lo : 1;
     uint64_t N = j.n_chunks > 0 ? (uint64_t)j.n_chunks : (P + p->opts.chunk_bytes - 1) / p->opts.chunk_bytes;
@@ -377,6 +406,79 @@ int gz_plan_batch(gz_plan_t *plan, const gz_job *jobs, int n_jobs, const gz_opts
   return make_plan(plan, jobs, n_jobs, opts);
 }
 
+static int launch(gz_plan_t p, uint8_t *ws, size_t ws_bytes, hipStream_t st);
+static int fetch(gz_plan_t p);
+
+int gz_plan_probes(gz_plan_t *plan, const void *d_comp, size_t comp_len, const uint64_t *bits, int n_probes,
+                   uint64_t range_bytes, const gz_opts *opts) {
+  if (!plan || !d_comp || comp_len == 0 || !bits || n_probes <= 0) return GZ_E_ARG;
+  *plan = nullptr;
+  gz_job j{};
+  j.d_comp = d_comp;
+  j.comp_len = comp_len;
+  int64_t h = 0;
+  uint32_t crc = 0, isize = 0;
+  int r = read_member(j, 0, &h, &crc, &isize);
+  if (r != GZ_OK) return r;
+  const uint64_t lo_ok = 8ull * (uint64_t)h, hi_ok = 8ull * (comp_len - 8);
+  const uint64_t range = range_bytes ? range_bytes : (1ull << 20);
+  gz_plan_t p = new (std::nothrow) gz_plan_s();
+  if (!p) return GZ_E_ARG;
+  fill_defaults(p, opts);
+  if (p->win != 2048 && p->win != 4096 && p->win != 8192 && p->win != 16384 && p->win != 32768) {
+    gz_plan_destroy(p);
+    return GZ_E_ARG;
+  }
+  p->probe = true;
+  p->seg.h = h;
+  p->seg.crc = crc;
+  p->seg.isize = isize;
+  for (int i = 0; i < n_probes; i++) {
+    if (bits[i] < lo_ok || bits[i] >= hi_ok) {
+      snprintf(g_err, sizeof(g_err), "probe %d: bit %llu is outside the payload", i, (unsigned long long)bits[i]);
+      gz_plan_destroy(p);
+      return GZ_E_ARG;
+    }
+    p->probe_lo.push_back(bits[i]);
+    p->probe_hi.push_back(std::min<uint64_t>(hi_ok, bits[i] + 8 * range));
+  }
+  p->jobs.assign((size_t)n_probes, j);
+  r = plan_common(p);
+  if (r != GZ_OK) {
+    gz_plan_destroy(p);
+    return r;
+  }
+  (void)hipEventCreateWithFlags(&p->upload_done, hipEventDisableTiming);
+  *plan = p;
+  return GZ_OK;
+}
+
+int gz_find_blocks(gz_plan_t p, void *d_ws, size_t ws_bytes, void *stream) {
+  if (!p || !p->probe) return GZ_E_ARG;
+  return launch(p, (uint8_t *)d_ws, ws_bytes, (hipStream_t)stream);
+}
+
+int gz_probe_starts(gz_plan_t p, uint64_t *start_bits, uint32_t *n_retries) {
+  if (!p || !p->probe || !start_bits) return GZ_E_ARG;
+  const int r = fetch(p);
+  if (r != GZ_OK) return r;
+  for (size_t f = 0; f < p->files.size(); f++) {
+    const ChunkState &c = p->cst[p->files[f].first_chunk];
+    const bool ok = c.start != NONE && c.status == ST_OK && !(c.flags & CS_UNCONFIRMED);
+    start_bits[f] = ok ? c.start : NONE;
+    if (n_retries) n_retries[f] = c.retries;
+  }
+  return GZ_OK;
+}
+
+int gz_count_byte(const void *d_buf, uint64_t n, uint32_t value, uint64_t first, uint64_t window,
+                  uint64_t *d_counts, uint64_t n_counts, void *stream) {
+  if ((!d_buf && n) || value > 255 || window == 0 || (!d_counts && n_counts)) return GZ_E_ARG;
+  hipError_t e = gzk_count_byte((const uint8_t *)d_buf, n, value, first, window, (unsigned long long *)d_counts,
+                                n_counts, (hipStream_t)stream);
+  return e == hipSuccess ? GZ_OK : hip_fail(e, "count");
+}
+
 int gz_plan_info(gz_plan_t p, gz_info *info) {
   if (!p || !info) return GZ_E_ARG;
   memset(info, 0, sizeof(*info));
@@ -464,6 +566,15 @@ static int launch(gz_plan_t p, uint8_t *ws, size_t ws_bytes, hipStream_t st) {
   mark();
   if ((e = gzk_redo((int)p->win, grid, files, chunks, cs, N, ctr, pool, st)) != hipSuccess) return hip_fail(e, "redo");
   mark();
+  if (p->probe) {
+    // block-start probes end with their confirmed starts
+    p->timed = false;
+    p->ws = ws;
+    p->stream = st;
+    p->launched = true;
+    p->fetched = false;
+    return GZ_OK;
+  }
   if ((e = gzk_stitch((int)p->win, grid, files, chunks, cs, N, ctr, pool, st)) != hipSuccess)
     return hip_fail(e, "stitch");
   mark();
@@ -501,7 +612,7 @@ static void drop_graph(gz_plan_t p) {
 }
 
 int gz_decompress(gz_plan_t p, void *d_out, size_t out_cap, void *d_ws, size_t ws_bytes, void *stream) {
-  if (!p || p->files.size() != 1) return GZ_E_ARG;
+  if (!p || p->files.size() != 1 || p->probe) return GZ_E_ARG;
   if (!d_out && out_cap) return GZ_E_ARG;
   p->files[0].out = (uint8_t *)d_out;
   p->files[0].out_cap = d_out ? out_cap : 0;
@@ -509,12 +620,12 @@ int gz_decompress(gz_plan_t p, void *d_out, size_t out_cap, void *d_ws, size_t w
 }
 
 int gz_decompress_batch(gz_plan_t p, void *d_ws, size_t ws_bytes, void *stream) {
-  if (!p) return GZ_E_ARG;
+  if (!p || p->probe) return GZ_E_ARG;
   return launch(p, (uint8_t *)d_ws, ws_bytes, (hipStream_t)stream);
 }
 
 int gz_decompress_graph(gz_plan_t p, void *d_ws, size_t ws_bytes, void *stream) {
-  if (!p || !stream || p->opts.timing) return GZ_E_ARG;
+  if (!p || !stream || p->opts.timing || p->probe) return GZ_E_ARG;
   if (!d_ws || ws_bytes < p->lay.total || ((uintptr_t)d_ws & 255u)) {
     snprintf(g_err, sizeof(g_err), "workspace needs %llu bytes, 256-byte aligned",
              (unsigned long long)p->lay.total);
@@ -846,6 +957,7 @@ struct gz_stream_s {
   bool done = false;
   gz_plan_t cur = nullptr;   // plan of the segment in flight
   bool pending = false;
+  bool inside = false;       // opened at a block inside the member (gz_stream_open_at)
 };
 
 static int segment_plan(gz_stream_t s, uint64_t start_bit, uint32_t win_valid, void *d_out, uint64_t out_cap,
@@ -860,6 +972,7 @@ static int segment_plan(gz_stream_t s, uint64_t start_bit, uint32_t win_valid, v
   p->seg.out_before = s->out_total;
   p->seg.crc_in = s->crc_run;
   p->seg.win_valid = win_valid;
+  p->seg.mode = s->inside ? FD_NOCHECK : 0u;
   p->seg.h = s->h;
   p->seg.crc = s->crc;
   p->seg.isize = s->isize;
@@ -927,7 +1040,7 @@ int gz_stream_next(gz_stream_t s, void *d_out, size_t out_cap, void *d_ws, size_
   if (s->cur) gz_plan_destroy(s->cur);
   s->cur = nullptr;
   gz_plan_t p = nullptr;
-  const uint32_t wv = s->out_total > 0 ? (uint32_t)std::min<uint64_t>(s->out_total, WINDOW) : 0u;
+  const uint32_t wv = s->inside ? WINDOW : (uint32_t)std::min<uint64_t>(s->out_total, WINDOW);
   int r = segment_plan(s, s->bit, wv, d_out, out_cap, &p);
   if (r != GZ_OK) return r;
   uint8_t *ws = (uint8_t *)d_ws;
@@ -982,7 +1095,7 @@ int gz_stream_wait(gz_stream_t s, gz_segment_result *res) {
     s->bit = fst.end_bit;
     s->out_total += g.out_len;
     s->crc_run = g.crc32;
-    s->valid = (uint32_t)std::min<uint64_t>(s->out_total, WINDOW);
+    s->valid = s->inside ? WINDOW : (uint32_t)std::min<uint64_t>(s->out_total, WINDOW);
     s->done = fst.is_final != 0;
   } else if (g.status == GZ_E_CAPACITY && fst.overflow) {
     // symbols overflowed: later plans use a factor that covers them
@@ -1005,6 +1118,7 @@ int gz_stream_checkpoint(gz_stream_t s, gz_checkpoint *cp) {
   cp->crc32 = s->crc_run;
   cp->valid = s->valid;
   cp->done = s->done ? 1u : 0u;
+  cp->flags = s->inside ? 1u : 0u;
   if (s->valid > 0) {
     hipError_t e = hipMemcpy(cp->window, s->d_win, WINDOW, hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "reading the window");
@@ -1015,8 +1129,9 @@ int gz_stream_checkpoint(gz_stream_t s, gz_checkpoint *cp) {
 int gz_stream_resume(gz_stream_t s, const gz_checkpoint *cp) {
   if (!s || !cp || s->pending) return GZ_E_ARG;
   const uint64_t lo = 8ull * (uint64_t)s->h, hi = 8ull * (s->job.comp_len - 8);
-  if (cp->bit < lo || cp->bit > hi || cp->valid > WINDOW ||
-      cp->valid != (uint32_t)std::min<uint64_t>(cp->out_total, WINDOW))
+  const bool inside = (cp->flags & 1u) != 0;
+  if (cp->bit < lo || cp->bit > hi || cp->valid > WINDOW || (cp->flags & ~1u) ||
+      cp->valid != (inside ? WINDOW : (uint32_t)std::min<uint64_t>(cp->out_total, WINDOW)))
     return GZ_E_ARG;
   if (cp->valid > 0) {
     hipError_t e = hipMemcpy(s->d_win, cp->window, WINDOW, hipMemcpyHostToDevice);
@@ -1027,6 +1142,33 @@ int gz_stream_resume(gz_stream_t s, const gz_checkpoint *cp) {
   s->crc_run = cp->crc32;
   s->valid = cp->valid;
   s->done = cp->done != 0;
+  s->inside = inside;
+  return GZ_OK;
+}
+
+int gz_stream_open_at(gz_stream_t *stream, const void *d_comp, size_t comp_len, uint64_t block_bit, uint32_t marker,
+                      uint64_t segment_bytes, const gz_opts *opts) {
+  if (marker > 255) return GZ_E_ARG;
+  int r = gz_stream_open(stream, d_comp, comp_len, segment_bytes, opts);
+  if (r != GZ_OK) return r;
+  gz_stream_t s = *stream;
+  const uint64_t lo = 8ull * (uint64_t)s->h, hi = 8ull * (comp_len - 8);
+  if (block_bit < lo || block_bit >= hi) {
+    gz_stream_destroy(s);
+    *stream = nullptr;
+    return GZ_E_ARG;
+  }
+  // the undetermined context: 32768 copies of the marker
+  std::vector<uint8_t> w(WINDOW, (uint8_t)marker);
+  hipError_t e = hipMemcpy(s->d_win, w.data(), WINDOW, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    gz_stream_destroy(s);
+    *stream = nullptr;
+    return hip_fail(e, "writing the window");
+  }
+  s->bit = block_bit;
+  s->inside = true;
+  s->valid = WINDOW;
   return GZ_OK;
 }
 

@@ -76,6 +76,14 @@ struct FileDesc {
   uint64_t out_before;     // bytes of the member before this segment (ISIZE is checked on the sum)
   uint32_t crc_in;         // CRC-32 of those bytes (0 for none)
   uint32_t win_valid;      // real bytes in the carried window (the first chunk's window slot), 0: none
+  uint32_t mode;           // FD_* below
+  uint32_t pad2;
+};
+
+// file modes
+enum : uint32_t {
+  FD_PROBE = 1u,    // block-start probe: one chunk, decodes its first block (plus the confirmation)
+  FD_NOCHECK = 2u,  // decoding began inside the member: the trailer's CRC-32 and ISIZE do not apply
 };
 
 struct ChunkDesc {

@@ -597,7 +597,8 @@ __device__ __forceinline__ void inflate_chunk(InflateLDS<WIN> &sh, const FileDes
       return;
     }
     inflater_setup(inf, fd, cd, pool);
-    DecodeResult r = inf.run(b, stop, first ? 0u : 6u, defer);
+    // a probe stops after the first block (and its confirmation)
+    DecodeResult r = inf.run(b, (fd.mode & FD_PROBE) ? b + 1 : stop, first ? 0u : 6u, defer);
     if (r.status != D_OK && (first || r.blocks >= 6u)) {
       if (lane == 0) {
         cs[c].start = b;
@@ -778,7 +779,8 @@ __global__ __launch_bounds__(256) void k_capacity(const FileDesc *files, ChunkDe
       uint64_t cap = 0;
       if (s != NONE && s < end_bit) {
         const uint64_t e = nxt[tid] < end_bit ? nxt[tid] : end_bit;
-        const uint64_t span = e > s ? (e - s + 7) / 8 : 1;
+        // a probe's one block: at most the stop margin of compressed bytes
+        const uint64_t span = (fd.mode & FD_PROBE) ? STOP_MARGIN_BYTES : e > s ? (e - s + 7) / 8 : 1;
         cap = ((uint64_t)factor * span + SYM_SLACK + FLUSH_UNIT - 1) / FLUSH_UNIT * FLUSH_UNIT;
       }
       chunks[c0 + i].sym_cap = cap;
@@ -1584,7 +1586,7 @@ __global__ __launch_bounds__(256) void k_crc_final(const FileDesc *files, uint32
     // (all ones for none), carried over this segment's L bytes
     const uint32_t crc = fs[f].crc_acc ^ gf_mul(~files[f].crc_in, gf_xpow8(L, xpow)) ^ 0xFFFFFFFFu;
     fs[f].crc_out = crc;
-    if (!fs[f].is_final) continue;
+    if (!fs[f].is_final || (files[f].mode & FD_NOCHECK)) continue;
     if (crc != files[f].crc) fs[f].status = ST_CRC;
     else if (fs[f].size_bad) fs[f].status = ST_SIZE;
   }
@@ -1610,6 +1612,41 @@ __global__ __launch_bounds__(1024) void k_carry(const FileDesc *files, const Fil
     else if ((int64_t)WINDOW + pos >= lim) b = old[WINDOW + pos];
     dst[k] = b;
   }
+}
+
+// ---------------------------------------------------------------------------
+// k_count_byte: counts[(first + i) / window] += (buf[i] == value), i < n;
+// windows past n_counts are not counted.  Each thread takes 16 aligned bytes
+// of the global position space per step; a thread's per-window total is added
+// once per window it touches.
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_count_byte(const uint8_t *__restrict__ buf, uint64_t n, uint32_t value,
+                                                    uint64_t first, uint64_t window, unsigned long long *counts,
+                                                    uint64_t n_counts) {
+  const uint64_t stride = 16ull * gridDim.x * blockDim.x;
+  uint64_t cur_w = NONE;
+  unsigned long long acc = 0;
+  for (uint64_t g = 16ull * (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x); g < n; g += stride) {
+    const uint32_t lim = n - g < 16 ? (uint32_t)(n - g) : 16u;
+    // window of the step's first byte, and bytes left in it
+    uint64_t w = (first + g) / window;
+    uint64_t rem = window - (first + g) % window;
+    for (uint32_t h = 0; h < lim; h++) {
+      if (rem == 0) {
+        w++;
+        rem = window;
+      }
+      if (w != cur_w) {
+        if (acc && cur_w < n_counts) atomicAdd(&counts[cur_w], acc);
+        cur_w = w;
+        acc = 0;
+      }
+      acc += buf[g + h] == value ? 1ull : 0ull;
+      rem--;
+    }
+  }
+  if (acc && cur_w < n_counts) atomicAdd(&counts[cur_w], acc);
 }
 
 // ---------------------------------------------------------------------------
@@ -1728,6 +1765,17 @@ hipError_t gzk_propagate(uint32_t n, const uint32_t *acc_pos, const AccEntry *ac
   hipLaunchKernelGGL(k_prop_chain, dim3(1), dim3(PROP_THREADS), 0, st, acc_pos, n, acc, maps, wins, segwin);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(k_prop_apply, dim3(smax), dim3(PROP_THREADS), 0, st, acc_pos, n, acc, pool, segwin, wins);
+  return hipGetLastError();
+}
+
+hipError_t gzk_count_byte(const uint8_t *buf, uint64_t n, uint32_t value, uint64_t first, uint64_t window,
+                         unsigned long long *counts, uint64_t n_counts, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  const uint64_t per = 16ull * 256;
+  uint64_t blocks = (n + per - 1) / per;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_count_byte, dim3((uint32_t)blocks), dim3(256), 0, st, buf, n, value, first, window, counts,
+                     n_counts);
   return hipGetLastError();
 }
 

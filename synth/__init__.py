@@ -162,6 +162,18 @@ def random_dna(n: int, seed: int) -> bytes:
     return _ACGT[rng.integers(0, 4, size=n, dtype=np.uint8)].tobytes()
 
 
+def dna_x_string(n: int, seed: int, dna: int = 150, xs: int = 300) -> bytes:
+    """Repeats of `dna` random bases then `xs` 'x' characters, cut to n bytes
+    (the FASTQ-like string of Section IV-D)."""
+    rng = np.random.default_rng(seed)
+    period = dna + xs
+    reps = (n + period - 1) // period
+    a = np.empty((reps, period), dtype=np.uint8)
+    a[:, :dna] = _ACGT[rng.integers(0, 4, size=(reps, dna), dtype=np.uint8)]
+    a[:, dna:] = ord("x")
+    return a.reshape(-1)[:n].tobytes()
+
+
 def _deflate_segment(data: bytes, level: int, zdict: bytes | None, last: bool, strategy: int) -> bytes:
     if zdict:
         c = zlib.compressobj(level, zlib.DEFLATED, -15, 9, strategy, zdict=zdict)

@@ -202,3 +202,80 @@ def stream_run(comp: bytes, segment_bytes: int, resume=None, stop_after=None, **
     finally:
         L.gz_stream_destroy(h)
     return segs
+
+
+def probe_run(comp: bytes, bits, range_bytes: int, **opts):
+    """gz_plan_probes + gz_find_blocks + gz_probe_starts; returns (starts, rejected)."""
+    L = lib()
+    vp = C.c_void_p
+    L.gz_plan_probes.argtypes = [C.POINTER(vp), vp, C.c_size_t, vp, C.c_int, C.c_uint64, C.POINTER(Opts)]
+    L.gz_find_blocks.argtypes = [vp, vp, C.c_size_t, vp]
+    L.gz_probe_starts.argtypes = [vp, vp, vp]
+    L.emu_set_sync_limit(3_000_000_000)
+    store = padded(comp)
+    buf = store[: len(comp)]
+    b = np.asarray(bits, dtype=np.uint64)
+    o = Opts()
+    for k, v in opts.items():
+        setattr(o, k, v)
+    h = vp()
+    st = L.gz_plan_probes(C.byref(h), vp(buf.ctypes.data), buf.size, vp(b.ctypes.data), b.size, range_bytes,
+                          C.byref(o))
+    if st != 0:
+        return st, None
+    info = Info()
+    L.gz_plan_info(h, C.byref(info))
+    raw_ws = np.zeros(info.ws_bytes + 512, dtype=np.uint8)
+    off = (-raw_ws.ctypes.data) % 256
+    ws = raw_ws[off:off + info.ws_bytes]
+    assert L.gz_find_blocks(h, vp(ws.ctypes.data), ws.size, None) == 0
+    starts = np.zeros(b.size, dtype=np.uint64)
+    rej = np.zeros(b.size, dtype=np.uint32)
+    assert L.gz_probe_starts(h, vp(starts.ctypes.data), vp(rej.ctypes.data)) == 0
+    L.gz_plan_destroy(h)
+    return starts, rej
+
+
+def stream_at(comp: bytes, bit: int, marker: int, segment_bytes: int, window: int, **opts):
+    """gz_stream_open_at from `bit` to the end; returns (segment dicts, output bytes,
+    gz_count_byte counts of the marker per window)."""
+    L = stream_lib()
+    vp = C.c_void_p
+    L.gz_stream_open_at.argtypes = [C.POINTER(vp), vp, C.c_size_t, C.c_uint64, C.c_uint32, C.c_uint64,
+                                    C.POINTER(Opts)]
+    L.gz_count_byte.argtypes = [vp, C.c_uint64, C.c_uint32, C.c_uint64, C.c_uint64, vp, C.c_uint64, vp]
+    L.emu_set_sync_limit(3_000_000_000)
+    store = padded(comp)
+    buf = store[: len(comp)]
+    o = Opts()
+    for k, v in opts.items():
+        setattr(o, k, v)
+    h = vp()
+    st = L.gz_stream_open_at(C.byref(h), vp(buf.ctypes.data), buf.size, bit, marker, segment_bytes, C.byref(o))
+    if st != 0:
+        return st, None, None
+    counts = np.zeros(1 << 14, dtype=np.uint64)
+    segs, data = [], b""
+    try:
+        while True:
+            info = StreamInfo()
+            assert L.gz_stream_get_info(h, C.byref(info)) == 0
+            raw_ws = np.zeros(info.ws_bytes + 512, dtype=np.uint8)
+            off = (-raw_ws.ctypes.data) % 256
+            ws = raw_ws[off:off + info.ws_bytes]
+            out = np.zeros(max(1, info.out_bytes), dtype=np.uint8)
+            assert L.gz_stream_next(h, vp(out.ctypes.data), out.size, vp(ws.ctypes.data), ws.size, None) == 0
+            r = SegmentResult()
+            assert L.gz_stream_wait(h, C.byref(r)) == 0
+            d = {k: getattr(r, k) for k, _ in r._fields_}
+            segs.append(d)
+            if r.status != 0:
+                break
+            assert L.gz_count_byte(vp(out.ctypes.data), r.out_len, marker, len(data), window,
+                                   vp(counts.ctypes.data), counts.size, None) == 0
+            data += out[: r.out_len].tobytes()
+            if r.done:
+                break
+    finally:
+        L.gz_stream_destroy(h)
+    return segs, data, counts[: (len(data) + window - 1) // window].astype(np.int64)

@@ -256,3 +256,48 @@ def test_emu_stream_resume_and_checks(orc):
     segs = E.stream_run(bytes(bad), 6000, chunk_bytes=2048)
     assert [d["status"] for d, _, _ in segs[:-1]] == [0] * (len(segs) - 1)
     assert segs[-1][0]["status"] == -6
+
+
+def test_emu_block_probes(orc):
+    # flush points every 20 KiB give many short blocks
+    raw = synth.fastq_like(400 << 10, 321)
+    comp = synth.gzip_member(raw, 6, segment_bytes=20 << 10)
+    g = orc.gunzip(comp)
+    assert g.block_bit.size >= 20
+    P = 8 * g.payload_start
+    end = 8 * (len(comp) - 8)
+    # at a block start, just after one, mid-stream, and too close to the end
+    bits = [P, int(g.block_bit[1]), int(g.block_bit[1]) + 1, P + 8 * 30000 + 5, end - 8 * 200]
+    rng = 64 << 10
+    starts, rej = E.probe_run(comp, bits, rng, chunk_bytes=8192)
+    for b, s in zip(bits, starts):
+        ref = orc.find_start(comp, b, min(end, b + 8 * rng))
+        assert int(s) == (ref if ref >= 0 else NONE), (b, int(s), ref)
+    dyn = g.block_bit[g.block_type == 2]
+    assert int(starts[1]) == int(dyn[dyn >= bits[1]][0])
+    assert int(starts[2]) == int(dyn[dyn > bits[1]][0]) and int(starts[-1]) == NONE
+    # a bit outside the payload is an argument error
+    st, _ = E.probe_run(comp, [end + 8], rng)
+    assert st == -1
+
+
+@pytest.mark.parametrize("level", [1, 6])
+def test_emu_random_access_undetermined(orc, level):
+    raw = synth.random_dna(300000, 322 + level)
+    comp = synth.gzip_member(raw, level)
+    g = orc.gunzip(comp)
+    b = int(g.block_bit[1])  # from block 2, as Section IV-C
+    segs, data, counts = E.stream_at(comp, b, 0, 9000, 3602, chunk_bytes=4096)
+    assert all(d["status"] == 0 for d in segs) and segs[-1]["done"] == 1
+    sr = orc.symbolic(comp, b, 1 << 62, first=False)
+    assert sr.status == orc.OK
+    sym = sr.sym
+    und = sym >= 0x8000
+    exp = np.where(und, 0, sym).astype(np.uint8)
+    assert data == exp.tobytes()
+    # determined bytes are the true bytes at the block's output offset
+    o = int(g.block_out_off[1])
+    assert np.array_equal(exp[~und], np.frombuffer(raw, np.uint8)[o:][~und])
+    n_win = (und.size + 3601) // 3602
+    ref_counts = np.add.reduceat(und.astype(np.int64), np.arange(0, und.size, 3602)) if und.size else []
+    assert n_win == counts.size and np.array_equal(counts, ref_counts)
