@@ -273,7 +273,7 @@ def main():
     ap.add_argument("--batch-files", type=int, default=32, help="files of the batched-vs-plain set (0: skip)")
     ap.add_argument("--serve-jobs", type=int, default=400, help="jobs of the serving run (0: skip)")
     ap.add_argument("--serve-load", type=float, default=0.7, help="offered load, fraction of measured capacity")
-    ap.add_argument("--stream-mib", type=int, default=96,
+    ap.add_argument("--stream-mib", type=int, default=256,
                     help="bounded-memory streaming leg: compressed MiB per segment (0: skip)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after warmup, one device-to-device copy of this many MiB (HBM counter calibration)")

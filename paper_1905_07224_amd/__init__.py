@@ -559,6 +559,7 @@ class Stream:
                                                C.byref(_opts(**opts))))
         self._ws = None
         self._out = None
+        self._info = None
         self.done = False
         self.last = None
 
@@ -582,7 +583,9 @@ class Stream:
         if self.done:
             raise GzError(GZ_E_ARG, "the member is finished")
         for _ in range(retries + 1):
-            info = self.info()
+            if self._info is None or (self.last is not None and self.last["status"] == GZ_E_CAPACITY):
+                self._info = self.info()
+            info = self._info
             out_need = info["out_bytes"]
             if self.last is not None and self.last["status"] == GZ_E_CAPACITY:
                 out_need = max(out_need, self.last["out_needed"])

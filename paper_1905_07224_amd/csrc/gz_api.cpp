@@ -142,6 +142,7 @@ struct gz_plan_s {
   Layout lay{};
   uint64_t order_bytes = 0, scan_off = 0;
   uint8_t *pinned = nullptr;
+  uint64_t pinned_bytes = 0;
   hipEvent_t upload_done = nullptr;
   bool upload_pending = false;
   hipEvent_t pass_ev[GZ_N_PASSES + 1] = {};
@@ -347,15 +348,25 @@ static int plan_common(gz_plan_t p) {
   L.sym_elems = sym_elems;
   o = align_up(o + sym_elems * 2, 256);
   L.total = o;
-  // pinned copy of the job table
-  if (p->pinned) (void)hipHostFree(p->pinned);
+  // pinned copy of the job table (kept when a re-plan fits in it; the last
+  // upload from it has finished before it is rewritten, see launch)
+  if (p->pinned && p->pinned_bytes >= L.table_bytes) return GZ_OK;
+  if (p->pinned) {
+    if (p->upload_pending) {
+      (void)hipEventSynchronize(p->upload_done);
+      p->upload_pending = false;
+    }
+    (void)hipHostFree(p->pinned);
+  }
   p->pinned = nullptr;
+  p->pinned_bytes = 0;
   hipError_t e = hipHostMalloc((void **)&p->pinned, L.table_bytes, hipHostMallocDefault);
   if (e != hipSuccess) return hip_fail(e, "pinned job table");
+  p->pinned_bytes = L.table_bytes;
   return GZ_OK;
 }
 
-static void fill_defaults(gz_plan_t p, const gz_opts *opts) {
+static void fill_defaults(gz_plan_t p, const gz_opts *opts, bool query_device = true) {
   if (opts) p->opts = *opts;
   if (p->opts.chunk_bytes == 0) p->opts.chunk_bytes = DEFAULT_CHUNK_BYTES;
   if (p->opts.sym_factor == 0) p->opts.sym_factor = 8;
@@ -363,6 +374,7 @@ static void fill_defaults(gz_plan_t p, const gz_opts *opts) {
   // from HBM, so a smaller ring trades those reads for more waves per CU
   p->win = p->opts.window_syms ? p->opts.window_syms : DEFAULT_RING;
   p->groups = p->opts.scan_groups;
+  if (!query_device) return;
   (void)hipGetDevice(&p->device);
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, p->device) == hipSuccess) p->n_cu = prop.multiProcessorCount;
@@ -955,17 +967,30 @@ struct gz_stream_s {
   uint64_t bit = 0, out_total = 0;
   uint32_t crc_run = 0, valid = 0;
   bool done = false;
-  gz_plan_t cur = nullptr;   // plan of the segment in flight
+  gz_plan_t cur = nullptr;   // plan of the segment in flight, re-planned in place for the next
   bool pending = false;
   bool inside = false;       // opened at a block inside the member (gz_stream_open_at)
+  uint64_t info_ws = 0, info_out = 0;  // sizes for any segment at the current symbol factor (0: not known)
 };
 
+// Plan a segment into *io (created when null, else re-planned in place so
+// its pinned table is reused).
 static int segment_plan(gz_stream_t s, uint64_t start_bit, uint32_t win_valid, void *d_out, uint64_t out_cap,
-                        gz_plan_t *out) {
-  *out = nullptr;
-  gz_plan_t p = new (std::nothrow) gz_plan_s();
-  if (!p) return GZ_E_ARG;
-  fill_defaults(p, &s->opts);
+                        gz_plan_t *io) {
+  gz_plan_t p = *io;
+  const bool fresh = p == nullptr;
+  if (fresh) {
+    p = new (std::nothrow) gz_plan_s();
+    if (!p) return GZ_E_ARG;
+  } else {
+    if (p->upload_pending) {
+      (void)hipEventSynchronize(p->upload_done);
+      p->upload_pending = false;
+    }
+    p->launched = false;
+    p->fetched = false;
+  }
+  fill_defaults(p, &s->opts, fresh);
   p->seg.on = true;
   p->seg.start_bit = start_bit;
   p->seg.stop_bit = start_bit + 8 * s->seg_bytes;
@@ -983,10 +1008,23 @@ static int segment_plan(gz_stream_t s, uint64_t start_bit, uint32_t win_valid, v
   const int r = plan_common(p);
   if (r != GZ_OK) {
     gz_plan_destroy(p);
+    *io = nullptr;
     return r;
   }
-  (void)hipEventCreateWithFlags(&p->upload_done, hipEventDisableTiming);
-  *out = p;
+  if (fresh) (void)hipEventCreateWithFlags(&p->upload_done, hipEventDisableTiming);
+  *io = p;
+  return GZ_OK;
+}
+
+// Workspace and output sizes of a full segment that starts from a carried
+// window (the largest layout), at the current symbol factor.
+static int stream_sizes(gz_stream_t s) {
+  gz_plan_t p = nullptr;
+  const int r = segment_plan(s, 8ull * (uint64_t)s->h, WINDOW, nullptr, 0, &p);
+  if (r != GZ_OK) return r;
+  s->info_ws = p->lay.total;
+  s->info_out = p->files[0].pool_elems;
+  gz_plan_destroy(p);
   return GZ_OK;
 }
 
@@ -1000,6 +1038,7 @@ int gz_stream_open(gz_stream_t *stream, const void *d_comp, size_t comp_len, uin
   if (!s) return GZ_E_ARG;
   if (opts) s->opts = *opts;
   s->opts.timing = 0;
+  if (!s->opts.sym_factor) s->opts.sym_factor = 8;
   s->seg_bytes = segment_bytes ? segment_bytes : (256ull << 20);
   s->job.d_comp = d_comp;
   s->job.comp_len = comp_len;
@@ -1020,13 +1059,12 @@ int gz_stream_open(gz_stream_t *stream, const void *d_comp, size_t comp_len, uin
 int gz_stream_get_info(gz_stream_t s, gz_stream_info *info) {
   if (!s || !info) return GZ_E_ARG;
   memset(info, 0, sizeof(*info));
-  // a full segment that starts from a carried window has the largest layout
-  gz_plan_t p = nullptr;
-  const int r = segment_plan(s, 8ull * (uint64_t)s->h, WINDOW, nullptr, 0, &p);
-  if (r != GZ_OK) return r;
-  info->ws_bytes = p->lay.total;
-  info->out_bytes = p->files[0].pool_elems;
-  gz_plan_destroy(p);
+  if (!s->info_ws) {
+    const int r = stream_sizes(s);
+    if (r != GZ_OK) return r;
+  }
+  info->ws_bytes = s->info_ws;
+  info->out_bytes = s->info_out;
   info->segment_bytes = s->seg_bytes;
   info->payload_start = (uint64_t)s->h;
   info->payload_end = s->job.comp_len - 8;
@@ -1037,28 +1075,23 @@ int gz_stream_get_info(gz_stream_t s, gz_stream_info *info) {
 
 int gz_stream_next(gz_stream_t s, void *d_out, size_t out_cap, void *d_ws, size_t ws_bytes, void *hip_stream) {
   if (!s || s->done || s->pending || !d_out || out_cap == 0) return GZ_E_ARG;
-  if (s->cur) gz_plan_destroy(s->cur);
-  s->cur = nullptr;
-  gz_plan_t p = nullptr;
   const uint32_t wv = s->inside ? WINDOW : (uint32_t)std::min<uint64_t>(s->out_total, WINDOW);
-  int r = segment_plan(s, s->bit, wv, d_out, out_cap, &p);
+  int r = segment_plan(s, s->bit, wv, d_out, out_cap, &s->cur);
   if (r != GZ_OK) return r;
+  gz_plan_t p = s->cur;
   uint8_t *ws = (uint8_t *)d_ws;
   hipStream_t st = (hipStream_t)hip_stream;
   if (!ws || ws_bytes < p->lay.total || ((uintptr_t)ws & 255u)) {
     snprintf(g_err, sizeof(g_err), "workspace needs %llu bytes, 256-byte aligned",
              (unsigned long long)p->lay.total);
-    gz_plan_destroy(p);
     return ws && ws_bytes < p->lay.total ? GZ_E_CAPACITY : GZ_E_ARG;
   }
   // the first chunk's window slot holds the carried window (nothing else
   // writes that slot before window propagation reads it)
   uint8_t *slot = ws + p->lay.win_off + (uint64_t)p->files[0].first_chunk * WINDOW;
   hipError_t e;
-  if (wv > 0 && (e = hipMemcpyAsync(slot, s->d_win, WINDOW, hipMemcpyDeviceToDevice, st)) != hipSuccess) {
-    gz_plan_destroy(p);
+  if (wv > 0 && (e = hipMemcpyAsync(slot, s->d_win, WINDOW, hipMemcpyDeviceToDevice, st)) != hipSuccess)
     return hip_fail(e, "carried window");
-  }
   r = launch(p, ws, ws_bytes, st);
   if (r == GZ_OK) {
     // the next window: the last 32 KiB of (carried window ++ this output)
@@ -1066,11 +1099,7 @@ int gz_stream_next(gz_stream_t s, void *d_out, size_t out_cap, void *d_ws, size_
                   s->d_win, st);
     if (e != hipSuccess) r = hip_fail(e, "carry");
   }
-  if (r != GZ_OK) {
-    gz_plan_destroy(p);
-    return r;
-  }
-  s->cur = p;
+  if (r != GZ_OK) return r;
   s->pending = true;
   return GZ_OK;
 }
@@ -1101,6 +1130,7 @@ int gz_stream_wait(gz_stream_t s, gz_segment_result *res) {
     // symbols overflowed: later plans use a factor that covers them
     const uint64_t f2 = needed_factor(s->cur, 0);
     s->opts.sym_factor = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(f2, 2ull * s->opts.sym_factor), 1u << 20);
+    s->info_ws = 0;
     gz_stream_info info;
     if (gz_stream_get_info(s, &info) == GZ_OK) res->ws_needed = info.ws_bytes;
   }

@@ -875,6 +875,13 @@ __global__ __launch_bounds__(64) void k_confirm(const FileDesc *files, const Chu
     for (uint32_t g = 0; g < fd.n_chunks && !ok && !always_decode; g++) {
       uint32_t xn = x + 1;
       for (uint32_t h = 0; h < fd.n_chunks && xn < c1 && uni64(cs[xn].start) == NONE; h++) xn++;
+      // the chain reached a segment's stop: the blocks still owed are the
+      // next segment's first ones, decoded from this proven end; the start
+      // itself is proven or repaired by the chain check of k_finalize
+      if (xn >= c1 && fd.stop_bit != NONE && at >= fd.stop_bit) {
+        ok = true;
+        break;
+      }
       if (xn >= c1 || uni64(cs[xn].start) != at || uni(cs[xn].status) != ST_OK) break;
       const uint32_t kx = uni(cs[xn].n_blocks);
       if ((uni(cs[xn].flags) & CS_FINAL) || kx >= need) {
