@@ -262,18 +262,20 @@ struct Inflater {
     return br.past_end() ? D_TRUNC : D_OK;
   }
 
-  // Token descriptors of one lookup round (per lane k: the token that would
-  // start at bit offset k).  TOK_SPECIAL set: the walk stops there, with the
-  // kind in bits 29..28 (end-of-block: its code length in the low bits).
+  // Token words of one lookup round (per lane k: the token that would start
+  // at bit offset k): bits 5..0 the bits it uses (at most 48), bits 14..6
+  // its output length (1: a literal), bits 30..15 the literal byte or the
+  // match distance (1..32768).  TOK_SPECIAL set: the walk stops there, with
+  // the kind in bits 29..28 (end-of-block: its code length in the low bits).
   static constexpr uint32_t TOK_SPECIAL = 0x80000000u;
   static constexpr uint32_t TOK_EOB = TOK_SPECIAL | (1u << 28);
   static constexpr uint32_t TOK_SLOW = TOK_SPECIAL | (2u << 28);   // longer code, or invalid: decoded alone
   static constexpr uint32_t TOK_ASCII = TOK_SPECIAL | (3u << 28);  // non-ASCII literal in a checked block
 
-  // The token that would start at bit offset k of a lookup round, from the
-  // 64 stream bits at that offset (w0: bits k .. k + 31, w1: k + 32 .. k + 63).
+  // The token word at bit offset k of a lookup round, from the 64 stream
+  // bits at that offset (w0: bits k .. k + 31, w1: k + 32 .. k + 63).
   template <bool CHECK>
-  __device__ __forceinline__ void token_at(uint32_t w0, uint32_t w1, uint32_t &info, int32_t &tval) const {
+  __device__ __forceinline__ uint32_t token_at(uint32_t w0, uint32_t w1) const {
     const uint32_t LMASK = (1u << LIT_BITS) - 1u, DMASK = (1u << DIST_BITS) - 1u;
     const uint64_t w = ((uint64_t)w1 << 32) | w0;
     const uint32_t e = sh_lit(w0 & LMASK);
@@ -283,16 +285,11 @@ struct Inflater {
     const uint32_t dl = ed & 15u, dex = (ed >> 8) & 15u;
     const uint32_t len = (e >> 16) + ((w0 >> cl) & ((1u << ex) - 1u));
     const uint32_t dist = (ed >> 16) + ((uint32_t)(w >> (u + dl)) & ((1u << dex) - 1u));
-    if ((kind & 7u) == K_LIT) {
-      info = (CHECK && kind == K_LITX) ? TOK_ASCII : (cl | (1u << 8));
-      tval = (int32_t)(REF_LIT | ((e >> 8) & 255u));
-    } else if (kind == K_LEN) {
-      info = ((ed >> 4) & 15u) == K_LEN ? (u + dl + dex) | (len << 8) : TOK_SLOW;
-      tval = -(int32_t)dist;
-    } else {
-      info = kind == K_EOB ? (TOK_EOB | cl) : TOK_SLOW;
-      tval = 0;
-    }
+    if ((kind & 7u) == K_LIT)
+      return (CHECK && kind == K_LITX) ? TOK_ASCII : (cl | (1u << 6) | (((e >> 8) & 255u) << 15));
+    if (kind == K_LEN)
+      return ((ed >> 4) & 15u) == K_LEN ? (u + dl + dex) | (len << 6) | (dist << 15) : TOK_SLOW;
+    return kind == K_EOB ? (TOK_EOB | cl) : TOK_SLOW;
   }
 
   // Huffman-coded block body until end-of-block (section 3.2.5), decoded in
@@ -301,14 +298,15 @@ struct Inflater {
   // literal/length code, extra length bits, distance code and extra distance
   // bits (at most 48 bits, RFC 1951 section 3.2.5), with one lookup in each
   // table.  The scalar walk then follows the real tokens from offset 0 (each
-  // one bit count further) while they start below offset 128, and turns them
-  // into batches of up to 64 output symbols.  CHECK: literals must be ASCII
-  // text (block-start trial and confirmation).
+  // one bit count further) while they start below offset 128, recording only
+  // where each starts in the batch of up to 64 output symbols; then every
+  // lane finds its token (the last start at or before it) and takes its
+  // source from the token's word.  CHECK: literals must be ASCII text
+  // (block-start trial and confirmation).
   template <bool CHECK>
   __device__ int huffman(uint64_t size_cap, uint64_t blk0) {
     const int lane = lane_id();
-    uint32_t info0 = 0, info1 = 0;  // bits used | output symbols << 8, or a TOK_ kind
-    int32_t tval0 = 0, tval1 = 0;   // REF_LIT | literal, or -distance
+    uint32_t tok0 = 0, tok1 = 0;  // token words at offsets lane and lane + 64
     uint32_t off = 0;   // bit offset of the walk from br.pos, where the round was decoded
     bool need = true;   // a round to be decoded at br.pos + off
     uint32_t rem = 0, mdist = 0;  // part of a match still to be produced
@@ -327,44 +325,53 @@ struct Inflater {
         const uint32_t a0 = lo_half ? q[0] : q[1], a1 = lo_half ? q[1] : q[2], a2 = lo_half ? q[2] : q[3];
         const uint32_t b2 = lo_half ? q[4] : q[5];
         const uint32_t b0 = a2, b1 = lo_half ? q[3] : q[4];
-        token_at<CHECK>(__builtin_amdgcn_alignbit(a1, a0, sh), __builtin_amdgcn_alignbit(a2, a1, sh), info0, tval0);
-        token_at<CHECK>(__builtin_amdgcn_alignbit(b1, b0, sh), __builtin_amdgcn_alignbit(b2, b1, sh), info1, tval1);
+        tok0 = token_at<CHECK>(__builtin_amdgcn_alignbit(a1, a0, sh), __builtin_amdgcn_alignbit(a2, a1, sh));
+        tok1 = token_at<CHECK>(__builtin_amdgcn_alignbit(b1, b0, sh), __builtin_amdgcn_alignbit(b2, b1, sh));
         off = 0;
         need = false;
       }
-      int32_t ref = 0;
-      uint32_t j = 0;
-      if (rem) {
-        const uint32_t n = min(rem, 64u);
-        if ((uint32_t)lane < n) ref = lane - (int32_t)mdist;
-        j = n;
-        rem -= n;
+      // start lanes of the batch's tokens, and each start lane's token word
+      // (the rest of a match begun in the last batch is the token at lane 0)
+      uint64_t starts = 0;
+      uint32_t word = 0;
+      uint32_t jr = 0;  // output symbols of the tokens walked so far
+      uint32_t x = 0, lastw = 0;
+      const uint32_t cont = rem ? 1u : 0u;
+      if (cont) {
+        lastw = (2u << 6) | (mdist << 15);
+        starts = 1;
+        if (lane == 0) word = lastw;
+        jr = rem;
       }
-      uint32_t x = 0, ntok = 0;
-      while (j < 64u && off < 128u) {
-        // both halves read, one kept by a mask (straight-line code)
-        const uint32_t hm = 0u - (off >> 6);
-        const int ln = (int)(off & 63u);
-        const uint32_t x0 = (uint32_t)__builtin_amdgcn_readlane((int)info0, ln);
-        const uint32_t x1 = (uint32_t)__builtin_amdgcn_readlane((int)info1, ln);
-        x = x0 ^ ((x0 ^ x1) & hm);
-        if (x & TOK_SPECIAL) break;
-        const uint32_t v0 = (uint32_t)__builtin_amdgcn_readlane(tval0, ln);
-        const uint32_t v1 = (uint32_t)__builtin_amdgcn_readlane(tval1, ln);
-        const int32_t v = (int32_t)(v0 ^ ((v0 ^ v1) & hm));
-        const uint32_t len = x >> 8;
-        const uint32_t n = min(len, 64u - j);
-        const int32_t add = v < 0 ? lane : 0;
-        if ((uint32_t)lane - j < n) ref = v + add;
-        j += n;
-        rem = len - n;
-        mdist = (uint32_t)(-v);
-        off += x & 255u;
-        ntok++;
-        x = 0;
+      if (jr < 64u) {
+        while (off < 128u) {
+          const int ln = (int)(off & 63u);
+          const uint32_t x0 = (uint32_t)__builtin_amdgcn_readlane((int)tok0, ln);
+          const uint32_t x1 = (uint32_t)__builtin_amdgcn_readlane((int)tok1, ln);
+          x = off < 64u ? x0 : x1;
+          if (x & TOK_SPECIAL) break;
+          starts |= 1ull << jr;
+          if ((uint32_t)lane == jr) word = x;
+          lastw = x;
+          jr += (x >> 6) & 511u;
+          off += x & 63u;
+          x = 0;
+          if (jr >= 64u) break;
+        }
       }
-      nsyms += ntok;
+      // a token running past the batch continues in the next one
+      const uint32_t j = jr < 64u ? jr : 64u;
+      rem = jr - j;
+      mdist = lastw >> 15;
+      nsyms += (uint32_t)__builtin_popcountll(starts) - cont;
       if (j) {
+        // each lane's token: the last start at or before the lane
+        const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+        const uint64_t m = starts & upto;
+        const int src = 63 - (int)__builtin_clzll(m | 1ull);
+        const uint32_t w = (uint32_t)__shfl((int)word, src);
+        const int32_t ref = ((w >> 6) & 511u) == 1u ? (int32_t)(REF_LIT | ((w >> 15) & 255u))
+                                                    : lane - (int32_t)(w >> 15);
         const int r = put_batch(ref, j);
         if (r != D_OK) return r;
       }
