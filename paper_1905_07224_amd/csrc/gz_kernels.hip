@@ -332,37 +332,47 @@ struct Inflater {
       }
       // start lanes of the batch's tokens, and each start lane's token word
       // (the rest of a match begun in the last batch is the token at lane 0)
-      uint64_t starts = 0;
+      // (a token word is never 0, so the start lanes are where word != 0)
       uint32_t word = 0;
       uint32_t jr = 0;  // output symbols of the tokens walked so far
-      uint32_t x = 0, lastw = 0;
       const uint32_t cont = rem ? 1u : 0u;
       if (cont) {
-        lastw = (2u << 6) | (mdist << 15);
-        starts = 1;
-        if (lane == 0) word = lastw;
+        if (lane == 0) word = (2u << 6) | (mdist << 15);
         jr = rem;
       }
-      if (jr < 64u) {
-        while (off < 128u) {
-          const int ln = (int)(off & 63u);
-          const uint32_t x0 = (uint32_t)__builtin_amdgcn_readlane((int)tok0, ln);
-          const uint32_t x1 = (uint32_t)__builtin_amdgcn_readlane((int)tok1, ln);
-          x = off < 64u ? x0 : x1;
-          if (x & TOK_SPECIAL) break;
-          starts |= 1ull << jr;
-          if ((uint32_t)lane == jr) word = x;
-          lastw = x;
-          jr += (x >> 6) & 511u;
-          off += x & 63u;
-          x = 0;
-          if (jr >= 64u) break;
-        }
+      // offsets below 64 come from tok0, the rest from tok1 (a walk never
+      // returns below an offset it passed, so the two halves are two loops);
+      // a walk that stops below 64 symbols and offset 128 stopped at a
+      // special token
+      if ((jr | off) < 64u) {
+        uint32_t t;
+        do {
+          t = (uint32_t)__builtin_amdgcn_readlane((int)tok0, (int)off);
+          if (t & TOK_SPECIAL) break;
+          word = (uint32_t)lane == jr ? t : word;
+          jr += (t >> 6) & 511u;
+          off += t & 63u;
+        } while ((jr | off) < 64u);
       }
-      // a token running past the batch continues in the next one
+      if (jr < 64u && off - 64u < 64u) {
+        uint32_t t;
+        do {
+          t = (uint32_t)__builtin_amdgcn_readlane((int)tok1, (int)(off - 64u));
+          if (t & TOK_SPECIAL) break;
+          word = (uint32_t)lane == jr ? t : word;
+          jr += (t >> 6) & 511u;
+          off += t & 63u;
+        } while ((jr | (off >> 1)) < 64u);
+      }
+      uint32_t x = 0;  // the special token that stopped the walk, else 0
+      if (jr < 64u && off < 128u)
+        x = (uint32_t)__builtin_amdgcn_readlane(off < 64u ? (int)tok0 : (int)tok1, (int)(off & 63u));
+      const uint64_t starts = __ballot(word != 0u);
+      // a token running past the batch continues in the next one (its
+      // word is at the last start lane)
       const uint32_t j = jr < 64u ? jr : 64u;
       rem = jr - j;
-      mdist = lastw >> 15;
+      if (rem) mdist = (uint32_t)__builtin_amdgcn_readlane((int)word, 63 - __builtin_clzll(starts)) >> 15;
       nsyms += (uint32_t)__builtin_popcountll(starts) - cont;
       if (j) {
         // each lane's token: the last start at or before the lane
