@@ -273,23 +273,37 @@ struct Inflater {
   static constexpr uint32_t TOK_ASCII = TOK_SPECIAL | (3u << 28);  // non-ASCII literal in a checked block
 
   // The token word at bit offset k of a lookup round, from the 64 stream
-  // bits at that offset (w0: bits k .. k + 31, w1: k + 32 .. k + 63).
+  // bits at that offset (w: bits k .. k + 63) and its two table entries
+  // (e: literal/length, ed: distance, looked up at the bits after the
+  // length's extra bits).  Straight-line code: every case is computed and
+  // one is selected.
   template <bool CHECK>
-  __device__ __forceinline__ uint32_t token_at(uint32_t w0, uint32_t w1) const {
-    const uint32_t LMASK = (1u << LIT_BITS) - 1u, DMASK = (1u << DIST_BITS) - 1u;
-    const uint64_t w = ((uint64_t)w1 << 32) | w0;
-    const uint32_t e = sh_lit(w0 & LMASK);
+  __device__ __forceinline__ static uint32_t token_word(uint64_t w, uint32_t e, uint32_t ed) {
+    const uint32_t w0 = (uint32_t)w;
     const uint32_t kind = (e >> 4) & 15u, cl = e & 15u, ex = (e >> 8) & 15u;
     const uint32_t u = cl + ex;
-    const uint32_t ed = sh_dist((uint32_t)(w >> u) & DMASK);
     const uint32_t dl = ed & 15u, dex = (ed >> 8) & 15u;
     const uint32_t len = (e >> 16) + ((w0 >> cl) & ((1u << ex) - 1u));
     const uint32_t dist = (ed >> 16) + ((uint32_t)(w >> (u + dl)) & ((1u << dex) - 1u));
-    if ((kind & 7u) == K_LIT)
-      return (CHECK && kind == K_LITX) ? TOK_ASCII : (cl | (1u << 6) | (((e >> 8) & 255u) << 15));
-    if (kind == K_LEN)
-      return ((ed >> 4) & 15u) == K_LEN ? (u + dl + dex) | (len << 6) | (dist << 15) : TOK_SLOW;
-    return kind == K_EOB ? (TOK_EOB | cl) : TOK_SLOW;
+    uint32_t wl = cl | (1u << 6) | (((e >> 8) & 255u) << 15);
+    if (CHECK) wl = kind == K_LITX ? TOK_ASCII : wl;
+    const uint32_t wm = ((ed >> 4) & 15u) == K_LEN ? (u + dl + dex) | (len << 6) | (dist << 15) : TOK_SLOW;
+    const uint32_t wo = kind == K_EOB ? (TOK_EOB | cl) : TOK_SLOW;
+    return (kind & 7u) == K_LIT ? wl : kind == K_LEN ? wm : wo;
+  }
+
+  // Token words at bit offsets k (wa) and k + 64 (wb): both
+  // literal/length lookups, then both distance lookups.
+  template <bool CHECK>
+  __device__ __forceinline__ void token_pair(uint64_t wa, uint64_t wb, uint32_t &ta, uint32_t &tb) const {
+    const uint32_t LMASK = (1u << LIT_BITS) - 1u, DMASK = (1u << DIST_BITS) - 1u;
+    const uint32_t ea = sh_lit((uint32_t)wa & LMASK);
+    const uint32_t eb = sh_lit((uint32_t)wb & LMASK);
+    const uint32_t ua = (ea & 15u) + ((ea >> 8) & 15u), ub = (eb & 15u) + ((eb >> 8) & 15u);
+    const uint32_t eda = sh_dist((uint32_t)(wa >> ua) & DMASK);
+    const uint32_t edb = sh_dist((uint32_t)(wb >> ub) & DMASK);
+    ta = token_word<CHECK>(wa, ea, eda);
+    tb = token_word<CHECK>(wb, eb, edb);
   }
 
   // Huffman-coded block body until end-of-block (section 3.2.5), decoded in
@@ -325,8 +339,9 @@ struct Inflater {
         const uint32_t a0 = lo_half ? q[0] : q[1], a1 = lo_half ? q[1] : q[2], a2 = lo_half ? q[2] : q[3];
         const uint32_t b2 = lo_half ? q[4] : q[5];
         const uint32_t b0 = a2, b1 = lo_half ? q[3] : q[4];
-        tok0 = token_at<CHECK>(__builtin_amdgcn_alignbit(a1, a0, sh), __builtin_amdgcn_alignbit(a2, a1, sh));
-        tok1 = token_at<CHECK>(__builtin_amdgcn_alignbit(b1, b0, sh), __builtin_amdgcn_alignbit(b2, b1, sh));
+        const uint64_t wa = ((uint64_t)__builtin_amdgcn_alignbit(a2, a1, sh) << 32) | __builtin_amdgcn_alignbit(a1, a0, sh);
+        const uint64_t wb = ((uint64_t)__builtin_amdgcn_alignbit(b2, b1, sh) << 32) | __builtin_amdgcn_alignbit(b1, b0, sh);
+        token_pair<CHECK>(wa, wb, tok0, tok1);
         off = 0;
         need = false;
       }
