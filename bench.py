@@ -299,11 +299,13 @@ def main():
     dev = torch.device("cuda:0")
     d_comp = torch.frombuffer(bytearray(comp), dtype=torch.uint8).to(dev)
     out = torch.empty(len(raw), dtype=torch.uint8, device=dev)
-    chunk_bytes = args.chunk_bytes or gz.DEFAULT_CHUNK_BYTES
     window = args.window or gz.DEFAULT_WINDOW
-    plan = gz.Plan(d_comp, 0, chunk_bytes=chunk_bytes, waves_per_chunk=args.waves_per_chunk,
+    # chunk_bytes 0: the library's default (about 48 KiB, the count rounded to
+    # whole rounds of the persistent decoder)
+    plan = gz.Plan(d_comp, 0, chunk_bytes=args.chunk_bytes, waves_per_chunk=args.waves_per_chunk,
                    window_syms=window, timing=1)
     n_chunks = plan.n_chunks
+    chunk_bytes = (plan.info.payload_end - plan.info.payload_start + n_chunks - 1) // n_chunks
     log(f"plan: {n_chunks} chunks, workspace {plan.info.ws_bytes / 2**30:.2f} GiB")
     stream = torch.cuda.current_stream()
 

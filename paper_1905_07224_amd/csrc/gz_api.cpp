@@ -210,6 +210,15 @@ static int read_member(const gz_job &j, uint32_t f, int64_t *h_out, uint32_t *cr
   return GZ_OK;
 }
 
+// Chunks the persistent inflate grid decodes at once (one wave each).
+static uint64_t decode_slots(gz_plan_t p) {
+  const uint32_t lds_per_cu = 160 * 1024;
+  const uint32_t per_wave = inflate_lds_bytes(p->win) + 256;
+  const uint32_t waves_per_cu = p->opts.inflate_waves_per_cu ? p->opts.inflate_waves_per_cu
+                                                             : std::max<uint32_t>(1, lds_per_cu / per_wave);
+  return (uint64_t)waves_per_cu * (uint64_t)std::max(1, p->n_cu);
+}
+
 static int plan_common(gz_plan_t p) {
   const uint32_t F = (uint32_t)p->jobs.size();
   p->files.clear();
@@ -554,11 +563,7 @@ static int launch(gz_plan_t p, uint8_t *ws, size_t ws_bytes, hipStream_t st) {
   uint8_t *wins = ws + L.win_off;
   uint16_t *pool = (uint16_t *)(ws + L.sym_off);
 
-  const uint32_t lds_per_cu = 160 * 1024;
-  const uint32_t per_wave = inflate_lds_bytes(p->win) + 256;
-  uint32_t waves_per_cu = p->opts.inflate_waves_per_cu ? p->opts.inflate_waves_per_cu
-                                                       : std::max<uint32_t>(1, lds_per_cu / per_wave);
-  uint32_t grid = std::min<uint32_t>(N, waves_per_cu * (uint32_t)p->n_cu);
+  uint32_t grid = (uint32_t)std::min<uint64_t>(N, decode_slots(p));
   if (grid == 0) grid = 1;
 
   mark();

@@ -510,13 +510,27 @@ __device__ __forceinline__ bool start_stage1(const Src &s, uint64_t b) {
   return left == 0;
 }
 
+// Kraft sums of three code-length code lengths at once: entry i (9 bits,
+// three 3-bit lengths) is the sum of 128 >> L over its nonzero lengths L.
+__device__ __forceinline__ void kraft3_fill(uint8_t *k3, int tid, int nthreads) {
+  for (int i = tid; i < 512; i += nthreads) {
+    uint32_t v = 0;
+    for (int f = 0; f < 3; f++) {
+      const uint32_t L = ((uint32_t)i >> (3 * f)) & 7u;
+      if (L) v += 128u >> L;
+    }
+    k3[i] = (uint8_t)v;
+  }
+}
+
 // The cheap stage for the 32 candidates of one aligned dword at once: bit k
 // of the result is start_stage1 of bit 32 * W + k of the aligned view (file
 // bit 32 * W + k - 8 * mis).  x0..x3: dwords W .. W + 3 (zero past the
 // buffer).  The 3-bit header pattern is tested for all 32 positions with
 // word operations; the rest only where it holds (one position in eight).
+// The code-length code's Kraft sum takes seven lookups in k3 (kraft3_fill).
 __device__ __forceinline__ uint32_t start_stage1_word(const Src &s, int64_t W, uint32_t x0, uint32_t x1, uint32_t x2,
-                                                      uint32_t x3) {
+                                                      uint32_t x3, const uint8_t *k3) {
   const uint64_t lo = ((uint64_t)x1 << 32) | x0;
   uint32_t pat = (uint32_t)(~lo & ~(lo >> 1) & (lo >> 2));  // BFINAL = 0, BTYPE = 10
   uint32_t pass = 0;
@@ -531,17 +545,106 @@ __device__ __forceinline__ uint32_t start_stage1_word(const Src &s, int64_t W, u
     const uint32_t w2 = __builtin_amdgcn_alignbit(x3, x2, k);
     if (((w0 >> 3) & 31u) > 29u || ((w0 >> 8) & 31u) > 29u) continue;
     const uint32_t hclen = ((w0 >> 13) & 15u) + 4u;
-    // code-length code lengths: 3 bits each from bit 17
-    const uint64_t cl = (uint64_t)(w0 >> 17) | ((uint64_t)w1 << 15) | ((uint64_t)w2 << 47);
-    int left = 128;
-#pragma unroll
-    for (uint32_t i = 0; i < 19; i++) {
-      const uint32_t L = (uint32_t)(cl >> (3 * i)) & 7u;
-      if (i < hclen && L) left -= 128 >> L;
-    }
-    if (left == 0) pass |= 1u << k;
+    // code-length code lengths: 3 bits each from bit 17, hclen of them
+    const uint64_t cl = ((uint64_t)(w0 >> 17) | ((uint64_t)w1 << 15) | ((uint64_t)w2 << 47)) &
+                        ((1ull << (3 * hclen)) - 1ull);
+    const uint32_t sum = (uint32_t)k3[cl & 511u] + k3[(cl >> 9) & 511u] + k3[(cl >> 18) & 511u] +
+                         k3[(cl >> 27) & 511u] + k3[(cl >> 36) & 511u] + k3[(cl >> 45) & 511u] + k3[cl >> 54];
+    if (sum == 128u) pass |= 1u << k;
   }
   return pass;
+}
+
+// The checks of read_dynamic_tables(strict, nothing stored), with the
+// code-length symbols decoded speculatively: in a round of 128 bit offsets
+// lane k decodes the symbol that would start at offset k and at k + 64 (one
+// lookup each in the code-length table, extra bits included), then a scalar
+// walk follows the real symbols from offset 0.  The walk keeps what the
+// final checks need (the Kraft sums of the literal/length and distance
+// codes, the end-of-block code's length, the number of distance codes and
+// of 1-bit ones), so no code length is stored and no table is built.
+__device__ __forceinline__ uint32_t cl_symbol_word(uint32_t bits, const TablesLDS &sh) {
+  const uint32_t e = sh.dist[bits & 127u];
+  const uint32_t cl = e & 15u, sym = e >> 8;
+  const uint32_t ex = sym == 16u ? 2u : sym == 17u ? 3u : sym == 18u ? 7u : 0u;
+  const uint32_t extra = (bits >> cl) & ((1u << ex) - 1u);
+  return (cl + ex) | (sym << 4) | (extra << 9);  // bits used, symbol, extra value
+}
+
+__device__ int check_dynamic_tables(WaveBits &br, TablesLDS &sh) {
+  const int lane = lane_id();
+  uint64_t v = br.next();
+  const uint32_t hlit = (uint32_t)(v & 31u) + 257u;
+  const uint32_t hdist = (uint32_t)((v >> 5) & 31u) + 1u;
+  const uint32_t hclen = (uint32_t)((v >> 10) & 15u) + 4u;
+  br.skip(14);
+  if (hlit > 286u || hdist > 30u) return D_BAD;
+  v = br.next();
+  if (lane < 19) sh.lens[lane] = 0;
+  wave_sync();
+  if (lane < (int)hclen) {
+    const uint64_t ord_lo = (16ull) | (17ull << 5) | (18ull << 10) | (0ull << 15) | (8ull << 20) | (7ull << 25) |
+                            (9ull << 30) | (6ull << 35) | (10ull << 40) | (5ull << 45) | (11ull << 50) |
+                            (4ull << 55);
+    const uint64_t ord_hi = (12ull) | (3ull << 5) | (13ull << 10) | (2ull << 15) | (14ull << 20) | (1ull << 25) |
+                            (15ull << 30);
+    uint32_t sym = lane < 12 ? (uint32_t)((ord_lo >> (5 * lane)) & 31u) : (uint32_t)((ord_hi >> (5 * (lane - 12))) & 31u);
+    sh.lens[sym] = (uint8_t)((v >> (3 * lane)) & 7u);
+  }
+  br.skip(3 * hclen);
+  wave_sync();
+  int ncl;
+  if (build_tree<CL_BITS, TREE_CL>(sh.lens, 19, sh.dist, &sh.di, sh.dsorted, &ncl, true) != 0) return D_BAD;
+  wave_sync();
+  const uint32_t total = hlit + hdist;
+  uint32_t i = 0, prev = 0, eob = 0, ndist = 0, d1 = 0;
+  int lit_left = 32768, dist_left = 32768;
+  const uint32_t sh5 = (uint32_t)lane & 31u;
+  const bool lo_half = lane < 32;
+  while (i < total) {
+    uint32_t q[6];
+    br.view192(q);
+    const uint32_t ta = cl_symbol_word(lo_half ? __builtin_amdgcn_alignbit(q[1], q[0], sh5)
+                                               : __builtin_amdgcn_alignbit(q[2], q[1], sh5), sh);
+    const uint32_t tb = cl_symbol_word(lo_half ? __builtin_amdgcn_alignbit(q[3], q[2], sh5)
+                                               : __builtin_amdgcn_alignbit(q[4], q[3], sh5), sh);
+    uint32_t off = 0;
+    while (off < 128u && i < total) {
+      const uint32_t t = (uint32_t)__builtin_amdgcn_readlane(off < 64u ? (int)ta : (int)tb, (int)(off & 63u));
+      const uint32_t sym = (t >> 4) & 31u, extra = t >> 9;
+      uint32_t L, n;
+      if (sym < 16u) {
+        L = sym;
+        n = 1;
+      } else if (sym == 16u) {
+        if (i == 0) return D_BAD;
+        L = prev;
+        n = 3u + extra;
+      } else {
+        L = 0;
+        n = (sym == 17u ? 3u : 11u) + extra;
+      }
+      if (i + n > total) return D_BAD;
+      if (L) {
+        const uint32_t nl = i < hlit ? min(i + n, hlit) - i : 0u;
+        lit_left -= (int)nl << (15 - L);
+        dist_left -= (int)(n - nl) << (15 - L);
+        ndist += n - nl;
+        if (L == 1u) d1 += n - nl;
+      }
+      if (i <= 256u && 256u < i + n) eob = L;
+      prev = L;
+      i += n;
+      off += t & 15u;
+      if (br.pos + off > br.s.end_bits) return D_TRUNC;
+      if (lit_left < 0 || dist_left < 0) return D_BAD;
+    }
+    br.skip(off);
+  }
+  if (eob == 0) return D_BAD;                  // no end-of-block code
+  if (lit_left != 0) return D_BAD;             // literal/length code incomplete
+  if (dist_left > 0 && ndist != 0 && !(ndist == 1u && d1 == 1u)) return D_BAD;
+  return D_OK;
 }
 
 // Full static check, whole wave: the dynamic tables at b + 3 are valid.
@@ -549,8 +652,7 @@ __device__ __forceinline__ bool start_stage2(const Src &s, uint64_t b, TablesLDS
   WaveBits br;
   br.s = s;
   br.init(b + 3);
-  bool nd;
-  return read_dynamic_tables(br, sh, true, false, &nd) == D_OK;
+  return check_dynamic_tables(br, sh) == D_OK;
 }
 
 // First candidate in [from, to) that passes the static checks, whole wave.

@@ -711,6 +711,9 @@ __global__ void k_init(ChunkState *cs, uint32_t n_chunks, FileState *fs, uint32_
 __global__ __launch_bounds__(256) void k_scan(const FileDesc *files, const ChunkDesc *chunks, ChunkState *cs,
                                               const uint32_t *scan_list, uint32_t n_scan, uint32_t groups) {
   __shared__ TablesLDS sh[4];
+  __shared__ uint8_t k3[512];
+  kraft3_fill(k3, (int)threadIdx.x, (int)blockDim.x);
+  __syncthreads();
   const uint32_t item = blockIdx.x / groups, g = blockIdx.x % groups;
   if (item >= n_scan) return;
   const uint32_t c = scan_list[item];
@@ -733,7 +736,7 @@ __global__ __launch_bounds__(256) void k_scan(const FileDesc *files, const Chunk
     const int64_t W = Wt + lane;
     uint32_t surv = 0;
     if (W < W1) {
-      surv = start_stage1_word(s, W, s.dw(W), s.dw(W + 1), s.dw(W + 2), s.dw(W + 3));
+      surv = start_stage1_word(s, W, s.dw(W), s.dw(W + 1), s.dw(W + 2), s.dw(W + 3), k3);
       // only candidates in [lo_bit, hi_bit): bits [klo, khi) of this dword
       const int64_t b0 = 32 * W - mb;
       const int64_t klo = std::min<int64_t>(32, std::max<int64_t>(0, (int64_t)cd.lo_bit - b0));

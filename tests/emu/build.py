@@ -11,13 +11,14 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(os.path.dirname(HERE))
 CSRC = os.path.join(ROOT, "paper_1905_07224_amd", "csrc")
 LIB = os.path.join(HERE, "libgzemu.so")
-SRCS = [os.path.join(CSRC, "gz_kernels.hip"), os.path.join(CSRC, "gz_api.cpp"), os.path.join(CSRC, "gz_serve.cpp"),
+# stage2_diff.cpp includes gz_kernels.hip (one translation unit for the kernels)
+SRCS = [os.path.join(HERE, "stage2_diff.cpp"), os.path.join(CSRC, "gz_api.cpp"), os.path.join(CSRC, "gz_serve.cpp"),
         os.path.join(HERE, "emu_rt.cpp")]
 CXX = "/opt/rocm/lib/llvm/bin/clang++" if os.path.exists("/opt/rocm/lib/llvm/bin/clang++") else "clang++"
 
 
 def build(opt="-O1", extra=()):
-    deps = SRCS + [os.path.join(HERE, "include", "hip", "hip_runtime.h")] + [
+    deps = SRCS + [os.path.join(CSRC, "gz_kernels.hip"), os.path.join(HERE, "include", "hip", "hip_runtime.h")] + [
         os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h")]
     if os.path.exists(LIB) and os.path.getmtime(LIB) >= max(os.path.getmtime(d) for d in deps) and not extra:
         return LIB

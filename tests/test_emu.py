@@ -301,3 +301,60 @@ def test_emu_random_access_undetermined(orc, level):
     n_win = (und.size + 3601) // 3602
     ref_counts = np.add.reduceat(und.astype(np.int64), np.arange(0, und.size, 3602)) if und.size else []
     assert n_win == counts.size and np.array_equal(counts, ref_counts)
+
+
+def _stage1_survivors(comp: bytes, limit_bits: int):
+    """Bits passing the cheap block-start checks (header pattern, HLIT and
+    HDIST ranges, complete code-length code), computed with numpy."""
+    bits = np.unpackbits(np.frombuffer(comp, np.uint8), bitorder="little").astype(np.int64)
+    n = min(bits.size - 17 - 57, limit_bits)
+    b = np.arange(n)
+    b = b[(bits[b] == 0) & (bits[b + 1] == 0) & (bits[b + 2] == 1)]
+
+    def field(off, width):
+        v = np.zeros(b.size, np.int64)
+        for k in range(width):
+            v |= bits[b + off + k] << k
+        return v
+
+    ok = (field(3, 5) <= 29) & (field(8, 5) <= 29)
+    b = b[ok]
+    hclen = field(13, 4) + 4
+    left = np.full(b.size, 128, np.int64)
+    for i in range(19):
+        L = field(17 + 3 * i, 3)
+        left -= np.where((i < hclen) & (L > 0), 128 >> L, 0)
+    return b[left == 0]
+
+
+@pytest.mark.parametrize("kind", ["fastq6", "words1", "dna9", "binary6"])
+def test_emu_scan_table_check_equals_decoder(orc, kind):
+    """The scan's speculative table check accepts exactly the candidates the
+    decoder's table reader accepts, and both agree with the oracle's static
+    block-start check (Appendix A)."""
+    import ctypes as C
+
+    raw = {"fastq6": lambda: synth.fastq_like(3 << 20, 331), "words1": lambda: synth.word_stream(3 << 20, 332),
+           "dna9": lambda: synth.random_dna(3 << 20, 333),
+           "binary6": lambda: np.random.default_rng(334).integers(0, 256, 2 << 20, dtype=np.uint8).tobytes()}[kind]()
+    level = int(kind[-1])
+    comp = synth.gzip_member(raw, level)
+    # the stage-1 survivors of the first MiB; the true (non-final, dynamic)
+    # block starts there are among them
+    cand = _stage1_survivors(comp, 8 * min(len(comp), 1 << 20)).astype(np.uint64)
+    g = orc.gunzip(comp)
+    true_starts = set(int(x) for x, t, f in zip(g.block_bit, g.block_type, g.block_final)
+                      if t == 2 and not f and x < 8 * (1 << 20))
+    assert true_starts <= set(int(x) for x in cand) and cand.size > 50
+    L = E.lib()
+    L.emu_stage2_diff.argtypes = [C.c_void_p, C.c_uint64, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]
+    store = E.padded(comp)
+    r_read = np.zeros(cand.size, np.int32)
+    r_check = np.zeros(cand.size, np.int32)
+    L.emu_set_sync_limit(0)
+    L.emu_stage2_diff(store.ctypes.data, len(comp), cand.ctypes.data, cand.size, r_read.ctypes.data,
+                      r_check.ctypes.data)
+    assert np.array_equal(r_read, r_check), np.nonzero(r_read != r_check)[0][:10]
+    ref = np.array([orc.block_static(comp, int(x))[0] for x in cand], np.int32)
+    assert np.array_equal(r_check, ref)
+    assert all(r_check[np.searchsorted(cand, t)] for t in true_starts)
