@@ -53,8 +53,8 @@ extern "C" {
 typedef struct gz_opts {
   uint64_t chunk_bytes;   /* nominal compressed bytes per chunk when n_chunks == 0 (default 48 KiB) */
   uint32_t sym_factor;    /* symbol capacity per chunk = sym_factor * compressed bytes + slack (default 8) */
-  uint32_t window_syms;   /* LDS history ring per decoding wave, in symbols: 2048, 4096, 8192, 16384 or
-                             32768 (default 2048); match sources further back are read from HBM.
+  uint32_t window_syms;   /* LDS history ring per decoding wave, in symbols: 1024, 2048, 4096, 8192, 16384
+                             or 32768 (default 1024); match sources further back are read from HBM.
                              Any other value: GZ_E_ARG */
   uint32_t scan_groups;   /* workgroups that search one chunk's start in parallel (default: 4096 / chunks, 1..64) */
   uint32_t inflate_waves_per_cu; /* persistent inflate grid = this * CU count (default: occupancy) */
@@ -140,8 +140,8 @@ int gz_decompress_batch(gz_plan_t plan, void *d_ws, size_t ws_bytes, void *strea
  * Errors as gz_decompress_batch. */
 int gz_decompress_graph(gz_plan_t plan, void *d_ws, size_t ws_bytes, void *stream);
 
-/* Choose opts.chunk_bytes (32 KiB .. 1 MiB) and opts.window_syms (2048,
- * 4096 or 8192) for one file by timing each candidate on it (two runs each,
+/* Choose opts.chunk_bytes (32 KiB .. 1 MiB) and opts.window_syms (1024,
+ * 2048 or 4096) for one file by timing each candidate on it (two runs each,
  * the second timed with HIP events on `stream`), and cache the choice per
  * (device, compressed-size class, compression-ratio class) for the process;
  * a cached choice returns at once.  *best: in, the other options; out, the

@@ -118,7 +118,7 @@ EXPORTS = ["gz_plan", "gz_plan_batch", "gz_plan_info", "gz_decompress", "gz_deco
 GZ_N_PASSES = N_PASSES = 13
 # defaults of gz_opts (include/gzgpu.h)
 DEFAULT_CHUNK_BYTES = 48 << 10
-DEFAULT_WINDOW = 2048
+DEFAULT_WINDOW = 1024
 
 
 def lib():

@@ -395,7 +395,7 @@ static int make_plan(gz_plan_t *plan, const gz_job *jobs, int n, const gz_opts *
   gz_plan_t p = new (std::nothrow) gz_plan_s();
   if (!p) return GZ_E_ARG;
   fill_defaults(p, opts);
-  if (p->win != 2048 && p->win != 4096 && p->win != 8192 && p->win != 16384 && p->win != 32768) {
+  if (p->win != 1024 && p->win != 2048 && p->win != 4096 && p->win != 8192 && p->win != 16384 && p->win != 32768) {
     gz_plan_destroy(p);
     return GZ_E_ARG;
   }
@@ -446,7 +446,7 @@ int gz_plan_probes(gz_plan_t *plan, const void *d_comp, size_t comp_len, const u
   gz_plan_t p = new (std::nothrow) gz_plan_s();
   if (!p) return GZ_E_ARG;
   fill_defaults(p, opts);
-  if (p->win != 2048 && p->win != 4096 && p->win != 8192 && p->win != 16384 && p->win != 32768) {
+  if (p->win != 1024 && p->win != 2048 && p->win != 4096 && p->win != 8192 && p->win != 16384 && p->win != 32768) {
     gz_plan_destroy(p);
     return GZ_E_ARG;
   }
@@ -851,7 +851,7 @@ namespace {
 std::mutex g_tune_mu;
 std::map<std::tuple<int, int, int>, gz_opts> g_tune;
 const uint64_t k_tune_chunks[] = {32ull << 10, 48ull << 10, 64ull << 10, 128ull << 10, 256ull << 10, 1ull << 20};
-const uint32_t k_tune_rings[] = {2048, 4096, 8192};
+const uint32_t k_tune_rings[] = {1024, 2048, 4096};
 }  // namespace
 
 int gz_autotune(const void *d_comp, size_t comp_len, void *d_out, size_t out_cap, void *d_ws, size_t ws_bytes,

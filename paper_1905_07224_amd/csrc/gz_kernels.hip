@@ -53,7 +53,7 @@ struct Inflater {
   // stores before it, so those are complete, and the read bypasses the L1,
   // which may still hold lines of an earlier attempt at this chunk.  The unit
   // being moved to HBM is never older than 512 + 64 symbols.
-  static_assert(WIN >= 2048 && WIN <= 32768 && (WIN & (WIN - 1)) == 0, "ring size");
+  static_assert(WIN >= 1024 && WIN <= 32768 && (WIN & (WIN - 1)) == 0, "ring size");
   static constexpr uint32_t RMASK = WIN - 1;
 
   InflateLDS<WIN> &sh;
@@ -1724,6 +1724,10 @@ hipError_t gzk_scan(const FileDesc *files, const ChunkDesc *chunks, ChunkState *
 
 #define GZ_WIN_SWITCH(win, CALL)   \
   switch (win) {                   \
+    case 1024: {                   \
+      constexpr int W = 1024;      \
+      CALL;                        \
+    } break;                       \
     case 2048: {                   \
       constexpr int W = 2048;      \
       CALL;                        \
