@@ -1594,6 +1594,22 @@ __global__ __launch_bounds__(256) void k_crc(const FileDesc *files, uint32_t n_f
   uint32_t r = 0;
   uint64_t p = a;
   if (((uintptr_t)out & 15u) == 0) {
+    // a whole 128-byte line per lane per step, loaded before it is folded in
+    // (lanes are CRC_LANE bytes apart, so each line is fetched once)
+    for (; p + 128 <= b; p += 128) {
+      uint4 q[8];
+#pragma unroll
+      for (int u = 0; u < 8; u++) q[u] = *reinterpret_cast<const uint4 *>(out + p + 16 * u);
+#pragma unroll
+      for (int u = 0; u < 8; u++) {
+        const uint32_t w4[4] = {q[u].x, q[u].y, q[u].z, q[u].w};
+#pragma unroll
+        for (int h = 0; h < 4; h++) {
+          const uint32_t w = r ^ w4[h];
+          r = S[3][w & 0xFFu] ^ S[2][(w >> 8) & 0xFFu] ^ S[1][(w >> 16) & 0xFFu] ^ S[0][w >> 24];
+        }
+      }
+    }
     for (; p + 16 <= b; p += 16) {
       const uint4 q = *reinterpret_cast<const uint4 *>(out + p);
       const uint32_t w4[4] = {q.x, q.y, q.z, q.w};
