@@ -647,6 +647,134 @@ __device__ int check_dynamic_tables(WaveBits &br, TablesLDS &sh) {
   return D_OK;
 }
 
+// The same checks as check_dynamic_tables for one candidate per lane, with
+// no wave operation (lanes check different candidates): the code-length
+// code's lookup table is built by the lane in its own column of `tab`
+// (128 entries, entry x at tab[64 * x + lane]: symbol | length << 5), and
+// the code lengths are read through a per-lane 64-bit bit buffer.
+struct LaneBits {
+  const Src *s;
+  int64_t D;     // next aligned dword to load
+  uint64_t acc;  // unread bits, first one in bit 0
+  uint32_t n;    // bits in acc (>= 32 after every refill)
+  uint64_t pos;  // file bit of acc's bit 0
+  __device__ __forceinline__ void init(const Src &src, uint64_t b) {
+    s = &src;
+    const uint64_t a = b + 8ull * src.mis;
+    D = (int64_t)(a >> 5);
+    const uint32_t sh = (uint32_t)(a & 31);
+    acc = (uint64_t)src.dw(D) >> sh;
+    n = 32 - sh;
+    D++;
+    acc |= (uint64_t)src.dw(D) << n;
+    n += 32;
+    D++;
+    pos = b;
+  }
+  __device__ __forceinline__ void skip(uint32_t k) {
+    acc >>= k;
+    n -= k;
+    pos += k;
+    if (n < 32) {
+      acc |= (uint64_t)s->dw(D) << n;
+      n += 32;
+      D++;
+    }
+  }
+};
+
+__device__ __forceinline__ bool lane_tables_ok(const Src &s, uint64_t b, uint8_t *tab, int lane) {
+  LaneBits br;
+  br.init(s, b + 3);
+  const uint32_t hlit = (uint32_t)(br.acc & 31u) + 257u;
+  const uint32_t hdist = (uint32_t)((br.acc >> 5) & 31u) + 1u;
+  const uint32_t hclen = (uint32_t)((br.acc >> 10) & 15u) + 4u;
+  br.skip(14);
+  if (hlit > 286u || hdist > 30u) return false;
+  // code-length code lengths by symbol, 3 bits each (order 16 17 18 0 8 7 9
+  // 6 10 5 11 4 12 3 13 2 14 1 15 in the stream)
+  // (the buffer holds at least 32 bits: the lengths are read as up to 10,
+  // then up to 9 more)
+  const uint32_t h1 = hclen < 10u ? hclen : 10u, h2 = hclen - h1;
+  uint64_t w = br.acc & ((1ull << (3 * h1)) - 1ull);
+  br.skip(3 * h1);
+  w |= (br.acc & ((1ull << (3 * h2)) - 1ull)) << 30;
+  br.skip(3 * h2);
+  const uint8_t order[19] = {16, 17, 18, 0, 8, 7, 9, 6, 10, 5, 11, 4, 12, 3, 13, 2, 14, 1, 15};
+  uint64_t bysym = 0;
+#pragma unroll
+  for (int i = 0; i < 19; i++) bysym |= ((w >> (3 * i)) & 7ull) << (3 * order[i]);
+  // lengths per length value (8 bits each), the Kraft sum, first codes
+  uint64_t cnt = 0;
+#pragma unroll
+  for (int sy = 0; sy < 19; sy++) {
+    const uint32_t L = (uint32_t)(bysym >> (3 * sy)) & 7u;
+    cnt += L ? 1ull << (8 * L) : 0ull;
+  }
+  uint32_t kraft = 0;
+  uint64_t next = 0;  // next code of each length (8 bits each)
+  uint32_t code = 0;
+#pragma unroll
+  for (int L = 1; L <= 7; L++) {
+    const uint32_t c = (uint32_t)(cnt >> (8 * L)) & 255u;
+    kraft += c << (7 - L);
+    code = (code + (L > 1 ? (uint32_t)(cnt >> (8 * (L - 1))) & 255u : 0u)) << 1;
+    next |= (uint64_t)code << (8 * L);
+  }
+  if (kraft != 128u) return false;
+  // the lane's table: every 7-bit index whose first L stream bits are the
+  // symbol's code (read first bit first) holds the symbol
+  for (int sy = 0; sy < 19; sy++) {
+    const uint32_t L = (uint32_t)(bysym >> (3 * sy)) & 7u;
+    if (!L) continue;
+    const uint32_t c = (uint32_t)(next >> (8 * L)) & 255u;
+    next += 1ull << (8 * L);
+    const uint32_t rev = __builtin_bitreverse32(c) >> (32 - L);
+    for (uint32_t k = 0; k < (1u << (7 - L)); k++) tab[64u * (rev | (k << L)) + (uint32_t)lane] = (uint8_t)(sy | (L << 5));
+  }
+  const uint32_t total = hlit + hdist;
+  uint32_t i = 0, prev = 0, eob = 0, ndist = 0, d1 = 0;
+  int lit_left = 32768, dist_left = 32768;
+  for (uint32_t it = 0; it < 320u && i < total; it++) {
+    const uint32_t e = tab[64u * (uint32_t)(br.acc & 127u) + (uint32_t)lane];
+    const uint32_t sym = e & 31u, cl = e >> 5;
+    uint32_t L, rep;
+    if (sym < 16u) {
+      br.skip(cl);
+      L = sym;
+      rep = 1;
+    } else {
+      const uint32_t ex = sym == 16u ? 2u : sym == 17u ? 3u : 7u;
+      const uint32_t extra = (uint32_t)(br.acc >> cl) & ((1u << ex) - 1u);
+      br.skip(cl + ex);
+      if (sym == 16u) {
+        if (i == 0) return false;
+        L = prev;
+        rep = 3u + extra;
+      } else {
+        L = 0;
+        rep = (sym == 17u ? 3u : 11u) + extra;
+      }
+    }
+    if (i + rep > total) return false;
+    if (L) {
+      const uint32_t nl = i < hlit ? min(i + rep, hlit) - i : 0u;
+      lit_left -= (int)nl << (15 - L);
+      dist_left -= (int)(rep - nl) << (15 - L);
+      ndist += rep - nl;
+      if (L == 1u) d1 += rep - nl;
+    }
+    if (i <= 256u && 256u < i + rep) eob = L;
+    prev = L;
+    i += rep;
+    if (br.pos > s.end_bits) return false;
+    if (lit_left < 0 || dist_left < 0) return false;
+  }
+  if (i < total || eob == 0 || lit_left != 0) return false;
+  if (dist_left > 0 && ndist != 0 && !(ndist == 1u && d1 == 1u)) return false;
+  return true;
+}
+
 // Full static check, whole wave: the dynamic tables at b + 3 are valid.
 __device__ __forceinline__ bool start_stage2(const Src &s, uint64_t b, TablesLDS &sh) {
   WaveBits br;

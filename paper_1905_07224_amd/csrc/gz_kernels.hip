@@ -702,16 +702,27 @@ __global__ void k_init(ChunkState *cs, uint32_t n_chunks, FileState *fs, uint32_
 // k_scan: for every chunk after the first of its file, the smallest bit in
 // [lo_bit, hi_bit) passing the static checks.  A wave covers 2048 candidate
 // bits per step, one aligned dword per lane (the cheap stage for all 32 bits
-// of it at once); the survivors, rare, then get the full static check in bit
-// order by the whole wave.  `groups` workgroups share one chunk and its
-// 4 waves each take steps in an interleaved order; a step is skipped once a
-// passing candidate before it is known.
+// of it at once).  The survivors, rare, are queued in bit order; every
+// SCAN_BATCH of them (and the rest at the end) are checked at once, one per
+// lane (the full table check), and the first that passes is the wave's
+// answer.  `groups` workgroups share one chunk and its 4 waves each take
+// steps in an interleaved order; a step is skipped once a passing candidate
+// before it is known.
 // ---------------------------------------------------------------------------
+
+constexpr uint32_t SCAN_BATCH = 64;
+
+__device__ __forceinline__ uint64_t readlane64(uint64_t v, int l) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
+  return ((uint64_t)hi << 32) | lo;
+}
 
 __global__ __launch_bounds__(256) void k_scan(const FileDesc *files, const ChunkDesc *chunks, ChunkState *cs,
                                               const uint32_t *scan_list, uint32_t n_scan, uint32_t groups) {
-  __shared__ TablesLDS sh[4];
   __shared__ uint8_t k3[512];
+  __shared__ uint8_t cltab[4][128 * 64];                  // per lane code-length tables, per wave
+  __shared__ unsigned long long queue[4][2 * SCAN_BATCH];  // per wave: survivors in bit order
   kraft3_fill(k3, (int)threadIdx.x, (int)blockDim.x);
   __syncthreads();
   const uint32_t item = blockIdx.x / groups, g = blockIdx.x % groups;
@@ -723,12 +734,34 @@ __global__ __launch_bounds__(256) void k_scan(const FileDesc *files, const Chunk
   const uint32_t wave = uni32(threadIdx.x >> 6);
   const int lane = lane_id();
   unsigned long long *cand = (unsigned long long *)&cs[c].cand;
+  unsigned long long *q = queue[wave];
+  uint32_t nq = 0;  // queued survivors
+  // check the first k queued survivors, one per lane: true when one passed
+  // (its bit went to the chunk's candidate); else they are dropped
+  auto check = [&](uint32_t k) -> bool {
+    wave_sync();
+    const uint64_t cur = uni64(__hip_atomic_load(cand, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    const uint64_t b = (uint32_t)lane < k ? (uint64_t)q[lane] : NONE;
+    const bool ok = b < cur && lane_tables_ok(s, b, cltab[wave], lane);
+    const uint64_t m = __ballot(ok);
+    if (m) {
+      const uint64_t bb = readlane64(b, __ffsll((unsigned long long)m) - 1);
+      if (lane == 0) atomicMin(cand, (unsigned long long)bb);
+      return true;
+    }
+    const uint64_t rest = (uint32_t)lane + k < nq ? (uint64_t)q[lane + k] : 0ull;
+    wave_sync();
+    if ((uint32_t)lane + k < nq) q[lane] = rest;
+    nq -= k;
+    return false;
+  };
   // aligned-view dwords holding the range
   const int64_t mb = 8 * (int64_t)s.mis;
   const int64_t W0 = ((int64_t)cd.lo_bit + mb) >> 5;
   const int64_t W1 = ((int64_t)cd.hi_bit + mb + 31) >> 5;
   const uint64_t steps = (uint64_t)(W1 - W0 + 63) / 64;
-  for (uint64_t t = (uint64_t)g + (uint64_t)groups * wave; t < steps; t += (uint64_t)groups * 4u) {
+  bool found = false;
+  for (uint64_t t = (uint64_t)g + (uint64_t)groups * wave; t < steps && !found; t += (uint64_t)groups * 4u) {
     const int64_t Wt = W0 + 64 * (int64_t)t;
     const uint64_t first_bit = (uint64_t)std::max<int64_t>(32 * Wt - mb, (int64_t)cd.lo_bit);
     const uint64_t cur = uni64(__hip_atomic_load(cand, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
@@ -744,28 +777,24 @@ __global__ __launch_bounds__(256) void k_scan(const FileDesc *files, const Chunk
       const uint64_t keep = khi > klo ? (((1ull << (khi - klo)) - 1ull) << klo) : 0ull;
       surv &= (uint32_t)keep;
     }
+    // queue the survivors in bit order (lanes in order, bits within a lane)
     uint64_t m = __ballot(surv != 0);
-    bool done = false;
-    for (int q = 0; q < 64 && m && !done; q++) {
+    for (int r = 0; r < 64 && m && !found; r++) {
       const int l = __ffsll((unsigned long long)m) - 1;
       m &= m - 1;
       uint32_t sl = (uint32_t)__builtin_amdgcn_readlane((int)surv, l);
-      for (int r = 0; r < 32 && sl; r++) {
+      for (int x = 0; x < 32 && sl && !found; x++) {
         const uint32_t k = (uint32_t)__builtin_ctz(sl);
         sl &= sl - 1;
-        const uint64_t bb = (uint64_t)(32 * (Wt + l) - mb) + k;
-        if (bb >= uni64(__hip_atomic_load(cand, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
-          done = true;
-          break;
-        }
-        if (start_stage2(s, bb, sh[wave])) {
-          if (lane == 0) atomicMin(cand, (unsigned long long)bb);
-          done = true;
-          break;
-        }
+        if (lane == 0) q[nq] = (unsigned long long)((uint64_t)(32 * (Wt + l) - mb) + k);
+        nq++;
+        if (nq == 2 * SCAN_BATCH) found = check(SCAN_BATCH);
       }
     }
+    if (!found && nq >= SCAN_BATCH) found = check(SCAN_BATCH);
   }
+  // the rest of the queue (all before any step not taken)
+  for (int r = 0; r < 4 && !found && nq; r++) found = check(nq < SCAN_BATCH ? nq : SCAN_BATCH);
 }
 
 // ---------------------------------------------------------------------------

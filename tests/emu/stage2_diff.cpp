@@ -1,6 +1,7 @@
-// Test-only: the block-start table check of the scan (check_dynamic_tables)
-// against the table reader of the decoder (read_dynamic_tables, strict,
-// nothing stored) at given candidate bits, in the CPU executor.  This file
+// Test-only: the block-start table checks of the scan (check_dynamic_tables,
+// whole wave; lane_tables_ok, one candidate per lane) against the table
+// reader of the decoder (read_dynamic_tables, strict, nothing stored) at
+// given candidate bits, in the CPU executor.  This file
 // is the executor's translation unit for the kernels: it includes their
 // source, then adds the comparison kernel.
 #include "gz_kernels.hip"
@@ -10,10 +11,16 @@ using namespace gzgpu;
 namespace {
 
 __global__ void k_stage2_diff(const uint8_t *buf, uint64_t n, const uint64_t *bits, int nb, int32_t *res_read,
-                              int32_t *res_check) {
+                              int32_t *res_check, int32_t *res_lane) {
   __shared__ TablesLDS sh;
+  __shared__ uint8_t tab[128 * 64];
   Src s;
   s.init(buf, n);
+  // one candidate per lane
+  for (int i0 = 0; i0 < nb; i0 += 64) {
+    const int i = i0 + (int)threadIdx.x;
+    if (i < nb) res_lane[i] = lane_tables_ok(s, bits[i], tab, (int)threadIdx.x) ? 1 : 0;
+  }
   for (int i = 0; i < nb; i++) {
     WaveBits a;
     a.s = s;
@@ -34,7 +41,7 @@ __global__ void k_stage2_diff(const uint8_t *buf, uint64_t n, const uint64_t *bi
 }  // namespace
 
 extern "C" int emu_stage2_diff(const uint8_t *buf, uint64_t n, const uint64_t *bits, int nb, int32_t *res_read,
-                               int32_t *res_check) {
-  hipLaunchKernelGGL(k_stage2_diff, dim3(1), dim3(64), 0, 0, buf, n, bits, nb, res_read, res_check);
+                               int32_t *res_check, int32_t *res_lane) {
+  hipLaunchKernelGGL(k_stage2_diff, dim3(1), dim3(64), 0, 0, buf, n, bits, nb, res_read, res_check, res_lane);
   return 0;
 }

@@ -329,9 +329,9 @@ def _stage1_survivors(comp: bytes, limit_bits: int):
 
 @pytest.mark.parametrize("kind", ["fastq6", "words1", "dna9", "binary6"])
 def test_emu_scan_table_check_equals_decoder(orc, kind):
-    """The scan's speculative table check accepts exactly the candidates the
-    decoder's table reader accepts, and both agree with the oracle's static
-    block-start check (Appendix A)."""
+    """The scan's table checks (whole wave, and one candidate per lane) accept
+    exactly the candidates the decoder's table reader accepts, and all agree
+    with the oracle's static block-start check (Appendix A)."""
     import ctypes as C
 
     raw = {"fastq6": lambda: synth.fastq_like(3 << 20, 331), "words1": lambda: synth.word_stream(3 << 20, 332),
@@ -347,14 +347,16 @@ def test_emu_scan_table_check_equals_decoder(orc, kind):
                       if t == 2 and not f and x < 8 * (1 << 20))
     assert true_starts <= set(int(x) for x in cand) and cand.size > 50
     L = E.lib()
-    L.emu_stage2_diff.argtypes = [C.c_void_p, C.c_uint64, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]
+    L.emu_stage2_diff.argtypes = [C.c_void_p, C.c_uint64, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]
     store = E.padded(comp)
     r_read = np.zeros(cand.size, np.int32)
     r_check = np.zeros(cand.size, np.int32)
+    r_lane = np.zeros(cand.size, np.int32)
     L.emu_set_sync_limit(0)
     L.emu_stage2_diff(store.ctypes.data, len(comp), cand.ctypes.data, cand.size, r_read.ctypes.data,
-                      r_check.ctypes.data)
+                      r_check.ctypes.data, r_lane.ctypes.data)
     assert np.array_equal(r_read, r_check), np.nonzero(r_read != r_check)[0][:10]
+    assert np.array_equal(r_read, r_lane), np.nonzero(r_read != r_lane)[0][:10]
     ref = np.array([orc.block_static(comp, int(x))[0] for x in cand], np.int32)
     assert np.array_equal(r_check, ref)
     assert all(r_check[np.searchsorted(cand, t)] for t in true_starts)
