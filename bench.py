@@ -300,8 +300,7 @@ def main():
     d_comp = torch.frombuffer(bytearray(comp), dtype=torch.uint8).to(dev)
     out = torch.empty(len(raw), dtype=torch.uint8, device=dev)
     window = args.window or gz.DEFAULT_WINDOW
-    # chunk_bytes 0: the library's default (about 48 KiB, the count rounded to
-    # whole rounds of the persistent decoder)
+    # chunk_bytes 0: the library's default (40 KiB)
     plan = gz.Plan(d_comp, 0, chunk_bytes=args.chunk_bytes, waves_per_chunk=args.waves_per_chunk,
                    window_syms=window, timing=1)
     n_chunks = plan.n_chunks

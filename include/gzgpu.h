@@ -51,7 +51,7 @@ extern "C" {
  * into n roughly equal parts; Section VI-A and Appendix A give the
  * block-start checks whose constants appear here.) */
 typedef struct gz_opts {
-  uint64_t chunk_bytes;   /* nominal compressed bytes per chunk when n_chunks == 0 (default 48 KiB) */
+  uint64_t chunk_bytes;   /* nominal compressed bytes per chunk when n_chunks == 0 (default 40 KiB) */
   uint32_t sym_factor;    /* symbol capacity per chunk = sym_factor * compressed bytes + slack (default 8) */
   uint32_t window_syms;   /* LDS history ring per decoding wave, in symbols: 1024, 2048, 4096, 8192, 16384
                              or 32768 (default 1024); match sources further back are read from HBM.

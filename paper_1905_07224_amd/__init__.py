@@ -117,7 +117,7 @@ EXPORTS = ["gz_plan", "gz_plan_batch", "gz_plan_info", "gz_decompress", "gz_deco
            "gz_plan_probes", "gz_find_blocks", "gz_probe_starts", "gz_stream_open_at", "gz_count_byte"]
 GZ_N_PASSES = N_PASSES = 13
 # defaults of gz_opts (include/gzgpu.h)
-DEFAULT_CHUNK_BYTES = 48 << 10
+DEFAULT_CHUNK_BYTES = 40 << 10
 DEFAULT_WINDOW = 1024
 
 

@@ -850,7 +850,7 @@ const char *gz_strerror(int code) {
 namespace {
 std::mutex g_tune_mu;
 std::map<std::tuple<int, int, int>, gz_opts> g_tune;
-const uint64_t k_tune_chunks[] = {32ull << 10, 48ull << 10, 64ull << 10, 128ull << 10, 256ull << 10, 1ull << 20};
+const uint64_t k_tune_chunks[] = {32ull << 10, 40ull << 10, 64ull << 10, 128ull << 10, 256ull << 10, 1ull << 20};
 const uint32_t k_tune_rings[] = {1024, 2048, 4096};
 }  // namespace
 
