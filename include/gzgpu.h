@@ -205,6 +205,13 @@ int gz_device_info(int dev, int *n_cu, int *lds_bytes);
  * block.  (bit offset, window, CRC-32, length) is a checkpoint: a stream
  * resumed from it produces the same bytes as one that got there itself.
  *
+ * Several members (concatenated gzip files, or BGZF-style blocked files,
+ * which the paper leaves unhandled: Section VIII): a member's trailer is the
+ * 8 bytes after its final block, and when more bytes follow they must be
+ * the next member, which the stream then decodes from its header with a new
+ * window, length and CRC-32 (RFC 1952 section 2.2).  Segment outputs, in
+ * order, are then the gunzip of the whole input.
+ *
  * Memory: the caller provides, per segment, an output buffer and a workspace
  * (gz_stream_get_info gives sizes that fit every segment at the options'
  * symbol factor); the stream allocates one 32 KiB device buffer for the
@@ -226,9 +233,9 @@ typedef struct gz_stream_info {
 
 typedef struct gz_segment_result {
   int32_t status;          /* GZ_OK or GZ_E_*; after an error the stream stays where it was */
-  uint32_t done;           /* 1: the final block was decoded; CRC-32 and ISIZE are checked */
+  uint32_t done;           /* 1: the input is finished (the last member's final block was decoded) */
   uint64_t out_len;        /* bytes this segment wrote at d_out */
-  uint64_t out_total;      /* bytes of the member decoded so far, this segment included */
+  uint64_t out_total;      /* bytes decoded so far (all members), this segment included */
   uint64_t start_bit;      /* the segment decoded [start_bit, end_bit) of the .gz file */
   uint64_t end_bit;
   uint64_t out_needed;     /* GZ_E_CAPACITY: output bytes this segment needs */
@@ -237,13 +244,18 @@ typedef struct gz_segment_result {
   uint32_t n_chunks;
   uint32_t n_repairs;
   uint32_t n_retries;
+  uint32_t member;         /* index of the member this segment decoded (0 for the first) */
+  uint32_t member_done;    /* 1: the segment ended that member (its CRC-32 and ISIZE were checked) */
 } gz_segment_result;
 
 typedef struct gz_checkpoint {
   uint64_t bit;            /* where the next segment starts, in bits from the start of the .gz file */
-  uint64_t out_total;      /* bytes decoded before it */
-  uint32_t crc32;          /* CRC-32 of those bytes */
-  uint32_t valid;          /* real history bytes at the end of window: min(out_total, 32768) */
+  uint64_t out_total;      /* bytes decoded before it (all members) */
+  uint64_t member_out;     /* of those, the bytes of the current member */
+  uint32_t member;         /* index of the current member */
+  uint32_t pad;
+  uint32_t crc32;          /* CRC-32 of the current member's bytes */
+  uint32_t valid;          /* real history bytes at the end of window: min(member_out, 32768) */
   uint32_t done;           /* the member is finished */
   uint32_t flags;          /* 1: a stream opened inside the member (gz_stream_open_at); valid is 32768 */
   uint8_t window[32768];   /* the 32768 bytes before `bit` (the first 32768 - valid are zero) */
@@ -264,13 +276,15 @@ int gz_stream_next(gz_stream_t stream, void *d_out, size_t out_cap, void *d_ws, 
 /* Wait for the segment (with the same deadline as gz_result_get) and
  * advance the stream if it succeeded.  After a capacity error the stream
  * raises its symbol factor as needed; gz_stream_get_info then gives the
- * larger sizes. */
+ * larger sizes.  When a member ends before the input does, the next
+ * member's header is read (a small synchronous copy): bytes that are not a
+ * gzip member give GZ_E_HEADER (the segment's bytes are still valid). */
 int gz_stream_wait(gz_stream_t stream, gz_segment_result *res);
 /* Copy the position after the last finished segment (synchronous). */
 int gz_stream_checkpoint(gz_stream_t stream, gz_checkpoint *cp);
 /* Continue from a checkpoint of a stream over the same input.  Errors:
- * GZ_E_ARG (a bit outside the payload, valid > 32768, valid differing from
- * min(out_total, 32768)), GZ_E_HIP. */
+ * GZ_E_ARG (a bit outside the input, valid > 32768, valid differing from
+ * min(member_out, 32768)), GZ_E_HIP. */
 int gz_stream_resume(gz_stream_t stream, const gz_checkpoint *cp);
 void gz_stream_destroy(gz_stream_t stream);
 

@@ -347,8 +347,8 @@ static int plan_common(gz_plan_t p) {
   o = align_up(o + ((uint64_t)N + 1) * 4, 256);
   o = align_up(o + (uint64_t)N * sizeof(AccEntry), 256);
   const uint64_t nseg = (N + 63) / 64;
-  L.maps_off = o;
-  o = align_up(o + nseg * WINDOW * 2, 256);
+  L.maps_off = o;  // two map arrays: the prefix composition alternates between them
+  o = align_up(o + 2 * nseg * WINDOW * 2, 256);
   L.segwin_off = o;
   o = align_up(o + nseg * WINDOW, 256);
   L.win_off = o;
@@ -968,9 +968,10 @@ struct gz_stream_s {
   int64_t h = 0;
   uint32_t crc = 0, isize = 0;
   uint8_t *d_win = nullptr;  // carried window, 32 KiB of device memory
-  // position after the last finished segment
-  uint64_t bit = 0, out_total = 0;
-  uint32_t crc_run = 0, valid = 0;
+  // position after the last finished segment: bytes of all members, and of
+  // the current member (its CRC-32, its real history in the window)
+  uint64_t bit = 0, out_total = 0, member_out = 0;
+  uint32_t crc_run = 0, valid = 0, member = 0;
   bool done = false;
   gz_plan_t cur = nullptr;   // plan of the segment in flight, re-planned in place for the next
   bool pending = false;
@@ -999,10 +1000,10 @@ static int segment_plan(gz_stream_t s, uint64_t start_bit, uint32_t win_valid, v
   p->seg.on = true;
   p->seg.start_bit = start_bit;
   p->seg.stop_bit = start_bit + 8 * s->seg_bytes;
-  p->seg.out_before = s->out_total;
+  p->seg.out_before = s->member_out;
   p->seg.crc_in = s->crc_run;
   p->seg.win_valid = win_valid;
-  p->seg.mode = s->inside ? FD_NOCHECK : 0u;
+  p->seg.mode = (s->inside ? FD_NOCHECK : 0u) | FD_MEMBERS;
   p->seg.h = s->h;
   p->seg.crc = s->crc;
   p->seg.isize = s->isize;
@@ -1080,7 +1081,7 @@ int gz_stream_get_info(gz_stream_t s, gz_stream_info *info) {
 
 int gz_stream_next(gz_stream_t s, void *d_out, size_t out_cap, void *d_ws, size_t ws_bytes, void *hip_stream) {
   if (!s || s->done || s->pending || !d_out || out_cap == 0) return GZ_E_ARG;
-  const uint32_t wv = s->inside ? WINDOW : (uint32_t)std::min<uint64_t>(s->out_total, WINDOW);
+  const uint32_t wv = s->inside ? WINDOW : (uint32_t)std::min<uint64_t>(s->member_out, WINDOW);
   int r = segment_plan(s, s->bit, wv, d_out, out_cap, &s->cur);
   if (r != GZ_OK) return r;
   gz_plan_t p = s->cur;
@@ -1125,12 +1126,38 @@ int gz_stream_wait(gz_stream_t s, gz_segment_result *res) {
   res->n_repairs = g.n_repairs;
   res->n_retries = g.n_retries;
   res->out_needed = g.out_needed;
+  res->member = s->member;
   if (g.status == GZ_OK) {
     s->bit = fst.end_bit;
     s->out_total += g.out_len;
+    s->member_out += g.out_len;
     s->crc_run = g.crc32;
-    s->valid = s->inside ? WINDOW : (uint32_t)std::min<uint64_t>(s->out_total, WINDOW);
-    s->done = fst.is_final != 0;
+    s->valid = s->inside ? WINDOW : (uint32_t)std::min<uint64_t>(s->member_out, WINDOW);
+    if (fst.is_final) {
+      // the member is done; more bytes after its trailer are the next member
+      res->member_done = 1;
+      const uint64_t te = ((fst.end_bit + 7) >> 3) + 8;
+      s->done = true;
+      if (te < s->job.comp_len) {
+        gz_job nj = s->job;
+        nj.d_comp = (const uint8_t *)s->job.d_comp + te;
+        nj.comp_len = s->job.comp_len - te;
+        int64_t h = 0;
+        uint32_t c = 0, z = 0;
+        const int hr = nj.comp_len >= 18 ? read_member(nj, 0, &h, &c, &z) : GZ_E_HEADER;
+        if (hr != GZ_OK) {
+          res->status = hr == GZ_E_HIP ? GZ_E_HIP : GZ_E_HEADER;
+        } else {
+          s->done = false;
+          s->member++;
+          s->bit = 8 * (te + (uint64_t)h);
+          s->member_out = 0;
+          s->crc_run = 0;
+          s->valid = 0;
+          s->inside = false;
+        }
+      }
+    }
   } else if (g.status == GZ_E_CAPACITY && fst.overflow) {
     // symbols overflowed: later plans use a factor that covers them
     const uint64_t f2 = needed_factor(s->cur, 0);
@@ -1141,7 +1168,7 @@ int gz_stream_wait(gz_stream_t s, gz_segment_result *res) {
   }
   res->done = s->done ? 1u : 0u;
   res->out_total = s->out_total;
-  res->crc32 = s->crc_run;
+  res->crc32 = g.status == GZ_OK ? g.crc32 : s->crc_run;
   return GZ_OK;
 }
 
@@ -1150,6 +1177,8 @@ int gz_stream_checkpoint(gz_stream_t s, gz_checkpoint *cp) {
   memset(cp, 0, sizeof(*cp));
   cp->bit = s->bit;
   cp->out_total = s->out_total;
+  cp->member_out = s->member_out;
+  cp->member = s->member;
   cp->crc32 = s->crc_run;
   cp->valid = s->valid;
   cp->done = s->done ? 1u : 0u;
@@ -1165,8 +1194,8 @@ int gz_stream_resume(gz_stream_t s, const gz_checkpoint *cp) {
   if (!s || !cp || s->pending) return GZ_E_ARG;
   const uint64_t lo = 8ull * (uint64_t)s->h, hi = 8ull * (s->job.comp_len - 8);
   const bool inside = (cp->flags & 1u) != 0;
-  if (cp->bit < lo || cp->bit > hi || cp->valid > WINDOW || (cp->flags & ~1u) ||
-      cp->valid != (inside ? WINDOW : (uint32_t)std::min<uint64_t>(cp->out_total, WINDOW)))
+  if (cp->bit < lo || cp->bit > hi || cp->valid > WINDOW || (cp->flags & ~1u) || cp->member_out > cp->out_total ||
+      cp->valid != (inside ? WINDOW : (uint32_t)std::min<uint64_t>(cp->member_out, WINDOW)))
     return GZ_E_ARG;
   if (cp->valid > 0) {
     hipError_t e = hipMemcpy(s->d_win, cp->window, WINDOW, hipMemcpyHostToDevice);
@@ -1174,6 +1203,8 @@ int gz_stream_resume(gz_stream_t s, const gz_checkpoint *cp) {
   }
   s->bit = cp->bit;
   s->out_total = cp->out_total;
+  s->member_out = cp->member_out;
+  s->member = cp->member;
   s->crc_run = cp->crc32;
   s->valid = cp->valid;
   s->done = cp->done != 0;

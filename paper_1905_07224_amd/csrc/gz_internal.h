@@ -84,6 +84,7 @@ struct FileDesc {
 enum : uint32_t {
   FD_PROBE = 1u,    // block-start probe: one chunk, decodes its first block (plus the confirmation)
   FD_NOCHECK = 2u,  // decoding began inside the member: the trailer's CRC-32 and ISIZE do not apply
+  FD_MEMBERS = 4u,  // more members may follow: the trailer is the 8 bytes after the final block
 };
 
 struct ChunkDesc {
@@ -139,6 +140,8 @@ struct FileState {
   uint32_t crc_out;        // CRC-32 of the output (with the bytes before the segment)
   uint32_t is_final;       // the member's final block was decoded (the trailer is checked)
   uint64_t end_bit;        // where the last accepted chunk stopped
+  uint32_t trailer_crc;    // the member's trailer: CRC-32 and ISIZE
+  uint32_t trailer_isize;
 };
 
 struct Counters {
@@ -162,7 +165,7 @@ struct Layout {
   uint64_t counters_off;   // Counters
   uint64_t tiles_off;      // uint64[N+1] translate tile prefix
   uint64_t acc_off;        // uint32[N+1] accepted chunks before chunk j, then AccEntry[N] in chunk order
-  uint64_t maps_off;       // uint16[S][32768] propagation segment maps, S = ceil(N / 64)
+  uint64_t maps_off;       // uint16[2][S][32768] propagation segment maps and their prefix compositions, S = ceil(N / 64)
   uint64_t segwin_off;     // uint8[S][32768] input window of each propagation segment
   uint64_t win_off;        // uint8[N][32768] resolved windows
   uint64_t sym_off;        // uint16 symbol pool

@@ -1229,15 +1229,30 @@ __global__ __launch_bounds__(256) void k_finalize(const FileDesc *files, const C
     int32_t st = fs[f].status;
     const uint32_t ovf = (uint32_t)(packed >> 42);
     const bool fin = (last_flags & CS_FINAL) != 0;
+    // the member's trailer: the last 8 bytes, or (when more members may
+    // follow) the 8 bytes from the byte boundary after the final block
+    const bool members = (fd.mode & FD_MEMBERS) != 0;
+    const uint64_t tr = fin ? ((last_end + 7) >> 3) : 0;
+    uint32_t tcrc = fd.crc, tisize = fd.isize;
     if (st == ST_OK) {
       // a segment stops at a block boundary past its stop, or ends the member
       if (!fin && (fd.stop_bit == NONE || last_end == NONE || last_end < fd.stop_bit)) st = ST_DATA;
-      else if (fin && ((last_end + 7) >> 3) + 8 != fd.comp_len) st = ST_UNSUPPORTED;
+      else if (fin && !members && tr + 8 != fd.comp_len) st = ST_UNSUPPORTED;
+      else if (fin && members && tr + 8 > fd.comp_len) st = ST_DATA;  // truncated trailer
       else if (ovf) st = ST_CAPACITY;
       else if (carry > fd.out_cap) st = ST_CAPACITY;
     }
+    if (fin && members && tr + 8 <= fd.comp_len) {
+      tcrc = tisize = 0;
+      for (int k = 3; k >= 0; k--) {
+        tcrc = (tcrc << 8) | fd.comp[tr + k];
+        tisize = (tisize << 8) | fd.comp[tr + 4 + k];
+      }
+    }
+    fs[f].trailer_crc = tcrc;
+    fs[f].trailer_isize = tisize;
     // a length that differs from ISIZE is reported after the CRC check
-    fs[f].size_bad = fin && (uint32_t)(fd.out_before + carry) != fd.isize ? 1u : 0u;
+    fs[f].size_bad = fin && (uint32_t)(fd.out_before + carry) != tisize ? 1u : 0u;
     fs[f].is_final = fin ? 1u : 0u;
     fs[f].end_bit = last_end;
     fs[f].status = st;
@@ -1264,11 +1279,14 @@ __global__ __launch_bounds__(256) void k_finalize(const FileDesc *files, const C
 //   k_prop_maps   each segment composes its steps into one map from its input
 //                 window to the next segment's (16-bit entries: a byte, or
 //                 0x8000 | position in the input window), all segments at once
-//   k_prop_chain  one workgroup applies the maps in order: every segment's
-//                 input window
+//   k_prop_scan   prefix compositions of the maps, log2(S) rounds over all
+//                 segments at once (composition is associative: (A o B)[k]
+//                 is A[k] if a byte, else B[A[k] & 0x7FFF])
+//   k_prop_segwin every segment's input window: its prefix map applied to
+//                 the first window
 //   k_prop_apply  each segment runs its steps from its input window and
 //                 stores every chunk's window
-// so the sequential part is one step per segment, not per chunk.
+// so nothing is sequential over segments: the chain of S steps is a scan.
 // Each step: every thread gathers 32 of the 32768 entries into registers,
 // then (after a barrier) writes them; the next chunk's tail is loaded while
 // the current one is resolved.
@@ -1362,32 +1380,43 @@ __global__ __launch_bounds__(PROP_THREADS) void k_prop_maps(const uint32_t *acc_
   for (int k = threadIdx.x; k < (int)WINDOW; k += PROP_THREADS) mo[k] = m[k];
 }
 
-__global__ __launch_bounds__(PROP_THREADS) void k_prop_chain(const uint32_t *acc_pos, uint32_t n, const AccEntry *acc,
-                                                             const uint16_t *__restrict__ maps, const uint8_t *seed,
-                                                             uint8_t *__restrict__ segwin) {
-  __shared__ uint8_t w[WINDOW];
+// One round of the prefix composition: out[g] = in[g] o in[g - dist] for
+// g >= dist, else in[g] (maps exist for segments 0 .. S - 2).  Grid:
+// PROP_PARTS blocks per segment, each over a part of the 32768 entries.
+constexpr uint32_t PROP_PARTS = 32;
+__global__ __launch_bounds__(256) void k_prop_scan(const uint32_t *acc_pos, uint32_t n,
+                                                   const uint16_t *__restrict__ in, uint16_t *__restrict__ out,
+                                                   uint32_t dist) {
   const uint32_t A = acc_pos[n];
-  const int tid = (int)threadIdx.x;
-  // the first accepted chunk's window: carried in, or none
-  const uint8_t *w0 = A > 0 && (acc[0].pad & 2u) ? seed + (uint64_t)acc[0].chunk * WINDOW : nullptr;
-  for (int k = tid; k < (int)WINDOW; k += PROP_THREADS) w[k] = w0 ? w0[k] : (uint8_t)0;
-  __syncthreads();
   const uint32_t S = (A + PSEG - 1) / PSEG;
-  for (uint32_t g = 0; g < S; g++) {
-    uint8_t *wo = segwin + (uint64_t)g * WINDOW;
-    for (int k = tid; k < (int)WINDOW; k += PROP_THREADS) wo[k] = w[k];
-    if (g + 1 == S) break;
-    const uint16_t *mg = maps + (uint64_t)g * WINDOW;
-    uint32_t v[PROP_PER];
-#pragma unroll
-    for (int i = 0; i < PROP_PER; i++) {
-      const uint32_t x = mg[i * PROP_THREADS + tid];
-      v[i] = x < 256u ? x : (uint32_t)w[x & 0x7FFFu];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < PROP_PER; i++) w[i * PROP_THREADS + tid] = (uint8_t)v[i];
-    __syncthreads();
+  const uint32_t g = blockIdx.x / PROP_PARTS, part = blockIdx.x % PROP_PARTS;
+  if (g + 1 >= S) return;
+  const uint16_t *mg = in + (uint64_t)g * WINDOW;
+  const uint16_t *mp = g >= dist ? in + (uint64_t)(g - dist) * WINDOW : nullptr;
+  uint16_t *og = out + (uint64_t)g * WINDOW;
+  for (uint32_t k = part * blockDim.x + threadIdx.x; k < WINDOW; k += PROP_PARTS * blockDim.x) {
+    uint32_t x = mg[k];
+    if (mp && x >= 256u) x = mp[x & 0x7FFFu];
+    og[k] = (uint16_t)x;
+  }
+}
+
+// Segment g's input window: the first window (carried in, or none) for
+// g = 0, else the prefix map of segments 0 .. g - 1 applied to it.
+__global__ __launch_bounds__(256) void k_prop_segwin(const uint32_t *acc_pos, uint32_t n, const AccEntry *acc,
+                                                     const uint16_t *__restrict__ prefix, const uint8_t *seed,
+                                                     uint8_t *__restrict__ segwin) {
+  const uint32_t A = acc_pos[n];
+  const uint32_t S = (A + PSEG - 1) / PSEG;
+  const uint32_t g = blockIdx.x / PROP_PARTS, part = blockIdx.x % PROP_PARTS;
+  if (g >= S) return;
+  const uint8_t *w0 = A > 0 && (acc[0].pad & 2u) ? seed + (uint64_t)acc[0].chunk * WINDOW : nullptr;
+  const uint16_t *pg = g > 0 ? prefix + (uint64_t)(g - 1) * WINDOW : nullptr;
+  uint8_t *wo = segwin + (uint64_t)g * WINDOW;
+  for (uint32_t k = part * blockDim.x + threadIdx.x; k < WINDOW; k += PROP_PARTS * blockDim.x) {
+    uint32_t x = pg ? (uint32_t)pg[k] : 0x8000u | k;
+    if (x >= 256u) x = w0 ? w0[x & 0x7FFFu] : 0u;
+    wo[k] = (uint8_t)x;
   }
 }
 
@@ -1465,80 +1494,88 @@ __global__ __launch_bounds__(1024) void k_tilescan(const ChunkDesc *chunks, cons
 
 // ---------------------------------------------------------------------------
 // k_translate: out[o_i + p] = D_i[p] < 256 ? D_i[p] : w_i[D_i[p] & 0x7FFF].
-// Tiles of TRANSLATE_TILE symbols; a persistent grid walks them.
+// A persistent grid pulls whole chunks: the chunk's window goes to LDS once
+// (when the chunk has placeholders), then the chunk is walked in pieces of
+// TRANSLATE_TILE symbols whose placeholders are looked up there.  `tiles`
+// (the tile prefix of the size scan) is only used for its total: a batch
+// whose files failed translates nothing.
 // ---------------------------------------------------------------------------
 
 __global__ __launch_bounds__(256) void k_translate(const FileDesc *files, const ChunkDesc *chunks, const ChunkState *cs,
                                                    FileState *fs, const uint64_t *tiles, uint32_t n,
                                                    const uint8_t *wins, const uint16_t *pool, Counters *ctr) {
   __shared__ uint32_t s_item;
+  __shared__ uint4 wlw[WINDOW / 16];                 // the chunk's window
   __shared__ uint4 tbw[(TRANSLATE_TILE + 32) / 16];  // 16-byte aligned staging
+  const uint8_t *wl = reinterpret_cast<const uint8_t *>(wlw);
   uint8_t *tb = reinterpret_cast<uint8_t *>(tbw);
-  const uint64_t total = tiles[n];
-  for (uint64_t it = 0; it <= total; it++) {
+  if (tiles[n] == 0) return;
+  for (uint32_t it = 0; it <= n; it++) {
     if (threadIdx.x == 0) s_item = atomicAdd(&ctr->translate_next, 1u);
     __syncthreads();
-    const uint64_t item = s_item;
+    const uint32_t j = s_item;
     __syncthreads();
-    if (item >= total) break;
-    // chunk: the last j with tiles[j] <= item (chunks without tiles repeat the next value)
-    uint32_t lo = 0, hi = n;
-    for (int it = 0; it < 40 && hi - lo > 1; it++) {
-      uint32_t mid = (lo + hi) >> 1;
-      if (tiles[mid] <= item) lo = mid;
-      else hi = mid;
-    }
-    const uint32_t j = lo;
+    if (j >= n) break;
     const ChunkState sj = cs[j];
-    const FileDesc fd = files[chunks[j].file];
-    const uint64_t p0 = (item - tiles[j]) * TRANSLATE_TILE;
+    if (sj.start == NONE || sj.len == 0) continue;
+    const uint32_t f = chunks[j].file;
+    if (fs[f].status != ST_OK) continue;
+    const FileDesc fd = files[f];
     const uint64_t L = sj.len;
     const uint16_t *Dj = pool + chunks[j].sym_off;
-    const uint8_t *wj = wins + (uint64_t)j * WINDOW;
     const uint32_t lim = 32768u - sj.valid;  // placeholders below this lie before the data start
     uint8_t *out = fd.out + sj.out_off;
-    // the tile's bytes are staged in LDS at the output's alignment, then
-    // stored as aligned 16-byte words (byte stores for the partial words at
-    // the two ends, which the neighbouring tiles share)
-    const uint64_t cnt = L - p0 < TRANSLATE_TILE ? L - p0 : TRANSLATE_TILE;
-    const uintptr_t ob = (uintptr_t)(out + p0);
-    const uint32_t sh = (uint32_t)(ob & 15u);
+    // (with no history before the chunk every placeholder is a data error,
+    // whatever the window holds)
+    if (sj.valid) {
+      const uint4 *wj = reinterpret_cast<const uint4 *>(wins + (uint64_t)j * WINDOW);
+      for (uint32_t k = threadIdx.x; k < WINDOW / 16; k += blockDim.x) wlw[k] = wj[k];
+      __syncthreads();
+    }
     int err = 0;
-    for (uint64_t g = p0 + 8ull * threadIdx.x; g < p0 + cnt; g += 8ull * blockDim.x) {
-      const uint4 v = *reinterpret_cast<const uint4 *>(Dj + g);
-      const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+    for (uint64_t p0 = 0; p0 < L; p0 += TRANSLATE_TILE) {
+      // a piece's bytes are staged in LDS at the output's alignment, then
+      // stored as aligned 16-byte words (byte stores for the partial words
+      // at the two ends, which the neighbouring pieces share)
+      const uint64_t cnt = L - p0 < TRANSLATE_TILE ? L - p0 : TRANSLATE_TILE;
+      const uintptr_t ob = (uintptr_t)(out + p0);
+      const uint32_t sh = (uint32_t)(ob & 15u);
+      for (uint64_t g = p0 + 8ull * threadIdx.x; g < p0 + cnt; g += 8ull * blockDim.x) {
+        const uint4 v = *reinterpret_cast<const uint4 *>(Dj + g);
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
-      for (int h = 0; h < 8; h++) {
-        const uint64_t p = g + h;
-        if (p < p0 + cnt) {
-          const uint32_t t = (w[h >> 1] >> (16 * (h & 1))) & 0xFFFFu;
-          uint32_t b;
-          if (t < 256u) {
-            b = t;
-          } else {
-            const uint32_t m = t & 0x7FFFu;
-            if (t < 0x8000u || m < lim) err = 1;
-            b = wj[m];
+        for (int h = 0; h < 8; h++) {
+          const uint64_t p = g + h;
+          if (p < p0 + cnt) {
+            const uint32_t t = (w[h >> 1] >> (16 * (h & 1))) & 0xFFFFu;
+            uint32_t b;
+            if (t < 256u) {
+              b = t;
+            } else {
+              const uint32_t m = t & 0x7FFFu;
+              if (t < 0x8000u || m < lim) err = 1;
+              b = wl[m];
+            }
+            tb[sh + (p - p0)] = (uint8_t)b;
           }
-          tb[sh + (p - p0)] = (uint8_t)b;
         }
       }
+      __syncthreads();
+      const uint32_t end = sh + (uint32_t)cnt;      // LDS bytes [sh, end) hold the piece
+      const uint32_t first = (sh + 15u) & ~15u;     // first whole 16-byte word
+      const uint32_t last = end & ~15u;             // end of the whole words
+      uint8_t *base = (uint8_t *)(ob - sh);         // 16-byte aligned
+      if (first <= last) {
+        for (uint32_t k = first + 16u * threadIdx.x; k < last; k += 16u * blockDim.x)
+          *reinterpret_cast<uint4 *>(base + k) = *reinterpret_cast<const uint4 *>(&tb[k]);
+        for (uint32_t k = sh + threadIdx.x; k < first; k += blockDim.x) base[k] = tb[k];
+        for (uint32_t k = last + threadIdx.x; k < end; k += blockDim.x) base[k] = tb[k];
+      } else {
+        for (uint32_t k = sh + threadIdx.x; k < end; k += blockDim.x) base[k] = tb[k];
+      }
+      __syncthreads();
     }
-    __syncthreads();
-    const uint32_t end = sh + (uint32_t)cnt;      // LDS bytes [sh, end) hold the tile
-    const uint32_t first = (sh + 15u) & ~15u;     // first whole 16-byte word
-    const uint32_t last = end & ~15u;             // end of the whole words
-    uint8_t *base = (uint8_t *)(ob - sh);         // 16-byte aligned
-    if (first <= last) {
-      for (uint32_t k = first + 16u * threadIdx.x; k < last; k += 16u * blockDim.x)
-        *reinterpret_cast<uint4 *>(base + k) = *reinterpret_cast<const uint4 *>(&tb[k]);
-      for (uint32_t k = sh + threadIdx.x; k < first; k += blockDim.x) base[k] = tb[k];
-      for (uint32_t k = last + threadIdx.x; k < end; k += blockDim.x) base[k] = tb[k];
-    } else {
-      for (uint32_t k = sh + threadIdx.x; k < end; k += blockDim.x) base[k] = tb[k];
-    }
-    __syncthreads();
-    if (err) atomicCAS(&fs[chunks[j].file].status, ST_OK, ST_DATA);
+    if (err) atomicCAS(&fs[f].status, ST_OK, ST_DATA);
   }
 }
 
@@ -1674,7 +1711,7 @@ __global__ __launch_bounds__(256) void k_crc_final(const FileDesc *files, uint32
     const uint32_t crc = fs[f].crc_acc ^ gf_mul(~files[f].crc_in, gf_xpow8(L, xpow)) ^ 0xFFFFFFFFu;
     fs[f].crc_out = crc;
     if (!fs[f].is_final || (files[f].mode & FD_NOCHECK)) continue;
-    if (crc != files[f].crc) fs[f].status = ST_CRC;
+    if (crc != fs[f].trailer_crc) fs[f].status = ST_CRC;
     else if (fs[f].size_bad) fs[f].status = ST_SIZE;
   }
 }
@@ -1853,7 +1890,16 @@ hipError_t gzk_propagate(uint32_t n, const uint32_t *acc_pos, const AccEntry *ac
   hipLaunchKernelGGL(k_prop_maps, dim3(smax), dim3(PROP_THREADS), 0, st, acc_pos, n, acc, pool, wins, maps);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_prop_chain, dim3(1), dim3(PROP_THREADS), 0, st, acc_pos, n, acc, maps, wins, segwin);
+  // prefix compositions, alternating between the two map arrays
+  uint16_t *cur = maps, *alt = maps + (uint64_t)smax * WINDOW;
+  for (uint32_t dist = 1; dist + 1 < smax; dist *= 2) {
+    hipLaunchKernelGGL(k_prop_scan, dim3(PROP_PARTS * smax), dim3(256), 0, st, acc_pos, n, cur, alt, dist);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    uint16_t *t = cur;
+    cur = alt;
+    alt = t;
+  }
+  hipLaunchKernelGGL(k_prop_segwin, dim3(PROP_PARTS * smax), dim3(256), 0, st, acc_pos, n, acc, cur, wins, segwin);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(k_prop_apply, dim3(smax), dim3(PROP_THREADS), 0, st, acc_pos, n, acc, pool, segwin, wins);
   return hipGetLastError();

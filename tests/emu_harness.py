@@ -139,12 +139,14 @@ class SegmentResult(C.Structure):
     _fields_ = [("status", C.c_int32), ("done", C.c_uint32), ("out_len", C.c_uint64), ("out_total", C.c_uint64),
                 ("start_bit", C.c_uint64), ("end_bit", C.c_uint64), ("out_needed", C.c_uint64),
                 ("ws_needed", C.c_uint64), ("crc32", C.c_uint32), ("n_chunks", C.c_uint32),
-                ("n_repairs", C.c_uint32), ("n_retries", C.c_uint32)]
+                ("n_repairs", C.c_uint32), ("n_retries", C.c_uint32), ("member", C.c_uint32),
+                ("member_done", C.c_uint32)]
 
 
 class Checkpoint(C.Structure):
-    _fields_ = [("bit", C.c_uint64), ("out_total", C.c_uint64), ("crc32", C.c_uint32), ("valid", C.c_uint32),
-                ("done", C.c_uint32), ("pad", C.c_uint32), ("window", C.c_uint8 * 32768)]
+    _fields_ = [("bit", C.c_uint64), ("out_total", C.c_uint64), ("member_out", C.c_uint64),
+                ("member", C.c_uint32), ("pad", C.c_uint32), ("crc32", C.c_uint32), ("valid", C.c_uint32),
+                ("done", C.c_uint32), ("flags", C.c_uint32), ("window", C.c_uint8 * 32768)]
 
 
 def stream_lib():

@@ -65,8 +65,8 @@ def test_struct_sizes_match_header(libpath):
     assert ctypes.sizeof(gz.Info) == 8 * 3 + 4 * 4
     assert ctypes.sizeof(gz.Result) == 4 + 4 + 8 * 3 + 4 * 4 + 8 * 3 + 4 + 4
     assert ctypes.sizeof(gz.StreamInfo) == 8 * 5 + 4 * 2
-    assert ctypes.sizeof(gz.SegmentResult) == 4 + 4 + 8 * 6 + 4 * 4
-    assert ctypes.sizeof(gz.Checkpoint) == 8 * 2 + 4 * 4 + 32768
+    assert ctypes.sizeof(gz.SegmentResult) == 4 + 4 + 8 * 6 + 4 * 6
+    assert ctypes.sizeof(gz.Checkpoint) == 8 * 3 + 4 * 6 + 32768
 
 
 def test_struct_layout_matches_c_compiler(tmp_path):

@@ -360,3 +360,62 @@ def test_emu_scan_table_check_equals_decoder(orc, kind):
     ref = np.array([orc.block_static(comp, int(x))[0] for x in cand], np.int32)
     assert np.array_equal(r_check, ref)
     assert all(r_check[np.searchsorted(cand, t)] for t in true_starts)
+
+
+def test_emu_window_propagation_many_segments(orc):
+    """More than 2 * 64 accepted chunks: the windows of the propagation
+    segments come from prefix compositions of their maps (several rounds)."""
+    raw = synth.fastq_like(1200 << 10, 341)
+    comp = synth.gzip_member(raw, 6, segment_bytes=2048)
+    g = orc.gunzip(comp)
+    assert (g.block_type == 2).sum() > 500
+    r, tab = _check(orc, comp, 560, raw)
+    assert (tab["start"] != NONE).sum() > 8 * 64
+
+
+def _members():
+    from bitwriter import bgzf_member
+
+    parts = [synth.fastq_like(240 << 10, 351), synth.word_stream(60 << 10, 352), b"", synth.fastq_like(40 << 10, 353),
+             synth.word_stream(30 << 10, 354)]
+    comps = [synth.gzip_member(parts[0], 6), synth.gzip_member(parts[1], 1), synth.gzip_member(parts[2], 6),
+             bgzf_member(parts[3], 9), bgzf_member(parts[4], 6)]
+    return parts, comps
+
+
+def test_emu_stream_multiple_members(orc):
+    """Concatenated members (one empty, two BGZF-style): the stream's output
+    is the oracle's gunzip of the whole input; each member ends with its own
+    CRC-32; bytes after the last member that are not a member fail with the
+    oracle's status (header)."""
+    parts, comps = _members()
+    comp = b"".join(comps)
+    g = orc.gunzip(comp)
+    assert g.status == orc.OK and g.n_members == len(parts)
+    segs = E.stream_run(comp, 15000, chunk_bytes=4096)
+    assert all(d["status"] == 0 for d, _, _ in segs) and segs[-1][0]["done"] == 1
+    got = b"".join(x for _, x, _ in segs)
+    assert got == g.out.tobytes() == b"".join(parts)
+    ends = [d for d, _, _ in segs if d["member_done"]]
+    assert [d["member"] for d in ends] == list(range(len(parts)))
+    assert [d["crc32"] for d in ends] == [zlib.crc32(p) for p in parts]
+    # a checkpoint inside a member resumes to the same bytes
+    k = next(i for i, (d, _, _) in enumerate(segs) if not d["member_done"])
+    rest = E.stream_run(comp, 15000, resume=segs[k][2], chunk_bytes=4096)
+    assert b"".join(x for _, x, _ in rest) == b"".join(x for _, x, _ in segs[k + 1:])
+    # trailing bytes that are not a gzip member
+    bad = comp + b"\x00garbage"
+    gb = orc.gunzip(bad)
+    assert gb.status == orc.E_HEADER
+    sb = E.stream_run(bad, 15000, chunk_bytes=4096)
+    head = b"".join(x for _, x, _ in sb[:-1])
+    assert sb[-1][0]["status"] == -2 and sb[-1][0]["member_done"] == 1
+    assert head + g.out.tobytes()[len(head):] == g.out.tobytes()
+    assert len(head) + sb[-1][0]["out_len"] == g.out.size
+    # a wrong CRC in the second member
+    crc_at = len(comps[0]) + len(comps[1]) - 8
+    bc = bytearray(comp)
+    bc[crc_at] ^= 1
+    assert orc.gunzip(bytes(bc)).reason == "CRC"
+    sc = E.stream_run(bytes(bc), 15000, chunk_bytes=4096)
+    assert sc[-1][0]["status"] == -6 and sc[-1][0]["member"] == 1

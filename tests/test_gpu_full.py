@@ -178,3 +178,38 @@ def test_stream_small_members(orc):
                 n_ok += 1
         assert ei.value.code == code and n_ok >= 2
         s.close()
+
+
+def test_stream_multiple_members(orc):
+    """Concatenated members (an empty one, BGZF-style ones) streamed: the
+    output is the oracle's gunzip of the whole input, each member ends with
+    its own CRC-32, and a non-member tail fails with the oracle's status."""
+    import paper_1905_07224_amd as gz
+    from bitwriter import bgzf_member
+
+    parts = [synth.fastq_like(5 << 20, 821), synth.word_stream(3 << 20, 822), b"", synth.fastq_like(60 << 10, 823),
+             synth.word_stream(50 << 10, 824), synth.fastq_like(2 << 20, 825)]
+    comps = [synth.gzip_member(parts[0], 6), synth.gzip_member(parts[1], 1), synth.gzip_member(b"", 6),
+             bgzf_member(parts[3], 6), bgzf_member(parts[4], 9), synth.gzip_member(parts[5], 9)]
+    comp = b"".join(comps)
+    g = orc.gunzip(comp)
+    assert g.status == orc.OK and g.n_members == len(parts)
+    for seg in (1 << 20, 1 << 30):
+        _say("members streamed, segment", seg)
+        s = gz.Stream(torch.frombuffer(bytearray(comp), dtype=torch.uint8).to("cuda:0"), seg)
+        got, ends = [], []
+        for part in s:
+            got.append(part.cpu().numpy().tobytes())
+            if s.last["member_done"]:
+                ends.append((s.last["member"], s.last["crc32"]))
+        s.close()
+        assert b"".join(got) == g.out.tobytes()
+        assert ends == [(i, zlib.crc32(p)) for i, p in enumerate(parts)]
+    bad = bytearray(comp + b"\x1f\x8b\x08")
+    assert orc.gunzip(bytes(bad)).status == orc.E_HEADER
+    s = gz.Stream(torch.frombuffer(bad, dtype=torch.uint8).to("cuda:0"), 1 << 20)
+    with pytest.raises(gz.GzError) as ei:
+        for _ in s:
+            pass
+    assert ei.value.code == gz.GZ_E_HEADER
+    s.close()
