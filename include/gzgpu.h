@@ -288,6 +288,21 @@ int gz_stream_checkpoint(gz_stream_t stream, gz_checkpoint *cp);
 int gz_stream_resume(gz_stream_t stream, const gz_checkpoint *cp);
 void gz_stream_destroy(gz_stream_t stream);
 
+/* BGZF-style input (RFC 1952 members whose extra field holds the 'BC'
+ * subfield with the member's size; the paper's experiments excluded such
+ * blocked files, Section VII): every member is a file of one batch plan,
+ * their outputs back to back at d_out in member order, decoded in one
+ * launch sequence by gz_decompress_batch (each member has its own empty
+ * context, so nothing crosses members).  The member sizes, CRC-32s and
+ * ISIZEs are read on the host from h_comp, a host copy of the input (NULL:
+ * the library copies d_comp to the host).  *out_len: the output length (the
+ * sum of the ISIZEs); *n_members: the number of files of the plan, whose
+ * statuses gz_result_get gives.  d_out may be NULL to learn *out_len.
+ * Errors: GZ_E_ARG, GZ_E_HEADER (a member without the subfield, or bytes
+ * after the last member), GZ_E_CAPACITY (out_cap below *out_len), GZ_E_HIP. */
+int gz_plan_bgzf(gz_plan_t *plan, const void *d_comp, const void *h_comp, size_t comp_len, void *d_out,
+                 size_t out_cap, const gz_opts *opts, uint64_t *out_len, uint32_t *n_members);
+
 /* ------------------------------------------------------------------------
  * Random access (Section IV).  Decoding from inside a member needs a block
  * start and the 32 KiB context before it (Section IV-A).  The start is

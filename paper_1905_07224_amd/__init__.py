@@ -116,7 +116,8 @@ EXPORTS = ["gz_plan", "gz_plan_batch", "gz_plan_info", "gz_decompress", "gz_deco
            "gz_pass_name", "gz_decompress_graph", "gz_autotune", "gz_server_create", "gz_server_submit",
            "gz_server_poll", "gz_server_stats", "gz_server_destroy", "gz_stream_open", "gz_stream_get_info",
            "gz_stream_next", "gz_stream_wait", "gz_stream_checkpoint", "gz_stream_resume", "gz_stream_destroy",
-           "gz_plan_probes", "gz_find_blocks", "gz_probe_starts", "gz_stream_open_at", "gz_count_byte"]
+           "gz_plan_probes", "gz_find_blocks", "gz_probe_starts", "gz_stream_open_at", "gz_count_byte",
+           "gz_plan_bgzf"]
 GZ_N_PASSES = N_PASSES = 13
 # defaults of gz_opts (include/gzgpu.h)
 DEFAULT_CHUNK_BYTES = 40 << 10
@@ -170,6 +171,8 @@ def lib():
         L.gz_probe_starts.argtypes = [vp, vp, vp]
         L.gz_stream_open_at.argtypes = [C.POINTER(vp), vp, C.c_size_t, u64, C.c_uint32, u64, C.POINTER(Opts)]
         L.gz_count_byte.argtypes = [vp, u64, C.c_uint32, u64, u64, vp, u64, vp]
+        L.gz_plan_bgzf.argtypes = [C.POINTER(vp), vp, vp, C.c_size_t, vp, C.c_size_t, C.POINTER(Opts),
+                                   C.POINTER(u64), C.POINTER(C.c_uint32)]
         for name in EXPORTS:
             if name not in ("gz_plan_destroy", "gz_strerror", "gz_pass_name", "gz_server_destroy",
                             "gz_stream_destroy"):
@@ -711,3 +714,37 @@ def undetermined_profile(comp, bit: int, window: int, marker: int = 0, segment_b
     torch.cuda.synchronize()
     n_win = (total + window - 1) // window
     return starts[0], total, counts[:n_win].cpu().numpy()
+
+
+def decompress_bgzf(comp, stream=None, **opts) -> torch.Tensor:
+    """A BGZF-style input decoded with one batch plan (gz_plan_bgzf): every
+    member at once, outputs back to back.  Raises GzError on any member's
+    failure."""
+    host = comp if isinstance(comp, (bytes, bytearray)) else None
+    dcomp = _as_device_bytes(comp)
+    hbuf = None
+    if host is not None:
+        hbuf = (C.c_uint8 * len(host)).from_buffer_copy(bytes(host))
+    n_out, n_mem = C.c_uint64(), C.c_uint32()
+    h = C.c_void_p()
+    with torch.cuda.device(dcomp.device):
+        _check(lib().gz_plan_bgzf(C.byref(h), C.c_void_p(dcomp.data_ptr()), hbuf, dcomp.numel(), None, 0,
+                                  C.byref(_opts(**opts)), C.byref(n_out), C.byref(n_mem)))
+        lib().gz_plan_destroy(h)
+        out = torch.empty(max(1, n_out.value), dtype=torch.uint8, device=dcomp.device)
+        h = C.c_void_p()
+        _check(lib().gz_plan_bgzf(C.byref(h), C.c_void_p(dcomp.data_ptr()), hbuf, dcomp.numel(),
+                                  C.c_void_p(out.data_ptr()), out.numel(), C.byref(_opts(**opts)), C.byref(n_out),
+                                  C.byref(n_mem)))
+        try:
+            info = Info()
+            _check(lib().gz_plan_info(h, C.byref(info)))
+            ws = torch.empty(info.ws_bytes, dtype=torch.uint8, device=dcomp.device)
+            _check(lib().gz_decompress_batch(h, C.c_void_p(ws.data_ptr()), ws.numel(), _stream_handle(stream)))
+            for f in range(n_mem.value):
+                r = Result()
+                _check(lib().gz_result_get(h, f, C.byref(r)))
+                _check(r.status)
+        finally:
+            lib().gz_plan_destroy(h)
+    return out[: n_out.value]

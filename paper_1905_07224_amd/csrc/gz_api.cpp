@@ -174,6 +174,13 @@ struct gz_plan_s {
     int64_t h = 0;        // payload start byte
     uint32_t crc = 0, isize = 0;
   } seg;
+  // members whose header and trailer were read by the caller (gz_plan_bgzf):
+  // payload start (from the member's start), trailer CRC-32 and ISIZE
+  struct Member {
+    int64_t h;
+    uint32_t crc, isize;
+  };
+  std::vector<Member> pre;
   // block-start probes (gz_plan_probes): file f searches [lo, hi) of the one input
   bool probe = false;
   std::vector<uint64_t> probe_lo, probe_hi;
@@ -229,7 +236,11 @@ static int plan_common(gz_plan_t p) {
     const gz_job &j = p->jobs[f];
     int64_t h = 0;
     uint32_t crc = 0, isize = 0;
-    if (p->seg.on || (p->probe && f > 0)) {
+    if (!p->pre.empty()) {
+      h = p->pre[f].h;
+      crc = p->pre[f].crc;
+      isize = p->pre[f].isize;
+    } else if (p->seg.on || (p->probe && f > 0)) {
       h = p->seg.h;
       crc = p->seg.crc;
       isize = p->seg.isize;
@@ -470,6 +481,82 @@ int gz_plan_probes(gz_plan_t *plan, const void *d_comp, size_t comp_len, const u
     return r;
   }
   (void)hipEventCreateWithFlags(&p->upload_done, hipEventDisableTiming);
+  *plan = p;
+  return GZ_OK;
+}
+
+int gz_plan_bgzf(gz_plan_t *plan, const void *d_comp, const void *h_comp, size_t comp_len, void *d_out,
+                 size_t out_cap, const gz_opts *opts, uint64_t *out_len, uint32_t *n_members) {
+  if (!plan || !d_comp || comp_len == 0) return GZ_E_ARG;
+  *plan = nullptr;
+  std::vector<uint8_t> copy;
+  const uint8_t *hb = (const uint8_t *)h_comp;
+  if (!hb) {
+    copy.resize(comp_len);
+    hipError_t e = hipMemcpy(copy.data(), d_comp, comp_len, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "reading the input");
+    hb = copy.data();
+  }
+  std::vector<gz_job> jobs;
+  std::vector<gz_plan_s::Member> pre;
+  uint64_t at = 0, total = 0;
+  while (at < comp_len) {
+    const uint8_t *m = hb + at;
+    const size_t left = comp_len - at;
+    // the member's size from its 'BC' extra subfield (RFC 1952 section 2.3.1.1)
+    uint64_t size = 0;
+    if (left >= 18 && m[0] == 0x1f && m[1] == 0x8b && m[2] == 8 && (m[3] & 4u)) {
+      const size_t xlen = (size_t)m[10] | ((size_t)m[11] << 8);
+      for (size_t q = 12; q + 4 <= 12 + xlen && q + 4 <= left;) {
+        const size_t slen = (size_t)m[q + 2] | ((size_t)m[q + 3] << 8);
+        if (m[q] == 'B' && m[q + 1] == 'C' && slen == 2 && q + 6 <= left) size = ((uint64_t)m[q + 4] | ((uint64_t)m[q + 5] << 8)) + 1;
+        q += 4 + slen;
+      }
+    }
+    const int64_t h = size ? parse_gzip_header(m, (size_t)std::min<uint64_t>(size, left)) : -1;
+    if (!size || size > left || h < 0 || (uint64_t)h + 8 > size) {
+      snprintf(g_err, sizeof(g_err), "member at byte %llu: not a BGZF member", (unsigned long long)at);
+      return GZ_E_HEADER;
+    }
+    const uint8_t *tr = m + size - 8;
+    gz_plan_s::Member mb;
+    mb.h = h;
+    mb.crc = (uint32_t)tr[0] | ((uint32_t)tr[1] << 8) | ((uint32_t)tr[2] << 16) | ((uint32_t)tr[3] << 24);
+    mb.isize = (uint32_t)tr[4] | ((uint32_t)tr[5] << 8) | ((uint32_t)tr[6] << 16) | ((uint32_t)tr[7] << 24);
+    gz_job j{};
+    j.d_comp = (const uint8_t *)d_comp + at;
+    j.comp_len = size;
+    j.d_out = d_out ? (uint8_t *)d_out + total : nullptr;
+    j.out_cap = mb.isize;  // a BGZF member holds at most 64 KiB, so ISIZE is its length
+    jobs.push_back(j);
+    pre.push_back(mb);
+    total += mb.isize;
+    at += size;
+  }
+  if (out_len) *out_len = total;
+  if (n_members) *n_members = (uint32_t)jobs.size();
+  if (jobs.empty()) return GZ_E_HEADER;
+  if (d_out && total > out_cap) {
+    snprintf(g_err, sizeof(g_err), "output needs %llu bytes", (unsigned long long)total);
+    return GZ_E_CAPACITY;
+  }
+  gz_plan_t p = new (std::nothrow) gz_plan_s();
+  if (!p) return GZ_E_ARG;
+  fill_defaults(p, opts);
+  if (p->win != 1024 && p->win != 2048 && p->win != 4096 && p->win != 8192 && p->win != 16384 && p->win != 32768) {
+    gz_plan_destroy(p);
+    return GZ_E_ARG;
+  }
+  p->jobs = jobs;
+  p->pre = pre;
+  const int r = plan_common(p);
+  if (r != GZ_OK) {
+    gz_plan_destroy(p);
+    return r;
+  }
+  (void)hipEventCreateWithFlags(&p->upload_done, hipEventDisableTiming);
+  if (p->opts.timing)
+    for (int i = 0; i <= GZ_N_PASSES; i++) (void)hipEventCreate(&p->pass_ev[i]);
   *plan = p;
   return GZ_OK;
 }

@@ -281,3 +281,43 @@ def stream_at(comp: bytes, bit: int, marker: int, segment_bytes: int, window: in
     finally:
         L.gz_stream_destroy(h)
     return segs, data, counts[: (len(data) + window - 1) // window].astype(np.int64)
+
+
+def bgzf_run(comp: bytes, **opts):
+    """gz_plan_bgzf + gz_decompress_batch: (status of the plan call, output
+    bytes, per-member statuses)."""
+    L = lib()
+    vp = C.c_void_p
+    L.gz_plan_bgzf.argtypes = [C.POINTER(vp), vp, vp, C.c_size_t, vp, C.c_size_t, C.POINTER(Opts),
+                               C.POINTER(C.c_uint64), C.POINTER(C.c_uint32)]
+    L.gz_decompress_batch.argtypes = [vp, vp, C.c_size_t, vp]
+    L.emu_set_sync_limit(3_000_000_000)
+    store = padded(comp)
+    buf = store[: len(comp)]
+    o = Opts()
+    for k, v in opts.items():
+        setattr(o, k, v)
+    n_out, n_mem = C.c_uint64(), C.c_uint32()
+    h = vp()
+    st = L.gz_plan_bgzf(C.byref(h), vp(buf.ctypes.data), None, buf.size, None, 0, C.byref(o), C.byref(n_out),
+                        C.byref(n_mem))
+    if st != 0:
+        return st, None, None
+    L.gz_plan_destroy(h)
+    out = np.zeros(max(1, n_out.value), dtype=np.uint8)
+    st = L.gz_plan_bgzf(C.byref(h), vp(buf.ctypes.data), None, buf.size, vp(out.ctypes.data), out.size, C.byref(o),
+                        C.byref(n_out), C.byref(n_mem))
+    assert st == 0, st
+    info = Info()
+    L.gz_plan_info(h, C.byref(info))
+    raw_ws = np.zeros(info.ws_bytes + 512, dtype=np.uint8)
+    off = (-raw_ws.ctypes.data) % 256
+    ws = raw_ws[off:off + info.ws_bytes]
+    assert L.gz_decompress_batch(h, vp(ws.ctypes.data), ws.size, None) == 0
+    sts = []
+    for f in range(n_mem.value):
+        r = Result()
+        L.gz_result_get(h, f, C.byref(r))
+        sts.append(r.status)
+    L.gz_plan_destroy(h)
+    return 0, out[: n_out.value].tobytes(), sts

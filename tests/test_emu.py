@@ -419,3 +419,25 @@ def test_emu_stream_multiple_members(orc):
     assert orc.gunzip(bytes(bc)).reason == "CRC"
     sc = E.stream_run(bytes(bc), 15000, chunk_bytes=4096)
     assert sc[-1][0]["status"] == -6 and sc[-1][0]["member"] == 1
+
+
+def test_emu_bgzf_batch(orc):
+    """A BGZF-style file (64 KiB members and the empty end member) decoded
+    as one batch of members equals the oracle's gunzip; a member without the
+    size subfield is refused; a bad CRC fails that member only."""
+    from bitwriter import bgzf_member
+
+    raw = synth.fastq_like(700 << 10, 361)
+    parts = [raw[i:i + (64 << 10)] for i in range(0, len(raw), 64 << 10)] + [b""]
+    comps = [bgzf_member(p, 6) for p in parts]
+    comp = b"".join(comps)
+    g = orc.gunzip(comp)
+    assert g.status == orc.OK and g.n_members == len(parts)
+    st, out, sts = E.bgzf_run(comp, chunk_bytes=8192)
+    assert st == 0 and out == g.out.tobytes() == raw and sts == [0] * len(parts)
+    st, _, _ = E.bgzf_run(comp + synth.gzip_member(b"abc", 6))
+    assert st == -2
+    bad = bytearray(comp)
+    bad[len(comps[0]) + len(comps[1]) - 8] ^= 1
+    st, out, sts = E.bgzf_run(bytes(bad), chunk_bytes=8192)
+    assert st == 0 and sts[1] == -6 and sts[0] == 0 and all(x == 0 for x in sts[2:])

@@ -213,3 +213,22 @@ def test_stream_multiple_members(orc):
             pass
     assert ei.value.code == gz.GZ_E_HEADER
     s.close()
+
+
+def test_bgzf_batch(orc):
+    """A BGZF-style file of 64 KiB members (about 64 MiB) decoded as one
+    batch: byte for byte the oracle's gunzip of all members."""
+    import paper_1905_07224_amd as gz
+    from bitwriter import bgzf_member
+
+    raw = synth.fastq_like(64 << 20, 831)
+    comp = b"".join(bgzf_member(raw[i:i + (64 << 10)], 6) for i in range(0, len(raw), 64 << 10)) + bgzf_member(b"")
+    g = orc.gunzip(comp)
+    assert g.status == orc.OK
+    _say("bgzf", len(comp), "bytes,", g.n_members, "members")
+    out = gz.decompress_bgzf(comp)
+    assert np.array_equal(out.cpu().numpy(), g.out)
+    bad = bytearray(comp)
+    bad[100] ^= 0x40
+    with pytest.raises(gz.GzError):
+        gz.decompress_bgzf(bytes(bad))
