@@ -266,3 +266,24 @@ def make(kind: str, size: int, seed: int, level: int, use_cache: bool = True, **
 def workload(name: str, use_cache: bool = True):
     kind, size, seed, level, kw = WORKLOADS[name]
     return make(kind, size, seed, level, use_cache=use_cache, **kw)
+
+
+def bgzf_member(data: bytes, level: int = 6) -> bytes:
+    """One BGZF-style gzip member (RFC 1952 with an FEXTRA field holding the
+    'BC' subfield: the member's total size minus one)."""
+    c = zlib.compressobj(level, zlib.DEFLATED, -15, 8)
+    body = c.compress(data) + c.flush()
+    total = 10 + 2 + 6 + len(body) + 8  # header, XLEN, the subfield, payload, trailer
+    extra = b"BC" + struct.pack("<H", 2) + struct.pack("<H", total - 1)
+    header = b"\x1f\x8b\x08\x04" + b"\x00\x00\x00\x00" + b"\x00\xff" + struct.pack("<H", len(extra)) + extra
+    trailer = struct.pack("<II", zlib.crc32(data) & 0xFFFFFFFF, len(data) & 0xFFFFFFFF)
+    return header + body + trailer
+
+
+def bgzf(data: bytes, level: int = 6, block: int = 64 << 10, threads: int | None = None) -> bytes:
+    """A BGZF-style file: members of `block` input bytes, then the empty member."""
+    pieces = [data[i:i + block] for i in range(0, len(data), block)]
+    nt = threads or min(16, os.cpu_count() or 1)
+    with ThreadPoolExecutor(max_workers=nt) as ex:
+        members = list(ex.map(lambda x: bgzf_member(x, level), pieces))
+    return b"".join(members) + bgzf_member(b"", level)

@@ -315,19 +315,3 @@ def gzip_wrap(deflate: bytes, data: bytes, flags: int = 0, extra: bytes = b"", n
     s = (len(data) & 0xFFFFFFFF) if isize is None else isize
     return bytes(hdr) + deflate + struct.pack("<II", c, s)
 
-
-def bgzf_member(data: bytes, level: int = 6) -> bytes:
-    """One BGZF-style gzip member (RFC 1952 with an FEXTRA field holding the
-    'BC' subfield: the member's total size minus one)."""
-    import struct
-    import zlib
-
-    c = zlib.compressobj(level, zlib.DEFLATED, -15, 8)
-    body = c.compress(data) + c.flush()
-    extra = b"BC" + struct.pack("<H", 2) + struct.pack("<H", 0)
-    header_len = 10 + 2 + len(extra)
-    total = header_len + len(body) + 8
-    extra = b"BC" + struct.pack("<H", 2) + struct.pack("<H", total - 1)
-    header = b"\x1f\x8b\x08\x04" + b"\x00\x00\x00\x00" + b"\x00\xff" + struct.pack("<H", len(extra)) + extra
-    trailer = struct.pack("<II", zlib.crc32(data) & 0xFFFFFFFF, len(data) & 0xFFFFFFFF)
-    return header + body + trailer

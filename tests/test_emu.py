@@ -374,12 +374,11 @@ def test_emu_window_propagation_many_segments(orc):
 
 
 def _members():
-    from bitwriter import bgzf_member
 
     parts = [synth.fastq_like(240 << 10, 351), synth.word_stream(60 << 10, 352), b"", synth.fastq_like(40 << 10, 353),
              synth.word_stream(30 << 10, 354)]
     comps = [synth.gzip_member(parts[0], 6), synth.gzip_member(parts[1], 1), synth.gzip_member(parts[2], 6),
-             bgzf_member(parts[3], 9), bgzf_member(parts[4], 6)]
+             synth.bgzf_member(parts[3], 9), synth.bgzf_member(parts[4], 6)]
     return parts, comps
 
 
@@ -425,11 +424,10 @@ def test_emu_bgzf_batch(orc):
     """A BGZF-style file (64 KiB members and the empty end member) decoded
     as one batch of members equals the oracle's gunzip; a member without the
     size subfield is refused; a bad CRC fails that member only."""
-    from bitwriter import bgzf_member
 
     raw = synth.fastq_like(700 << 10, 361)
     parts = [raw[i:i + (64 << 10)] for i in range(0, len(raw), 64 << 10)] + [b""]
-    comps = [bgzf_member(p, 6) for p in parts]
+    comps = [synth.bgzf_member(p, 6) for p in parts]
     comp = b"".join(comps)
     g = orc.gunzip(comp)
     assert g.status == orc.OK and g.n_members == len(parts)

@@ -185,12 +185,11 @@ def test_stream_multiple_members(orc):
     output is the oracle's gunzip of the whole input, each member ends with
     its own CRC-32, and a non-member tail fails with the oracle's status."""
     import paper_1905_07224_amd as gz
-    from bitwriter import bgzf_member
 
     parts = [synth.fastq_like(5 << 20, 821), synth.word_stream(3 << 20, 822), b"", synth.fastq_like(60 << 10, 823),
              synth.word_stream(50 << 10, 824), synth.fastq_like(2 << 20, 825)]
     comps = [synth.gzip_member(parts[0], 6), synth.gzip_member(parts[1], 1), synth.gzip_member(b"", 6),
-             bgzf_member(parts[3], 6), bgzf_member(parts[4], 9), synth.gzip_member(parts[5], 9)]
+             synth.bgzf_member(parts[3], 6), synth.bgzf_member(parts[4], 9), synth.gzip_member(parts[5], 9)]
     comp = b"".join(comps)
     g = orc.gunzip(comp)
     assert g.status == orc.OK and g.n_members == len(parts)
@@ -219,10 +218,9 @@ def test_bgzf_batch(orc):
     """A BGZF-style file of 64 KiB members (about 64 MiB) decoded as one
     batch: byte for byte the oracle's gunzip of all members."""
     import paper_1905_07224_amd as gz
-    from bitwriter import bgzf_member
 
     raw = synth.fastq_like(64 << 20, 831)
-    comp = b"".join(bgzf_member(raw[i:i + (64 << 10)], 6) for i in range(0, len(raw), 64 << 10)) + bgzf_member(b"")
+    comp = b"".join(synth.bgzf_member(raw[i:i + (64 << 10)], 6) for i in range(0, len(raw), 64 << 10)) + synth.bgzf_member(b"")
     g = orc.gunzip(comp)
     assert g.status == orc.OK
     _say("bgzf", len(comp), "bytes,", g.n_members, "members")
