@@ -346,6 +346,10 @@ def test_emu_scan_table_check_equals_decoder(orc, kind):
     true_starts = set(int(x) for x, t, f in zip(g.block_bit, g.block_type, g.block_final)
                       if t == 2 and not f and x < 8 * (1 << 20))
     assert true_starts <= set(int(x) for x in cand) and cand.size > 50
+    # the true starts and a seeded sample of the other survivors
+    others = np.array(sorted(set(int(x) for x in cand) - true_starts), np.uint64)
+    pick = np.random.default_rng(335).choice(others.size, min(others.size, 600), replace=False)
+    cand = np.array(sorted(true_starts | set(int(x) for x in others[pick])), np.uint64)
     L = E.lib()
     L.emu_stage2_diff.argtypes = [C.c_void_p, C.c_uint64, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]
     store = E.padded(comp)
@@ -375,7 +379,7 @@ def test_emu_window_propagation_many_segments(orc):
 
 def _members():
 
-    parts = [synth.fastq_like(240 << 10, 351), synth.word_stream(60 << 10, 352), b"", synth.fastq_like(40 << 10, 353),
+    parts = [synth.fastq_like(120 << 10, 351), synth.word_stream(60 << 10, 352), b"", synth.fastq_like(40 << 10, 353),
              synth.word_stream(30 << 10, 354)]
     comps = [synth.gzip_member(parts[0], 6), synth.gzip_member(parts[1], 1), synth.gzip_member(parts[2], 6),
              synth.bgzf_member(parts[3], 9), synth.bgzf_member(parts[4], 6)]
@@ -425,7 +429,7 @@ def test_emu_bgzf_batch(orc):
     as one batch of members equals the oracle's gunzip; a member without the
     size subfield is refused; a bad CRC fails that member only."""
 
-    raw = synth.fastq_like(700 << 10, 361)
+    raw = synth.fastq_like(300 << 10, 361)
     parts = [raw[i:i + (64 << 10)] for i in range(0, len(raw), 64 << 10)] + [b""]
     comps = [synth.bgzf_member(p, 6) for p in parts]
     comp = b"".join(comps)
