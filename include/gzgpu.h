@@ -53,7 +53,7 @@ extern "C" {
 typedef struct gz_opts {
   uint64_t chunk_bytes;   /* nominal compressed bytes per chunk when n_chunks == 0 (default 40 KiB) */
   uint32_t sym_factor;    /* symbol capacity per chunk = sym_factor * compressed bytes + slack (default 8) */
-  uint32_t window_syms;   /* LDS history ring per decoding wave, in symbols: 1024, 2048, 4096, 8192, 16384
+  uint32_t window_syms;   /* LDS history ring per decoding wave, in symbols: 512, 1024, 2048, 4096, 8192, 16384
                              or 32768 (default 1024); match sources further back are read from HBM.
                              Any other value: GZ_E_ARG */
   uint32_t scan_groups;   /* workgroups that search one chunk's start in parallel (default: 4096 / chunks, 1..64) */

@@ -386,6 +386,9 @@ static int plan_common(gz_plan_t p) {
   return GZ_OK;
 }
 
+// Ring sizes the decoder is built for: powers of two from 512 to 32768.
+static bool valid_ring(uint32_t win) { return win >= 512 && win <= 32768 && (win & (win - 1)) == 0; }
+
 static void fill_defaults(gz_plan_t p, const gz_opts *opts, bool query_device = true) {
   if (opts) p->opts = *opts;
   if (p->opts.chunk_bytes == 0) p->opts.chunk_bytes = DEFAULT_CHUNK_BYTES;
@@ -406,7 +409,7 @@ static int make_plan(gz_plan_t *plan, const gz_job *jobs, int n, const gz_opts *
   gz_plan_t p = new (std::nothrow) gz_plan_s();
   if (!p) return GZ_E_ARG;
   fill_defaults(p, opts);
-  if (p->win != 1024 && p->win != 2048 && p->win != 4096 && p->win != 8192 && p->win != 16384 && p->win != 32768) {
+  if (!valid_ring(p->win)) {
     gz_plan_destroy(p);
     return GZ_E_ARG;
   }
@@ -457,7 +460,7 @@ int gz_plan_probes(gz_plan_t *plan, const void *d_comp, size_t comp_len, const u
   gz_plan_t p = new (std::nothrow) gz_plan_s();
   if (!p) return GZ_E_ARG;
   fill_defaults(p, opts);
-  if (p->win != 1024 && p->win != 2048 && p->win != 4096 && p->win != 8192 && p->win != 16384 && p->win != 32768) {
+  if (!valid_ring(p->win)) {
     gz_plan_destroy(p);
     return GZ_E_ARG;
   }
@@ -543,7 +546,7 @@ int gz_plan_bgzf(gz_plan_t *plan, const void *d_comp, const void *h_comp, size_t
   gz_plan_t p = new (std::nothrow) gz_plan_s();
   if (!p) return GZ_E_ARG;
   fill_defaults(p, opts);
-  if (p->win != 1024 && p->win != 2048 && p->win != 4096 && p->win != 8192 && p->win != 16384 && p->win != 32768) {
+  if (!valid_ring(p->win)) {
     gz_plan_destroy(p);
     return GZ_E_ARG;
   }

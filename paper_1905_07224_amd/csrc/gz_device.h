@@ -58,6 +58,14 @@ __device__ __forceinline__ bool ascii_text(uint32_t c) {
 #endif
 typedef const GZ_GLOBAL uint32_t *gdw_ptr;
 
+// v_writelane_b32: `old` with lane l (uniform, below 64) replaced by the
+// uniform value v.  hipcc has no builtin name for LLVM's amdgcn writelane
+// intrinsic, so it is declared under the intrinsic's own name.
+#ifndef GZ_WRITELANE
+__device__ int gz_writelane_i32(int v, int l, int old) __asm("llvm.amdgcn.writelane.i32");
+#define GZ_WRITELANE(v, l, old) gz_writelane_i32((v), (l), (old))
+#endif
+
 struct Src {
   gdw_ptr base;          // comp rounded down to 4 bytes
   uint32_t mis;          // comp & 3

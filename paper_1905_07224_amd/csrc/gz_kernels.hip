@@ -14,6 +14,8 @@
 //   k_translate  pass 2b: every U_j replaced by w_i[j], written to the output
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "gz_device.h"
 #include "gz_internal.h"
 
@@ -28,7 +30,8 @@ struct InflateLDS {
   TablesLDS t;
   alignas(16) uint16_t ring[WIN];  // the last WIN symbols produced, by position mod WIN
 };
-static_assert(sizeof(InflateLDS<2048>) <= inflate_lds_bytes(2048) && sizeof(InflateLDS<4096>) <= inflate_lds_bytes(4096) && sizeof(InflateLDS<8192>) <= inflate_lds_bytes(8192) &&
+static_assert(sizeof(InflateLDS<512>) <= inflate_lds_bytes(512) && sizeof(InflateLDS<1024>) <= inflate_lds_bytes(1024) &&
+                  sizeof(InflateLDS<2048>) <= inflate_lds_bytes(2048) && sizeof(InflateLDS<4096>) <= inflate_lds_bytes(4096) && sizeof(InflateLDS<8192>) <= inflate_lds_bytes(8192) &&
                   sizeof(InflateLDS<16384>) <= inflate_lds_bytes(16384) &&
                   sizeof(InflateLDS<32768>) <= inflate_lds_bytes(32768),
               "decoder LDS larger than the occupancy estimate");
@@ -45,23 +48,29 @@ struct DecodeResult {
 
 template <int WIN>
 struct Inflater {
-  // The ring holds the last WIN symbols (WIN a power of two, 4096..32768).
-  // A batch reads all its sources before it writes any of its symbols, so a
-  // source pos - d + k with d <= WIN is in the ring; an older one (only when
-  // WIN < 32768) is read back from this chunk's symbols in HBM, which were
-  // stored at least WIN - 576 symbols earlier: every unit store waits for the
-  // stores before it, so those are complete, and the read bypasses the L1,
-  // which may still hold lines of an earlier attempt at this chunk.  The unit
-  // being moved to HBM is never older than 512 + 64 symbols.
-  static_assert(WIN >= 1024 && WIN <= 32768 && (WIN & (WIN - 1)) == 0, "ring size");
+  // The ring holds the last WIN symbols (WIN a power of two, 512..32768).
+  // Symbols move to HBM in units of UNIT <= WIN / 2; fewer than UNIT are
+  // unstored when a batch is issued and fewer than UNIT + 64 after it is
+  // written, so no unstored symbol is overwritten.  A batch reads all its
+  // sources before it writes any of its symbols, so a source pos - d + k with
+  // d <= WIN is in the ring; an older one (only when WIN < 32768) lies below
+  // pos - WIN <= stored - (WIN - UNIT), in a unit before the last one stored:
+  // every unit store waits for the stores before it, so those are complete,
+  // and the read bypasses the L1, which may still hold lines of an earlier
+  // attempt at this chunk.
+  static_assert(WIN >= 512 && WIN <= 32768 && (WIN & (WIN - 1)) == 0, "ring size");
   static constexpr uint32_t RMASK = WIN - 1;
+  static constexpr uint32_t UNIT = WIN < 2 * FLUSH_UNIT ? WIN / 2 : FLUSH_UNIT;
+  static constexpr uint32_t PER_LANE = UNIT / 64;  // symbols each lane moves: 8 (one uint4) or 4 (one uint2)
+  using UnitVec = typename std::conditional<PER_LANE == 8, uint4, uint2>::type;
+  static_assert(UNIT % 64 == 0 && (PER_LANE == 8 || PER_LANE == 4) && FLUSH_UNIT % UNIT == 0, "flush unit");
 
   InflateLDS<WIN> &sh;
   WaveBits br;
   uint16_t *D;       // chunk symbols in HBM
   uint64_t cap;      // symbol capacity
   uint64_t pos;      // symbols produced
-  uint64_t flushed;  // symbols stored to HBM (multiple of FLUSH_UNIT)
+  uint64_t flushed;  // symbols stored to HBM (multiple of UNIT)
   uint64_t nsyms;
   uint32_t nph;      // per lane placeholder count
   uint32_t nph_stop; // per lane placeholder count at the stop (symbols of D_i only)
@@ -79,16 +88,16 @@ struct Inflater {
     wave_sync();
     const int lane = lane_id();
     const uint64_t u = flushed;
-    const uint4 v = *reinterpret_cast<const uint4 *>(&sh.ring[(u + 8u * lane) & RMASK]);
-    if (u + FLUSH_UNIT <= cap) {
-      *reinterpret_cast<uint4 *>(D + u + 8u * lane) = v;
+    const UnitVec v = *reinterpret_cast<const UnitVec *>(&sh.ring[(u + PER_LANE * lane) & RMASK]);
+    if (u + UNIT <= cap) {
+      *reinterpret_cast<UnitVec *>(D + u + PER_LANE * lane) = v;
     } else {
       over = true;
     }
-    flushed = u + FLUSH_UNIT;
+    flushed = u + UNIT;
   }
   __device__ __forceinline__ void maybe_flush() {
-    while (pos > flushed && pos - flushed >= FLUSH_UNIT) flush_unit();
+    while (pos > flushed && pos - flushed >= UNIT) flush_unit();
   }
   __device__ void flush_all() {
     while (flushed < pos) flush_unit();
@@ -263,14 +272,18 @@ struct Inflater {
   }
 
   // Token words of one lookup round (per lane k: the token that would start
-  // at bit offset k): bits 5..0 the bits it uses (at most 48), bits 14..6
-  // its output length (1: a literal), bits 30..15 the literal byte or the
-  // match distance (1..32768).  TOK_SPECIAL set: the walk stops there, with
-  // the kind in bits 29..28 (end-of-block: its code length in the low bits).
-  static constexpr uint32_t TOK_SPECIAL = 0x80000000u;
-  static constexpr uint32_t TOK_EOB = TOK_SPECIAL | (1u << 28);
-  static constexpr uint32_t TOK_SLOW = TOK_SPECIAL | (2u << 28);   // longer code, or invalid: decoded alone
-  static constexpr uint32_t TOK_ASCII = TOK_SPECIAL | (3u << 28);  // non-ASCII literal in a checked block
+  // at bit offset k): bits 7..0 the bits it uses (at most 48), bits 16..8
+  // its output length (1: a literal), bits 31..17 the literal byte or the
+  // match distance minus one (0..32767).  The low 17 bits are what a token
+  // adds to the walk's packed (output symbols << 8 | bit offset) counter.
+  // A special token has length 511, so that adding it ends any walk, and
+  // its kind in bits 31..17 (end-of-block: its code length in bits 7..0).
+  static constexpr uint32_t TOK_STEP = 0x1FFFFu;
+  static constexpr uint32_t TOK_SPECIAL = 511u << 8;
+  static constexpr uint32_t TOK_EOB = TOK_SPECIAL | (1u << 17);
+  static constexpr uint32_t TOK_SLOW = TOK_SPECIAL | (2u << 17);   // longer code, or invalid: decoded alone
+  static constexpr uint32_t TOK_ASCII = TOK_SPECIAL | (3u << 17);  // non-ASCII literal in a checked block
+  __device__ __forceinline__ static bool tok_special(uint32_t t) { return (t & TOK_SPECIAL) == TOK_SPECIAL; }
 
   // The token word at bit offset k of a lookup round, from the 64 stream
   // bits at that offset (w: bits k .. k + 63) and its two table entries
@@ -285,9 +298,9 @@ struct Inflater {
     const uint32_t dl = ed & 15u, dex = (ed >> 8) & 15u;
     const uint32_t len = (e >> 16) + ((w0 >> cl) & ((1u << ex) - 1u));
     const uint32_t dist = (ed >> 16) + ((uint32_t)(w >> (u + dl)) & ((1u << dex) - 1u));
-    uint32_t wl = cl | (1u << 6) | (((e >> 8) & 255u) << 15);
+    uint32_t wl = cl | (1u << 8) | (((e >> 8) & 255u) << 17);
     if (CHECK) wl = kind == K_LITX ? TOK_ASCII : wl;
-    const uint32_t wm = ((ed >> 4) & 15u) == K_LEN ? (u + dl + dex) | (len << 6) | (dist << 15) : TOK_SLOW;
+    const uint32_t wm = ((ed >> 4) & 15u) == K_LEN ? (u + dl + dex) | (len << 8) | ((dist - 1u) << 17) : TOK_SLOW;
     const uint32_t wo = kind == K_EOB ? (TOK_EOB | cl) : TOK_SLOW;
     return (kind & 7u) == K_LIT ? wl : kind == K_LEN ? wm : wo;
   }
@@ -352,42 +365,44 @@ struct Inflater {
       uint32_t jr = 0;  // output symbols of the tokens walked so far
       const uint32_t cont = rem ? 1u : 0u;
       if (cont) {
-        if (lane == 0) word = (2u << 6) | (mdist << 15);
+        if (lane == 0) word = (2u << 8) | ((mdist - 1u) << 17);
         jr = rem;
       }
-      // offsets below 64 come from tok0, the rest from tok1 (a walk never
-      // returns below an offset it passed, so the two halves are two loops);
-      // a walk that stops below 64 symbols and offset 128 stopped at a
-      // special token
-      if ((jr | off) < 64u) {
-        uint32_t t;
+      // acc = jr << 8 | off; offsets below 64 come from tok0, the rest from
+      // tok1 (a walk never returns below an offset it passed, so the two
+      // halves are two loops).  Each step writes the token's word at lane jr
+      // and adds its step; a special token adds 511 symbols, which ends the
+      // walk, and is taken back out below.
+      uint32_t acc = (jr << 8) | off;
+      uint32_t t = 0;  // the last token walked
+      if ((acc & 0xFFFFC0C0u) == 0u) {
         do {
-          t = (uint32_t)__builtin_amdgcn_readlane((int)tok0, (int)off);
-          if (t & TOK_SPECIAL) break;
-          word = (uint32_t)lane == jr ? t : word;
-          jr += (t >> 6) & 511u;
-          off += t & 63u;
-        } while ((jr | off) < 64u);
+          t = (uint32_t)__builtin_amdgcn_readlane((int)tok0, (int)(acc & 63u));
+          word = (uint32_t)GZ_WRITELANE((int)t, (int)(acc >> 8), (int)word);
+          acc += t & TOK_STEP;
+        } while ((acc & 0xFFFFC0C0u) == 0u);
       }
-      if (jr < 64u && off - 64u < 64u) {
-        uint32_t t;
+      if ((acc & 0xFFFFC080u) == 0u) {
         do {
-          t = (uint32_t)__builtin_amdgcn_readlane((int)tok1, (int)(off - 64u));
-          if (t & TOK_SPECIAL) break;
-          word = (uint32_t)lane == jr ? t : word;
-          jr += (t >> 6) & 511u;
-          off += t & 63u;
-        } while ((jr | (off >> 1)) < 64u);
+          t = (uint32_t)__builtin_amdgcn_readlane((int)tok1, (int)(acc & 63u));
+          word = (uint32_t)GZ_WRITELANE((int)t, (int)(acc >> 8), (int)word);
+          acc += t & TOK_STEP;
+        } while ((acc & 0xFFFFC080u) == 0u);
       }
       uint32_t x = 0;  // the special token that stopped the walk, else 0
-      if (jr < 64u && off < 128u)
-        x = (uint32_t)__builtin_amdgcn_readlane(off < 64u ? (int)tok0 : (int)tok1, (int)(off & 63u));
+      if (tok_special(t)) {
+        x = t;
+        acc -= t & TOK_STEP;
+        word = (uint32_t)GZ_WRITELANE(0, (int)(acc >> 8), (int)word);
+      }
+      jr = acc >> 8;
+      off = acc & 255u;
       const uint64_t starts = __ballot(word != 0u);
       // a token running past the batch continues in the next one (its
       // word is at the last start lane)
       const uint32_t j = jr < 64u ? jr : 64u;
       rem = jr - j;
-      if (rem) mdist = (uint32_t)__builtin_amdgcn_readlane((int)word, 63 - __builtin_clzll(starts)) >> 15;
+      if (rem) mdist = ((uint32_t)__builtin_amdgcn_readlane((int)word, 63 - __builtin_clzll(starts)) >> 17) + 1u;
       nsyms += (uint32_t)__builtin_popcountll(starts) - cont;
       if (j) {
         // each lane's token: the last start at or before the lane
@@ -395,12 +410,12 @@ struct Inflater {
         const uint64_t m = starts & upto;
         const int src = 63 - (int)__builtin_clzll(m | 1ull);
         const uint32_t w = (uint32_t)__shfl((int)word, src);
-        const int32_t ref = ((w >> 6) & 511u) == 1u ? (int32_t)(REF_LIT | ((w >> 15) & 255u))
-                                                    : lane - (int32_t)(w >> 15);
+        const int32_t ref = ((w >> 8) & 511u) == 1u ? (int32_t)(REF_LIT | ((w >> 17) & 255u))
+                                                    : lane - (int32_t)((w >> 17) + 1u);
         const int r = put_batch(ref, j);
         if (r != D_OK) return r;
       }
-      if (x & TOK_SPECIAL) {
+      if (x) {
         if (x == TOK_ASCII) return D_ASCII;
         if ((x & ~255u) == TOK_EOB) {
           nsyms++;
@@ -875,8 +890,11 @@ __global__ __launch_bounds__(256) void k_capacity(const FileDesc *files, ChunkDe
 // k_inflate: persistent; each wave pops chunk indices from the work queue.
 // ---------------------------------------------------------------------------
 
+// The 512-symbol ring: at most 96 VGPRs (5 waves per SIMD), so that 18
+// decoders fit in a CU's LDS and registers; what does not fit in 96 is
+// loop-invariant and reloaded once per chunk.
 template <int WIN>
-__global__ __launch_bounds__(64) void k_inflate(const FileDesc *files, const ChunkDesc *chunks, ChunkState *cs,
+__global__ __launch_bounds__(64, WIN == 512 ? 5 : 1) void k_inflate(const FileDesc *files, const ChunkDesc *chunks, ChunkState *cs,
                                                 const uint32_t *order, uint32_t n, Counters *ctr, uint16_t *pool) {
   __shared__ InflateLDS<WIN> sh;
   for (uint32_t it = 0; it <= n; it++) {
@@ -995,7 +1013,7 @@ __device__ void extend_chunk(InflateLDS<WIN> &sh, const FileDesc &fd, const Chun
     sh.ring[p & (WIN - 1)] = p < cd.sym_cap ? inf.D[p] : (uint16_t)0;
   wave_sync();
   inf.pos = len;
-  inf.flushed = len & ~(uint64_t)(FLUSH_UNIT - 1);
+  inf.flushed = len & ~(uint64_t)(Inflater<WIN>::UNIT - 1);
   DecodeResult r = inf.run(e, stop, 0u);
   uint32_t ph = wave_sum(inf.nph_stop);
   if (lane == 0) {
@@ -1806,6 +1824,10 @@ hipError_t gzk_scan(const FileDesc *files, const ChunkDesc *chunks, ChunkState *
 
 #define GZ_WIN_SWITCH(win, CALL)   \
   switch (win) {                   \
+    case 512: {                    \
+      constexpr int W = 512;       \
+      CALL;                        \
+    } break;                       \
     case 1024: {                   \
       constexpr int W = 1024;      \
       CALL;                        \

@@ -25,7 +25,7 @@ def build(opt="-O1", extra=()):
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [CXX, "-std=c++17", opt, "-g", "-fPIC", "-shared", "-Wno-unused-function",
            "-I", os.path.join(HERE, "include"), "-I", os.path.join(ROOT, "include"), "-I", CSRC,
-           "-DGZ_GLOBAL=", "-x", "c++"] + SRCS + list(extra) + ["-o", tmp]
+           "-DGZ_GLOBAL=", "-DGZ_WRITELANE=__builtin_amdgcn_writelane", "-x", "c++"] + SRCS + list(extra) + ["-o", tmp]
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
     return LIB

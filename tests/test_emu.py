@@ -74,7 +74,7 @@ def test_emu_segmented_and_stored(orc):
 def test_emu_window_sizes(orc):
     raw = synth.fastq_like(100 << 10, 305)
     comp = synth.gzip_member(raw, 6)
-    for win in (1024, 2048, 4096, 8192, 16384, 32768):
+    for win in (512, 1024, 2048, 4096, 8192, 16384, 32768):
         st, out, r, tab = E.run(comp, 3, out_cap=len(raw) + 64, window_syms=win)
         assert st == 0 and out == raw
 

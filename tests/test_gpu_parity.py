@@ -226,7 +226,7 @@ def test_repeat_determinism(orc, c1):
     assert stats[0] == stats[1] == stats[2]
 
 
-@pytest.mark.parametrize("win", [1024, 2048, 4096, 8192, 16384, 32768])
+@pytest.mark.parametrize("win", [512, 1024, 2048, 4096, 8192, 16384, 32768])
 def test_window_sizes(orc, c1, win):
     raw, comp = c1
     _say("LDS window", win)
