@@ -363,9 +363,9 @@ struct Inflater {
       // (a token word is never 0, so the start lanes are where word != 0)
       uint32_t word = 0;
       uint32_t jr = 0;  // output symbols of the tokens walked so far
-      const uint32_t cont = rem ? 1u : 0u;
-      if (cont) {
-        if (lane == 0) word = (2u << 8) | ((mdist - 1u) << 17);
+      const uint32_t cont = min(rem, 1u);  // (an integer, not a lane mask)
+      if (rem) {
+        word = (uint32_t)GZ_WRITELANE((int)((2u << 8) | ((mdist - 1u) << 17)), 0, 0);
         jr = rem;
       }
       // acc = jr << 8 | off; offsets below 64 come from tok0, the rest from
