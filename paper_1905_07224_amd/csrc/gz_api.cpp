@@ -157,7 +157,8 @@ struct gz_plan_s {
   uint8_t *ws = nullptr;
   hipStream_t stream = nullptr;
   bool launched = false;
-  bool fetched = false;
+  bool fetched = false;         // the stream finished and fst holds the file states
+  bool fetched_chunks = false;  // cst and cdev hold the chunk states and table too
   std::vector<FileState> fst;
   std::vector<ChunkState> cst;
   std::vector<ChunkDesc> cdev;  // the device's chunk table after the run (capacities)
@@ -443,6 +444,7 @@ int gz_plan_batch(gz_plan_t *plan, const gz_job *jobs, int n_jobs, const gz_opts
 
 static int launch(gz_plan_t p, uint8_t *ws, size_t ws_bytes, hipStream_t st);
 static int fetch(gz_plan_t p);
+static int fetch_chunks(gz_plan_t p);
 
 int gz_plan_probes(gz_plan_t *plan, const void *d_comp, size_t comp_len, const uint64_t *bits, int n_probes,
                    uint64_t range_bytes, const gz_opts *opts) {
@@ -571,7 +573,7 @@ int gz_find_blocks(gz_plan_t p, void *d_ws, size_t ws_bytes, void *stream) {
 
 int gz_probe_starts(gz_plan_t p, uint64_t *start_bits, uint32_t *n_retries) {
   if (!p || !p->probe || !start_bits) return GZ_E_ARG;
-  const int r = fetch(p);
+  const int r = fetch_chunks(p);
   if (r != GZ_OK) return r;
   for (size_t f = 0; f < p->files.size(); f++) {
     const ChunkState &c = p->cst[p->files[f].first_chunk];
@@ -796,20 +798,35 @@ static int fetch(gz_plan_t p) {
       snprintf(g_err, sizeof(g_err), "the stream did not finish within %.0f s", limit);
       return GZ_E_HIP;
     }
-    std::this_thread::sleep_for(std::chrono::microseconds(el < 0.01 ? 20 : 1000));
+    // short polls for the first second, so that a finished run is seen
+    // within tens of microseconds
+    std::this_thread::sleep_for(std::chrono::microseconds(el < 1.0 ? 20 : 1000));
   }
   if (e != hipSuccess) return hip_fail(e, "stream synchronize");
-  const uint32_t F = (uint32_t)p->files.size(), N = (uint32_t)p->chunks.size();
+  const uint32_t F = (uint32_t)p->files.size();
   p->fst.resize(F);
-  p->cst.resize(N);
   e = hipMemcpy(p->fst.data(), p->ws + p->lay.fstate_off, F * sizeof(FileState), hipMemcpyDeviceToHost);
   if (e != hipSuccess) return hip_fail(e, "reading file state");
-  e = hipMemcpy(p->cst.data(), p->ws + p->lay.cstate_off, (size_t)N * sizeof(ChunkState), hipMemcpyDeviceToHost);
+  p->fetched = true;
+  p->fetched_chunks = false;
+  return GZ_OK;
+}
+
+// fetch(), and the per-chunk states and chunk table (read only by the calls
+// that report per-chunk data, and when a chunk overflowed its capacity).
+static int fetch_chunks(gz_plan_t p) {
+  int r = fetch(p);
+  if (r != GZ_OK) return r;
+  if (p->fetched_chunks) return GZ_OK;
+  const uint32_t N = (uint32_t)p->chunks.size();
+  p->cst.resize(N);
+  hipError_t e = hipMemcpy(p->cst.data(), p->ws + p->lay.cstate_off, (size_t)N * sizeof(ChunkState),
+                           hipMemcpyDeviceToHost);
   if (e != hipSuccess) return hip_fail(e, "reading chunk state");
   p->cdev.resize(N);
   e = hipMemcpy(p->cdev.data(), p->ws + p->lay.chunks_off, (size_t)N * sizeof(ChunkDesc), hipMemcpyDeviceToHost);
   if (e != hipSuccess) return hip_fail(e, "reading chunk table");
-  p->fetched = true;
+  p->fetched_chunks = true;
   return GZ_OK;
 }
 
@@ -847,6 +864,8 @@ int gz_result_get(gz_plan_t p, int file, gz_result *res) {
   res->crc32 = s.crc_out;
   if (s.overflow) {
     // the workspace of a plan whose symbol factor covers the worst chunk
+    r = fetch_chunks(p);
+    if (r != GZ_OK) return r;
     const uint64_t f2 = needed_factor(p, file);
     res->ws_needed = p->lay.total + 2 * (f2 > p->opts.sym_factor ? f2 - p->opts.sym_factor : 1) * p->span[file];
   }
@@ -856,7 +875,7 @@ int gz_result_get(gz_plan_t p, int file, gz_result *res) {
 int gz_chunk_table(gz_plan_t p, int file, uint64_t *start, uint64_t *cand, uint64_t *end, uint64_t *len,
                    uint64_t *out_off, int32_t *status, uint32_t *flags) {
   if (!p || file < 0 || file >= (int)p->files.size()) return GZ_E_ARG;
-  int r = fetch(p);
+  int r = fetch_chunks(p);
   if (r != GZ_OK) return r;
   const FileDesc &fd = p->files[file];
   for (uint32_t i = 0; i < fd.n_chunks; i++) {
@@ -874,7 +893,7 @@ int gz_chunk_table(gz_plan_t p, int file, uint64_t *start, uint64_t *cand, uint6
 
 int gz_debug_layout(gz_plan_t p, int file, uint64_t *sym_off, uint64_t *win_index, void **sym_base, void **win_base) {
   if (!p || file < 0 || file >= (int)p->files.size() || !p->launched) return GZ_E_ARG;
-  int r = fetch(p);
+  int r = fetch_chunks(p);
   if (r != GZ_OK) return r;
   const FileDesc &fd = p->files[file];
   for (uint32_t i = 0; i < fd.n_chunks; i++) {

@@ -1519,7 +1519,10 @@ __global__ __launch_bounds__(1024) void k_tilescan(const ChunkDesc *chunks, cons
 // whose files failed translates nothing.
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(256) void k_translate(const FileDesc *files, const ChunkDesc *chunks, const ChunkState *cs,
+constexpr uint32_t TRANSLATE_THREADS = 256;
+static_assert(TRANSLATE_TILE % (8u * TRANSLATE_THREADS) == 0, "translate piece");
+
+__global__ __launch_bounds__(TRANSLATE_THREADS) void k_translate(const FileDesc *files, const ChunkDesc *chunks, const ChunkState *cs,
                                                    FileState *fs, const uint64_t *tiles, uint32_t n,
                                                    const uint8_t *wins, const uint16_t *pool, Counters *ctr) {
   __shared__ uint32_t s_item;
@@ -1547,7 +1550,12 @@ __global__ __launch_bounds__(256) void k_translate(const FileDesc *files, const 
     // whatever the window holds)
     if (sj.valid) {
       const uint4 *wj = reinterpret_cast<const uint4 *>(wins + (uint64_t)j * WINDOW);
-      for (uint32_t k = threadIdx.x; k < WINDOW / 16; k += blockDim.x) wlw[k] = wj[k];
+      static_assert(WINDOW % (16u * TRANSLATE_THREADS) == 0, "window load");
+      uint4 wv[WINDOW / (16u * TRANSLATE_THREADS)];
+#pragma unroll
+      for (uint32_t i = 0; i < WINDOW / (16u * TRANSLATE_THREADS); i++) wv[i] = wj[threadIdx.x + TRANSLATE_THREADS * i];
+#pragma unroll
+      for (uint32_t i = 0; i < WINDOW / (16u * TRANSLATE_THREADS); i++) wlw[threadIdx.x + TRANSLATE_THREADS * i] = wv[i];
       __syncthreads();
     }
     int err = 0;
@@ -1558,9 +1566,18 @@ __global__ __launch_bounds__(256) void k_translate(const FileDesc *files, const 
       const uint64_t cnt = L - p0 < TRANSLATE_TILE ? L - p0 : TRANSLATE_TILE;
       const uintptr_t ob = (uintptr_t)(out + p0);
       const uint32_t sh = (uint32_t)(ob & 15u);
-      for (uint64_t g = p0 + 8ull * threadIdx.x; g < p0 + cnt; g += 8ull * blockDim.x) {
-        const uint4 v = *reinterpret_cast<const uint4 *>(Dj + g);
-        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+      // all of a thread's loads of the piece are issued before any is used
+      constexpr uint32_t PER = TRANSLATE_TILE / (8u * TRANSLATE_THREADS);
+      uint4 v[PER];
+#pragma unroll
+      for (uint32_t i = 0; i < PER; i++) {
+        const uint64_t g = p0 + 8ull * (threadIdx.x + TRANSLATE_THREADS * i);
+        v[i] = g < p0 + cnt ? *reinterpret_cast<const uint4 *>(Dj + g) : uint4{0u, 0u, 0u, 0u};
+      }
+#pragma unroll
+      for (uint32_t i = 0; i < PER; i++) {
+        const uint64_t g = p0 + 8ull * (threadIdx.x + TRANSLATE_THREADS * i);
+        const uint32_t w[4] = {v[i].x, v[i].y, v[i].z, v[i].w};
 #pragma unroll
         for (int h = 0; h < 8; h++) {
           const uint64_t p = g + h;
@@ -1946,7 +1963,7 @@ hipError_t gzk_carry(const FileDesc *files, const FileState *fs, const uint8_t *
 hipError_t gzk_translate(uint32_t grid, const FileDesc *files, const ChunkDesc *chunks, const ChunkState *cs,
                          FileState *fs, const uint64_t *tiles, uint32_t n, const uint8_t *wins, const uint16_t *pool,
                          Counters *ctr, hipStream_t st) {
-  hipLaunchKernelGGL(k_translate, dim3(grid), dim3(256), 0, st, files, chunks, cs, fs, tiles, n, wins, pool, ctr);
+  hipLaunchKernelGGL(k_translate, dim3(grid), dim3(TRANSLATE_THREADS), 0, st, files, chunks, cs, fs, tiles, n, wins, pool, ctr);
   return hipGetLastError();
 }
 
