@@ -152,29 +152,21 @@ struct Inflater {
 
   __device__ __forceinline__ int issue(int32_t ref, uint32_t j) {
     const int lane = lane_id();
-    const bool act = lane < (int)j;
-    uint32_t val = 0;
-    int32_t p = lane;
-    bool far = false, before = false;
-    int64_t a = 0;
     wave_sync();
-    if (act) {
-      if (ref >= REF_LIT) {
-        val = (uint32_t)ref & 0xFFFFu;
-      } else if (ref < 0) {
-        a = (int64_t)pos + ref;
-        if (a < 0) {
-          before = true;
-          val = 0x8000u | (uint32_t)(a + WINDOW);
-        } else if (WIN == 32768 || a >= (int64_t)pos - WIN) {
-          val = (uint32_t)sh.ring[a & RMASK];
-        } else {
-          far = true;
-        }
-      } else {
-        p = ref;
-      }
-    }
+    // every lane works out every case and selects one, with no divergent
+    // branch (whose exec-mask bookkeeping would cost more than the cases)
+    const bool act = lane < (int)j;
+    const bool lit = ref >= REF_LIT;
+    const bool back = act && !lit && ref < 0;  // a symbol produced before the batch
+    const int64_t a = (int64_t)pos + ref;
+    const bool before = back && a < 0;         // a placeholder U_j before the chunk
+    const bool near = WIN == 32768 || ref >= -(int32_t)WIN;  // a >= pos - WIN: in the ring
+    bool far = back && !before && !near;
+    // the ring slot of a (the index is masked, so lanes that do not need it
+    // read some slot of the ring, unused)
+    const uint32_t rv = (uint32_t)sh.ring[((uint32_t)pos + (uint32_t)ref) & RMASK];
+    const uint32_t val = lit ? ((uint32_t)ref & 0xFFFFu) : before ? (0x8000u | (uint32_t)(a + WINDOW)) : rv;
+    const int32_t p = act && !lit && ref >= 0 ? ref : lane;
     if (first && __ballot(before)) return D_FAR;
     // every lane loads (element 0 where no HBM source is needed), so the load
     // writes its register directly and is waited for only in finish()
