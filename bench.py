@@ -328,8 +328,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU; multi-GPU sharding of the chunk chain is "
-              "described in DESIGN.md but not implemented", file=sys.stderr)
+        print("bench.py: runs on one GPU only; the chunk chain is not sharded over several GPUs",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
