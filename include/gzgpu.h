@@ -159,10 +159,13 @@ int gz_result_get(gz_plan_t plan, int file, gz_result *res);
 
 /* Per-chunk state after the stream completes (host copies, arrays of the
  * file's n_chunks entries): accepted start bit (UINT64_MAX: empty chunk),
- * scan candidate, end bit, symbol count |D_i|, output offset, status (GZ_*)
- * and flags (1 final block reached, 2 empty, 4 extended, 8 repaired,
- * 16 capacity overflow).  Any pointer may be NULL.  Used by tests to check
- * each pass against the oracle. */
+ * the start the block-start checks of Appendix A accepted before any repair
+ * (UINT64_MAX: none passed in the chunk's range; the first chunk: the
+ * payload's first bit), end bit, symbol count |D_i|, output offset, status
+ * (GZ_*) and flags (1 final block reached, 2 empty, 4 extended, 8 repaired:
+ * the accepted start was not where the previous chunk stopped and was
+ * replaced by that bit, 16 capacity overflow).  Any pointer may be NULL.
+ * Used by tests to check each pass against the oracle. */
 int gz_chunk_table(gz_plan_t plan, int file, uint64_t *start, uint64_t *cand, uint64_t *end, uint64_t *len,
                    uint64_t *out_off, int32_t *status, uint32_t *flags);
 

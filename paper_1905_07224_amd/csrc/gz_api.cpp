@@ -881,7 +881,7 @@ int gz_chunk_table(gz_plan_t p, int file, uint64_t *start, uint64_t *cand, uint6
   for (uint32_t i = 0; i < fd.n_chunks; i++) {
     const ChunkState &s = p->cst[fd.first_chunk + i];
     if (start) start[i] = s.start;
-    if (cand) cand[i] = s.cand;
+    if (cand) cand[i] = s.found;
     if (end) end[i] = s.end;
     if (len) len[i] = s.len;
     if (out_off) out_off[i] = s.out_off;

@@ -101,6 +101,7 @@ struct ChunkDesc {
 struct ChunkState {
   uint64_t cand;           // smallest start passing the static checks (scan), NONE if none
   uint64_t start;          // accepted start bit, NONE if the chunk is empty
+  uint64_t found;          // start the block-start checks accepted, before any repair (NONE: none)
   uint64_t end;            // bit where decoding stopped (a block start, or the end of the final block)
   uint64_t len;            // symbols produced up to the stop
   uint64_t out_off;        // output offset

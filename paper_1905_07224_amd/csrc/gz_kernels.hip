@@ -626,6 +626,7 @@ __device__ __forceinline__ void inflate_chunk(InflateLDS<WIN> &sh, const FileDes
     if (b == NONE || (!first && b >= cd.hi_bit)) {
       if (lane == 0) {
         cs[c].start = NONE;
+        cs[c].found = NONE;
         cs[c].end = NONE;
         cs[c].len = 0;
         cs[c].flags = CS_EMPTY;
@@ -641,6 +642,7 @@ __device__ __forceinline__ void inflate_chunk(InflateLDS<WIN> &sh, const FileDes
     if (r.status != D_OK && (first || r.blocks >= 6u)) {
       if (lane == 0) {
         cs[c].start = b;
+        cs[c].found = b;
         cs[c].end = r.end;
         cs[c].len = r.len;
         cs[c].status = ST_DATA;
@@ -655,6 +657,7 @@ __device__ __forceinline__ void inflate_chunk(InflateLDS<WIN> &sh, const FileDes
       bool overflow = inf.over && r.len > cd.sym_cap;
       if (lane == 0) {
         cs[c].start = b;
+        cs[c].found = b;
         cs[c].end = r.end;
         cs[c].len = r.len;
         cs[c].status = overflow ? ST_CAPACITY : ST_OK;
@@ -684,6 +687,7 @@ __global__ void k_init(ChunkState *cs, uint32_t n_chunks, FileState *fs, uint32_
     ChunkState z;
     z.cand = NONE;
     z.start = NONE;
+    z.found = NONE;
     z.end = NONE;
     z.len = 0;
     z.out_off = 0;
@@ -1130,10 +1134,15 @@ __global__ __launch_bounds__(256) void k_finalize(const FileDesc *files, const C
         uint32_t nx;
         uint64_t stop = uni64(next_start(fd, cs, j, true, &nx));
         if (cur >= stop) {
+          // the previous chunk already decoded through this one's range:
+          // nothing of its own decode from the false start is kept
           if (tid == 0) {
             cs[j].start = cur;
             cs[j].end = cur;
             cs[j].len = 0;
+            cs[j].n_blocks = 0;
+            cs[j].n_syms = 0;
+            cs[j].n_placeholders = 0;
             cs[j].flags = CS_REPAIRED;
             cs[j].status = ST_OK;
           }

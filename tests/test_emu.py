@@ -443,3 +443,43 @@ def test_emu_bgzf_batch(orc):
     bad[len(comps[0]) + len(comps[1]) - 8] ^= 1
     st, out, sts = E.bgzf_run(bytes(bad), chunk_bytes=8192)
     assert st == 0 and sts[1] == -6 and sts[0] == 0 and all(x == 0 for x in sts[2:])
+
+
+@pytest.mark.parametrize("final_last,n", [(True, 2), (True, 4), (True, 9), (False, 4), (False, 12)])
+def test_emu_false_starts_repaired(orc, final_last, n):
+    """Chunk starts that pass Appendix A's checks inside a stored block
+    (tests/decoy.py) are replaced by where the previous chunk stopped, as the
+    oracle does: same starts before and after the repair, ends, lengths,
+    offsets, repair count and bytes."""
+    import decoy
+
+    gz, raw, real_bits, decoy_bits = decoy.decoy_member(final_last=final_last)
+    ref = orc.pugz(gz, n)
+    assert ref.status == orc.OK and ref.n_repairs >= 1
+    st, out, r, tab = E.run(gz, n, out_cap=len(raw) + 64, sync_limit=3_000_000_000)
+    assert st == 0 and out == raw == ref.out.tobytes()
+    found = np.array([-1 if int(s) == NONE else int(s) for s in tab["cand"]], dtype=np.int64)
+    assert np.array_equal(found, ref.cand), (list(found), list(ref.cand))
+    assert np.array_equal(_starts(tab), ref.start)
+    ne = ref.start >= 0
+    for k in ("end", "len", "out_off"):
+        assert np.array_equal(tab[k][ne].astype(np.int64), getattr(ref, "off" if k == "out_off" else k)[ne]), k
+    assert r.n_repairs == ref.n_repairs
+    assert r.n_placeholders == int(ref.placeholders.sum())
+    repaired = (tab["flags"] & 8) != 0
+    assert np.array_equal(np.nonzero(repaired)[0], np.nonzero((ref.cand != ref.start) & ne)[0])
+    assert set(found[repaired].tolist()) <= set(decoy_bits)
+
+
+def test_emu_too_far_across_chunks(orc):
+    """A match reaching before the data start: a data error whether the chunk
+    holding it has an empty context (one chunk) or a placeholder context
+    (found by the translation, as in the oracle)."""
+    import decoy
+
+    gz, bad_bit, bits = decoy.too_far_member()
+    for n in (1, 3, 6):
+        ref = orc.pugz(gz, n)
+        assert ref.status == orc.E_DATA
+        st, out, r, tab = E.run(gz, n, out_cap=64 << 10, sync_limit=3_000_000_000)
+        assert st == -4, (n, st)

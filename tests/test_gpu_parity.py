@@ -290,3 +290,54 @@ def test_device_crc32_batch_and_mismatch(orc):
         plan = gz.Plan(_dev(b), 2)
         plan.launch(torch.empty(2 * len(raws[1]) + 64, dtype=torch.uint8, device="cuda:0"))
         assert plan.result().status == want
+
+
+# ---------------------------------------------------------------- false block starts (tests/decoy.py)
+
+@pytest.mark.parametrize("final_last", [True, False], ids=["inner-final", "inner-nonfinal"])
+def test_false_starts_repaired(orc, final_last):
+    """Starts that pass Appendix A's checks inside a stored block are caught
+    by the stitch check and the chunk is decoded again from where its
+    predecessor stopped: device starts before and after the repair, ends,
+    lengths, offsets, repair counts and bytes equal the oracle's at every
+    chunk count from 2 to 15, with the default and the direct confirmation."""
+    import decoy
+
+    gz, raw, real_bits, decoy_bits = decoy.decoy_member(final_last=final_last)
+    total = 0
+    for n in range(2, 16):
+        ref = orc.pugz(gz, n)
+        assert ref.status == orc.OK and ref.out.tobytes() == raw
+        for cd in (0, 1):
+            _say("decoy final_last", final_last, "chunks", n, "confirm_decode", cd)
+            got, plan = _run(gz, n, confirm_decode=cd)
+            assert got == raw
+            tab = plan.chunk_table()
+            found = np.array([-1 if int(s) == _gz().NONE else int(s) for s in tab["cand"]], dtype=np.int64)
+            assert np.array_equal(found, ref.cand), (n, list(found), list(ref.cand))
+            assert np.array_equal(_starts(tab), ref.start), (n, list(_starts(tab)), list(ref.start))
+            ne = ref.start >= 0
+            assert np.array_equal(tab["end"][ne].astype(np.int64), ref.end[ne])
+            assert np.array_equal(tab["len"][ne].astype(np.int64), ref.len[ne])
+            assert np.array_equal(tab["out_off"][ne].astype(np.int64), ref.off[ne])
+            r = plan.result()
+            assert r.n_repairs == ref.n_repairs >= 1
+            assert r.n_placeholders == int(ref.placeholders.sum())
+            total += r.n_repairs
+    assert total >= 50
+
+
+def test_too_far_across_chunks(orc):
+    """A match reaching before the data start inside chunk 0 (empty context)
+    or a later chunk (found by the translation): GZ_E_DATA, as the oracle."""
+    import decoy
+
+    gz, bad_bit, bits = decoy.too_far_member()
+    for n in range(1, 9):
+        _say("too-far member, chunks", n)
+        ref = orc.pugz(gz, n)
+        assert ref.status == orc.E_DATA
+        plan = _gz().Plan(_dev(gz), n)
+        with pytest.raises(_gz().GzError) as ei:
+            plan.run()
+        assert ei.value.code == -4

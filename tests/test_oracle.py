@@ -646,3 +646,83 @@ def test_predicate_rules_on_handbuilt(orc):
     dynamic_block(bw, toks[:100], True)
     ok, why = orc.block_predicate(bw.getvalue(), 0)
     assert ok, why
+
+
+# ---------------------------------------------------------------- false block starts and repair
+
+@pytest.fixture(scope="module", params=[True, False], ids=["inner-final", "inner-nonfinal"])
+def decoy_case(request):
+    import decoy
+
+    return decoy.decoy_member(final_last=request.param)
+
+
+def test_decoy_is_a_false_positive(orc, decoy_case):
+    """The inner stream's block starts pass Appendix A's checks although they
+    lie inside a stored block of the real chain (Section VI-A's false
+    positives); the real chain is the encoder's."""
+    gz, raw, real_bits, decoy_bits = decoy_case
+    g = orc.gunzip(gz)
+    assert g.status == orc.OK and g.out.tobytes() == raw
+    assert g.block_bit.tolist() == real_bits  # the sequential decoder follows the encoder's chain
+    assert not set(decoy_bits) & set(real_bits)
+    # each stored block holds 40 inner blocks; all but the last six have a
+    # non-final trial block and five more blocks inside the stored payload
+    for g0 in range(0, len(decoy_bits), 40):
+        for b in decoy_bits[g0:g0 + 34]:
+            ok, why = orc.block_predicate(gz, b)
+            assert ok, (b, why)
+
+
+@pytest.mark.parametrize("n_chunks", [2, 3, 4, 6, 9, 13])
+def test_pugz_repairs_false_starts(orc, decoy_case, n_chunks):
+    """Every false start the search accepts is replaced by the bit where the
+    previous chunk stopped; the output stays the encoder's text (the
+    exactness argument of the stitch check: by induction from the first
+    chunk, every start that is kept is on the real chain)."""
+    gz, raw, real_bits, decoy_bits = decoy_case
+    p = orc.pugz(gz, n_chunks)
+    assert p.status == orc.OK, p.reason
+    assert p.out.tobytes() == raw
+    assert p.n_repairs >= 1
+    repaired = [i for i in range(n_chunks) if p.cand[i] >= 0 and p.cand[i] != p.start[i] and p.start[i] >= 0]
+    assert len(repaired) == p.n_repairs
+    real, dec = set(real_bits), set(decoy_bits)
+    for i in repaired:
+        assert int(p.cand[i]) in dec and int(p.start[i]) in real
+        assert p.start[i] == p.end[i - 1 - int(np.argmax(p.start[:i][::-1] >= 0))]
+    assert all(int(s) in real for s in p.start[p.start >= 0])
+    assert int(p.len.sum()) == len(raw)
+
+
+def test_pugz_too_far_found_by_translation(orc):
+    """A match reaching before the data start, inside a chunk other than the
+    first: pass 1 decodes it as a placeholder (the chunk's context is
+    unknown), and the translation finds the placeholder outside the real
+    history.  The sequential decoder reports the same error."""
+    import decoy
+
+    gz, bad_bit, bits = decoy.too_far_member()
+    g = orc.gunzip(gz)
+    assert g.status == orc.E_DATA and g.reason == "TOO_FAR"
+    seen = 0
+    for n in range(2, 9):
+        p = orc.pugz(gz, n)
+        assert p.status == orc.E_DATA and p.reason == "TOO_FAR", (n, p.reason)
+        ne = np.nonzero(p.start >= 0)[0]
+        i = int(ne[np.searchsorted(p.start[ne], bad_bit, side="right") - 1])
+        if i == 0:
+            continue
+        seen += 1
+        # pass 1 of that chunk alone succeeds; the bad reference is a placeholder
+        nxt = [int(p.start[j]) for j in ne if j > i]
+        s = orc.symbolic(gz, int(p.start[i]), nxt[0] if nxt else 1 << 62, first=False)
+        assert s.status == orc.OK
+        ph = s.sym[s.sym >= 0x8000] & 0x7FFF
+        # the windows and offsets were resolved before the translation failed
+        assert int(p.valid[i]) == min(int(p.off[i]), 32768) < 20000
+        assert ph.size and int(ph.min()) < 32768 - int(p.valid[i])
+    assert seen >= 4
+    # the whole member as one chunk: the first chunk has an empty context
+    p = orc.pugz(gz, 1)
+    assert p.status == orc.E_DATA and p.reason == "TOO_FAR"
