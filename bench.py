@@ -18,6 +18,8 @@ import sys
 import time
 import zlib
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -28,33 +30,300 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(sample_mib: int, chunk_bytes: int):
-    """The CPU oracle's two-pass decompression (single-threaded: block-start
-    search, symbolic pass, window propagation, translation, all bit-serial) on
-    a bounded sample of the same generator, cut into chunks of the same
-    compressed size, in decompressed GB/s."""
-    import oracle
-    import synth
+CLOCK_GHZ = 2.4  # MI355X engine clock used for wave-cycle figures
 
-    raw, gz = synth.make("fastq", sample_mib << 20, 2, 6, read_lens=(100, 150))
-    n = max(1, (len(gz) + chunk_bytes - 1) // chunk_bytes)
+
+def host_info():
+    """CPU model and core counts of the host running the oracle."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count(), "affinity_cores": len(os.sched_getaffinity(0))}
+
+
+def _pinned(core, fn):
+    """fn() with the calling thread pinned to one core (sched_setaffinity of
+    the thread, as taskset does for a process)."""
+    old = os.sched_getaffinity(0)
+    os.sched_setaffinity(0, {core})
+    try:
+        return fn()
+    finally:
+        os.sched_setaffinity(0, old)
+
+
+def cpu_baseline(comp: bytes, n_raw: int, crc_ref: int, workload: str):
+    """The oracle's sequential gunzip (plain bit-serial RFC 1951/1952 inflate)
+    of the benchmark's member, on one host core, in decompressed GB/s."""
+    import oracle
+
     oracle.lib()
-    t0 = time.perf_counter()
-    r = oracle.pugz(gz, n)
-    dt = time.perf_counter() - t0
-    ok = r.status == 0 and r.out.tobytes() == raw
+    core = max(os.sched_getaffinity(0))
+    a = np.frombuffer(comp, dtype=np.uint8)
+
+    def run():
+        t0 = time.perf_counter()
+        g = oracle.gunzip(a)
+        return g, time.perf_counter() - t0
+
+    g, dt = _pinned(core, run)
+    ok = g.status == 0 and g.out.size == n_raw and (zlib.crc32(g.out) & 0xFFFFFFFF) == crc_ref
+    del g
+    h = host_info()
     return {
-        "value": round(len(raw) / dt / 1e9, 6),
+        "value": round(n_raw / dt / 1e9, 6),
         "unit": "GB/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": f"{len(raw)} bytes of FASTQ-like text (same generator, 100/150 bp), gzip -6, {n} chunks of "
-                  f"{chunk_bytes} compressed bytes; two-pass CPU oracle on one host core, {dt:.1f} s, "
-                  f"bytes equal to the source: {ok}",
+        "sample": f"the whole {workload} member ({n_raw} bytes, {len(comp)} compressed): the oracle's sequential "
+                  f"gunzip on one host core (thread pinned to core {core}), {dt:.1f} s, "
+                  f"{len(comp) / dt / 1e6:.1f} MB/s compressed, output equal to the source: {ok}",
+        "seconds": round(dt, 3),
+        "cpu_model": h["cpu_model"],
+        "nproc": h["nproc"],
+        "affinity_cores": h["affinity_cores"],
     }
 
 
-def batched_vs_plain(n_files: int, reps: int):
+def oracle_aggregate(comps, n_raw_total: int):
+    """The oracle's gunzip over a set of files with one pinned thread per host
+    core (at most 16), files taken from a shared queue; aggregate decompressed
+    GB/s.  The oracle runs outside the interpreter lock."""
+    import queue
+    import threading
+
+    import oracle
+
+    oracle.lib()
+    cores = sorted(os.sched_getaffinity(0))[:16]
+    q = queue.Queue()
+    for c in comps:
+        q.put(np.frombuffer(c, dtype=np.uint8))
+    bad = []
+
+    def worker(core):
+        def loop():
+            while True:
+                try:
+                    a = q.get_nowait()
+                except queue.Empty:
+                    return
+                g = oracle.gunzip(a)
+                if g.status != 0:
+                    bad.append(g.status)
+        _pinned(core, loop)
+
+    th = [threading.Thread(target=worker, args=(c,)) for c in cores]
+    t0 = time.perf_counter()
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    dt = time.perf_counter() - t0
+    return {"GBps": round(n_raw_total / dt / 1e9, 4), "cores": len(cores), "seconds": round(dt, 3),
+            "files": len(comps), "all_ok": not bad}
+
+
+def copy_ceiling(dev, mib: int = 2048, reps: int = 5):
+    """Device-to-device copy of `mib` MiB (read + write bytes / time): the
+    HBM bandwidth a plain streaming kernel reaches on this GPU."""
+    import statistics
+
+    import torch
+
+    n = mib << 18
+    src = torch.ones(n, dtype=torch.int32, device=dev)
+    dst = torch.empty_like(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ms = []
+    for _ in range(reps + 1):
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    t = statistics.median(ms[1:])
+    del src, dst
+    return round(2 * 4 * n / t / 1e6, 1)
+
+
+def path_bytes_per_out(ratio: float) -> float:
+    """Algorithmic HBM bytes per decompressed byte of the whole path: the
+    compressed input once, 16-bit symbols written and read, the output
+    written (1/R + 5); the 96 KiB of windows per chunk come on top."""
+    return 1.0 / ratio + 5.0
+
+
+def fractions(gbps: float, ratio: float, copy_gbps):
+    b = path_bytes_per_out(ratio)
+    return {"hbm_frac": round(gbps * b / HBM_PEAK_GBS, 5),
+            "copy_frac": round(gbps * b / copy_gbps, 5) if copy_gbps else None}
+
+
+def timed_plan(gz, plan, out, steps: int, raw_dev=None):
+    """Warm up once (output compared with raw_dev when given), then time
+    `steps` launches; returns (seconds per step, last result, mean pass times)."""
+    import torch
+
+    stream = torch.cuda.current_stream()
+    plan.launch(out, stream)
+    r = plan.result()
+    if r.status != 0:
+        raise SystemExit(f"decompression failed: status {r.status}")
+    if raw_dev is not None and not (r.out_len == raw_dev.numel() and torch.equal(out[: r.out_len], raw_dev)):
+        raise SystemExit("output differs from the source text")
+    passes = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.launch(out, stream)
+        r = plan.result()
+        if r.status != 0:
+            raise SystemExit(f"decompression failed: status {r.status}")
+        if plan.opts.timing:
+            passes.append(plan.pass_times())
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    avg = {k: sum(p[k] for p in passes) / len(passes) for k in passes[0]} if passes else {}
+    return dt, r, avg
+
+
+def large_leg(gz, name: str, steps: int, copy_gbps, chunk_sweep=()):
+    """One of the large configurations (the level sweep's 4 GiB FASTQ-like
+    members, the 2 GiB word stream): decompressed GB/s in the benchmark's
+    launch configuration, HBM fractions, per-chunk placeholder fractions
+    (Section IV-C's undetermined context, per chunk), the window
+    propagation's time and bytes, and the block-start search's stage counts.
+    Returns (result dict, raw, comp, segment bits)."""
+    import torch
+
+    t = time.perf_counter()
+    raw, comp, seg = synth_workload(name)
+    gen_s = time.perf_counter() - t
+    dev = torch.device("cuda:0")
+    d_comp = torch.frombuffer(bytearray(comp), dtype=torch.uint8).to(dev)
+    d_raw = torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(dev)
+    out = torch.empty(len(raw), dtype=torch.uint8, device=dev)
+    plan = gz.Plan(d_comp, 0, timing=1)
+    dt, r, avg = timed_plan(gz, plan, out, steps, d_raw)
+    ratio = len(raw) / len(comp)
+    gbps = len(raw) / dt / 1e9
+    tab = plan.chunk_table()
+    st = plan.chunk_stats()
+    ne = tab["start"] != np.uint64(gz.NONE)
+    L = tab["len"][ne].astype(np.float64)
+    ph = st["n_placeholders"][ne].astype(np.float64)
+    frac = ph[1:] / np.maximum(L[1:], 1.0)  # chunk 0 has no unknown context
+    n_acc = int(ne.sum())
+    res = {
+        "workload": name,
+        "uncompressed_bytes": len(raw),
+        "compressed_bytes": len(comp),
+        "ratio": round(ratio, 4),
+        "generate_s": round(gen_s, 1),
+        "n_chunks": plan.n_chunks,
+        "chunks_with_start": n_acc,
+        "steps": steps,
+        "ms_per_step": round(dt * 1e3, 3),
+        "GBps": round(gbps, 3),
+        **fractions(gbps, ratio, copy_gbps),
+        "passes_ms": {k: round(v, 4) for k, v in avg.items()},
+        "placeholder_frac": {
+            "all_symbols": round(float(ph.sum() / max(L.sum(), 1.0)), 5),
+            "chunk_mean": round(float(frac.mean()), 5) if frac.size else None,
+            "chunk_p10": round(float(np.percentile(frac, 10)), 5) if frac.size else None,
+            "chunk_p50": round(float(np.percentile(frac, 50)), 5) if frac.size else None,
+            "chunk_p90": round(float(np.percentile(frac, 90)), 5) if frac.size else None,
+            "chunk_max": round(float(frac.max()), 5) if frac.size else None,
+        },
+        "propagate": {"us": round(avg.get("propagate", 0.0) * 1e3, 1),
+                      "algorithmic_bytes": n_acc * 3 * 32768,
+                      "note": "per accepted chunk: 32768 16-bit tail symbols read, a 32 KiB window written"},
+        "search": {k: int(st[k].sum()) for k in ("stage1", "stage2", "trial_rej", "confirm_rej")},
+        "stats": {k: int(getattr(r, k)) for k in ("n_repairs", "n_retries", "n_extended", "n_syms",
+                                                   "n_placeholders", "n_blocks")},
+        "bit_exact": True,
+    }
+    for cb in chunk_sweep:
+        p2 = gz.Plan(d_comp, 0, chunk_bytes=cb)
+        dt2, r2, _ = timed_plan(gz, p2, out, 2, d_raw)
+        res.setdefault("chunk_sweep", []).append({"chunk_bytes": cb, "n_chunks": p2.n_chunks,
+                                                  "GBps": round(len(raw) / dt2 / 1e9, 3)})
+        del p2
+    del plan, d_raw, out, d_comp
+    torch.cuda.empty_cache()
+    return res, raw, comp, seg, tab, st
+
+
+def synth_workload(name):
+    import synth
+
+    return synth.workload(name, index=True)
+
+
+def _segment_blocks(job):
+    import oracle
+
+    comp_arr, a, b, first = job
+    s = oracle.symbolic(comp_arr, a, b, first=first)
+    if s.status != 0:
+        raise SystemExit(f"oracle: segment at bit {a} failed ({s.reason})")
+    return s.block_bits
+
+
+def oracle_block_map(comp: bytes, seg_bits):
+    """The member's block map from the oracle's pass 1 over each of the
+    encoder's compression segments (each begins at a block boundary), run on
+    host threads in parallel."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import oracle
+
+    oracle.lib()
+    a = np.frombuffer(comp, dtype=np.uint8)
+    stops = list(seg_bits[1:]) + [1 << 62]
+    jobs = [(a, int(s), int(e), k == 0) for k, (s, e) in enumerate(zip(seg_bits, stops))]
+    with ThreadPoolExecutor(max_workers=min(16, len(os.sched_getaffinity(0)), len(jobs))) as ex:
+        parts = list(ex.map(_segment_blocks, jobs))
+    return np.concatenate(parts)
+
+
+def false_positives(tab, st, blocks, gz):
+    """Block-start candidates against the oracle's block map, per chunk:
+    the smallest bit passing the static checks, and the start accepted after
+    the trial and confirmation blocks."""
+    bm = np.asarray(blocks, dtype=np.int64)
+
+    def on_map(x):
+        x = x.astype(np.int64)
+        i = np.searchsorted(bm, x)
+        return (i < bm.size) & (bm[np.minimum(i, bm.size - 1)] == x)
+
+    none = np.uint64(gz.NONE)
+    sc = st["scan_cand"]
+    has_sc = sc != none
+    fd = tab["cand"]
+    has_fd = fd != none
+    n = sc.size
+    sc_fp = int((has_sc & ~on_map(np.where(has_sc, sc, 0))).sum())
+    fd_fp = int((has_fd & ~on_map(np.where(has_fd, fd, 0))).sum())
+    return {"chunks": int(n), "static_candidates": int(has_sc.sum()), "static_false": sc_fp,
+            "accepted": int(has_fd.sum()), "accepted_false": fd_fp,
+            "stage1_per_chunk_mean": round(float(st["stage1"].mean()), 3),
+            "stage1_per_chunk_max": int(st["stage1"].max()),
+            "stage2_per_chunk_mean": round(float(st["stage2"].mean()), 3),
+            "trial_rej_per_chunk_max": int(st["trial_rej"].max()),
+            "confirm_rej_per_chunk_max": int(st["confirm_rej"].max()),
+            "block_map_blocks": int(bm.size)}
+
+
+def batched_vs_plain(n_files: int, reps: int, copy_gbps=None):
     """Decompressed GB/s of n_files C1-like files (4 MiB FASTQ-like, gzip -6,
     seeds 1..n_files): back-to-back one-file launches on one stream (plain),
     one batched launch sequence (batched), and the batched sequence replayed
@@ -111,10 +380,18 @@ def batched_vs_plain(n_files: int, reps: int):
     ok_batch = all(bp.result(i).status == 0 for i in range(n_files)) and exact()
     ms_graph = timed(lambda: bp.launch_graph(s))
     ok_graph = all(bp.result(i).status == 0 for i in range(n_files)) and exact()
+    comp_total = sum(c.numel() for c in comps)
+    ratio = total / comp_total
+    host_comps = [c.cpu().numpy().tobytes() for c in comps]
+    agg = oracle_aggregate(host_comps, total)
     return {
         "files": n_files,
         "uncompressed_bytes": total,
-        "compressed_bytes": sum(c.numel() for c in comps),
+        "compressed_bytes": comp_total,
+        "plain_fractions": fractions(total / ms_plain / 1e6, ratio, copy_gbps),
+        "batched_fractions": fractions(total / ms_batch / 1e6, ratio, copy_gbps),
+        "graph_fractions": fractions(total / ms_graph / 1e6, ratio, copy_gbps),
+        "oracle_parallel": agg,
         "reps": reps,
         "plain_GBps": round(total / ms_plain / 1e6, 4),
         "batched_GBps": round(total / ms_batch / 1e6, 4),
@@ -305,6 +582,9 @@ def recorded_traffic(kernel: str, workload: str, chunk_bytes: int, window: int):
     return int(kv["traffic_bytes"]) if same else None
 
 
+LEGS = ("c2_1mib", "c3", "c4", "stream", "bgzf", "batched", "serving", "cpu")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -314,15 +594,14 @@ def main():
     ap.add_argument("--chunk-bytes", type=int, default=0, help="compressed bytes per chunk (0: library default)")
     ap.add_argument("--waves-per-chunk", type=int, default=1)
     ap.add_argument("--window", type=int, default=0, help="LDS history ring per decoding wave (0: library default)")
-    ap.add_argument("--cpu-sample-mib", type=int, default=256)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--batch-files", type=int, default=32, help="files of the batched-vs-plain set (0: skip)")
-    ap.add_argument("--serve-jobs", type=int, default=400, help="jobs of the serving run (0: skip)")
+    ap.add_argument("--legs", default=",".join(LEGS),
+                    help="legs beside the timed plain run: " + ",".join(LEGS) + " (empty: none)")
+    ap.add_argument("--large-steps", type=int, default=3, help="timed steps of the level-sweep and word legs")
+    ap.add_argument("--batch-files", type=int, default=32, help="files of the batched-vs-plain set")
+    ap.add_argument("--serve-jobs", type=int, default=400, help="jobs of the serving run")
     ap.add_argument("--serve-load", type=float, default=0.7, help="offered load, fraction of measured capacity")
-    ap.add_argument("--stream-mib", type=int, default=256,
-                    help="bounded-memory streaming leg: compressed MiB per segment (0: skip)")
-    ap.add_argument("--bgzf-mib", type=int, default=256,
-                    help="BGZF leg: MiB of FASTQ-like text as 64 KiB members, decoded as one batch (0: skip)")
+    ap.add_argument("--stream-mib", type=int, default=256, help="streaming leg: compressed MiB per segment")
+    ap.add_argument("--bgzf-mib", type=int, default=256, help="BGZF leg: MiB of FASTQ-like text in 64 KiB members")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after warmup, one device-to-device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -331,6 +610,10 @@ def main():
         print("bench.py: runs on one GPU only; the chunk chain is not sharded over several GPUs",
               file=sys.stderr)
         sys.exit(2)
+    legs = set(x for x in args.legs.split(",") if x)
+    unknown = legs - set(LEGS)
+    if unknown:
+        raise SystemExit(f"unknown legs: {sorted(unknown)}")
 
     import torch
 
@@ -343,6 +626,7 @@ def main():
     log(f"input ready: {len(raw)} bytes raw, {len(comp)} compressed (ratio {len(raw) / len(comp):.3f}) "
         f"in {time.perf_counter() - t:.1f} s")
     crc_ref = zlib.crc32(raw) & 0xFFFFFFFF
+    ratio = len(raw) / len(comp)
 
     dev = torch.device("cuda:0")
     d_comp = torch.frombuffer(bytearray(comp), dtype=torch.uint8).to(dev)
@@ -422,40 +706,83 @@ def main():
         "algorithmic_bytes": inflate_bytes,
         "avg_ms": round(inflate_ms, 4),
     }
+    # the decoder's serial chain: codes and output symbols per wave-cycle
+    waves = int(stats["inflate_waves"])
+    wave_cycles = inflate_ms * 1e-3 * CLOCK_GHZ * 1e9 * waves
+    decoder = {
+        "inflate_waves": waves,
+        "codes": int(stats["n_syms"]),
+        "codes_per_wave_cycle": round(stats["n_syms"] / wave_cycles, 5),
+        "out_symbols_per_wave_cycle": round(len(raw) / wave_cycles, 5),
+        "note": "wave-cycles = inflate time x 2.4 GHz x decoding waves of the persistent grid",
+    }
+    copy_gbps = copy_ceiling(dev)
+    log(f"copy ceiling: {copy_gbps} GB/s")
+    path = {"bytes_per_out_byte": round(path_bytes_per_out(ratio), 4), "copy_ceiling_GBps": copy_gbps,
+            **fractions(value, ratio, copy_gbps)}
+
+    extra = {}
+    if "c2_1mib" in legs:
+        p1 = gz.Plan(d_comp, 0, chunk_bytes=1 << 20)
+        dt1, _, _ = timed_plan(gz, p1, out, 3)
+        extra["c2_1MiB_chunks"] = {"chunk_bytes": 1 << 20, "n_chunks": p1.n_chunks,
+                                   "GBps": round(len(raw) / dt1 / 1e9, 3), **fractions(len(raw) / dt1 / 1e9, ratio,
+                                                                                       copy_gbps)}
+        log(f"C2 at 1 MiB chunks: {extra['c2_1MiB_chunks']}")
+        del p1
 
     streamed = None
-    if args.stream_mib:
+    if "stream" in legs:
         whole_bytes = plan.info.ws_bytes + out.numel()
         log(f"streaming: {args.stream_mib} MiB segments")
         streamed = streaming(gz, d_comp, args.stream_mib << 20, len(raw), crc_ref, whole_bytes)
         log(f"streaming: {streamed}")
+    del plan, out, d_comp
+    torch.cuda.empty_cache()
+
+    if "c3" in legs:
+        for name in ("fastq_4GiB_L1", "fastq_4GiB_L9"):
+            log(f"level sweep: {name}")
+            res, *_ = large_leg(gz, name, args.large_steps, copy_gbps, chunk_sweep=(256 << 10, 1 << 20, 4 << 20))
+            extra[name] = res
+            log(f"{name}: {res}")
+    if "c4" in legs:
+        name = "words_2GiB_L6"
+        log(f"word stream: {name}")
+        res, raw4, comp4, seg4, tab4, st4 = large_leg(gz, name, args.large_steps, copy_gbps)
+        t = time.perf_counter()
+        bm = oracle_block_map(comp4, seg4)
+        res["false_positives"] = false_positives(tab4, st4, bm, gz)
+        res["false_positives"]["oracle_block_map_s"] = round(time.perf_counter() - t, 1)
+        extra[name] = res
+        log(f"{name}: {res}")
+        del raw4, comp4
 
     bgzf = None
-    if args.bgzf_mib:
+    if "bgzf" in legs:
         log(f"bgzf: {args.bgzf_mib} MiB in 64 KiB members")
         bgzf = bgzf_leg(gz, args.bgzf_mib)
         log(f"bgzf: {bgzf}")
 
     batched = None
-    if args.batch_files:
-        del plan, out
+    if "batched" in legs:
         torch.cuda.empty_cache()
         log(f"batched vs plain: {args.batch_files} C1-like files")
-        batched = batched_vs_plain(args.batch_files, 5)
+        batched = batched_vs_plain(args.batch_files, 5, copy_gbps)
         log(f"batched vs plain: {batched}")
 
     served = None
-    if args.serve_jobs:
+    if "serving" in legs:
         torch.cuda.empty_cache()
         log(f"serving: {args.serve_jobs} jobs at load {args.serve_load}")
         served = serving(args.serve_jobs, args.serve_load, 96)
         log(f"serving: {served}")
 
     cpu = None
-    if not args.no_cpu_baseline:
-        log(f"cpu baseline: oracle on a {args.cpu_sample_mib} MiB sample")
-        cpu = cpu_baseline(args.cpu_sample_mib, chunk_bytes)
-        log(f"cpu baseline: {cpu['value']} GB/s")
+    if "cpu" in legs:
+        log("cpu baseline: the oracle's gunzip of the whole member on one core")
+        cpu = cpu_baseline(comp, len(raw), crc_ref, args.workload)
+        log(f"cpu baseline: {cpu}")
 
     line = {
         "metric": "decompressed GB/s on 1 MI355X (batched vs plain) + p50/p99 job latency; bit-exact",
@@ -475,7 +802,10 @@ def main():
             "path": "plain",
             "uncompressed_bytes": len(raw),
             "compressed_bytes": len(comp),
-            "ratio": round(len(raw) / len(comp), 4),
+            "ratio": round(ratio, 4),
+            "compression": "zlib level 6, one member; above 64 MiB of text it is compressed as 64 MiB "
+                           "segments, each primed with the previous 32 KiB and ended by a sync flush "
+                           "(pigz-style, still one member)",
             "chunk_bytes": chunk_bytes,
             "waves_per_chunk": args.waves_per_chunk,
             "n_chunks": n_chunks,
@@ -486,11 +816,15 @@ def main():
         "stats": {k: stats[k] for k in ("n_nonempty", "n_repairs", "n_extended", "n_retries", "n_syms",
                                          "n_placeholders", "n_blocks")},
         "roofline": roofline,
+        "path": path,
+        "decoder": decoder,
+        "configs": extra,
         "streaming": streamed,
         "bgzf": bgzf,
         "batched_vs_plain": batched,
         "serving": served,
         "cpu_baseline": cpu,
+        "host": host_info(),
         "bit_exact": True,
     }
     print(json.dumps(line), flush=True)

@@ -99,7 +99,7 @@ typedef struct gz_result {
   uint64_t n_placeholders; /* symbols that referenced a chunk's unknown window */
   uint64_t n_blocks;
   uint32_t crc32;          /* CRC-32 of the output, computed on the device (when the decode succeeded) */
-  uint32_t pad;
+  uint32_t inflate_waves;  /* decoding waves of the persistent pass-1 grid (one chunk at a time each) */
 } gz_result;
 
 typedef struct gz_plan_s *gz_plan_t;
@@ -168,6 +168,27 @@ int gz_result_get(gz_plan_t plan, int file, gz_result *res);
  * Used by tests to check each pass against the oracle. */
 int gz_chunk_table(gz_plan_t plan, int file, uint64_t *start, uint64_t *cand, uint64_t *end, uint64_t *len,
                    uint64_t *out_off, int32_t *status, uint32_t *flags);
+
+/* Per-chunk statistics after the stream completes (arrays of the file's
+ * n_chunks entries; any pointer may be NULL):
+ *   n_syms, n_placeholders, n_blocks: Huffman literal/length codes decoded
+ *     (end-of-block included), symbols of D_i that are placeholders U_j, and
+ *     blocks decoded, for the chunk's accepted decode (0 for an empty chunk);
+ *     n_placeholders / |D_i| is the share of the chunk's output that
+ *     depended on the unknown context (Section IV-C, Fig. 2);
+ *   scan_cand: the smallest bit of the chunk's range that passed the static
+ *     checks of the block-start search (UINT64_MAX: none);
+ *   stage1, stage2: candidates that passed the cheap header checks and were
+ *     given the full code-table check, and those that passed it;
+ *   trial_rej, confirm_rej: candidates rejected by the trial block (ASCII
+ *     literals, 1 KiB < size < 4 MiB) and by the five confirmation blocks
+ *     (Appendix A).
+ * The search stops at the first candidate that passes, and several
+ * workgroups search one chunk at once, so the stage counts cover the bits
+ * searched, not the whole range, and may differ between runs. */
+int gz_chunk_stats(gz_plan_t plan, int file, uint64_t *n_syms, uint64_t *n_placeholders, uint32_t *n_blocks,
+                   uint64_t *scan_cand, uint32_t *stage1, uint32_t *stage2, uint32_t *trial_rej,
+                   uint32_t *confirm_rej);
 
 /* Device addresses of a file's per-chunk symbol arrays and windows inside the
  * workspace of the last call (for tests): symbols of chunk c start at

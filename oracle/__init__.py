@@ -56,7 +56,8 @@ class _Gunzip(C.Structure):
 class _Sym(C.Structure):
     _fields_ = [("status", C.c_int), ("reason", C.c_int), ("sym", C.POINTER(C.c_uint16)),
                 ("len", C.c_size_t), ("end_bit", C.c_int64), ("final_reached", C.c_int),
-                ("n_blocks", C.c_int64), ("n_syms", C.c_int64), ("n_placeholders", C.c_int64)]
+                ("n_blocks", C.c_int64), ("n_syms", C.c_int64), ("n_placeholders", C.c_int64),
+                ("block_bits", C.POINTER(C.c_int64))]
 
 
 class _Pugz(C.Structure):
@@ -190,6 +191,7 @@ def symbolic(data, start_bit: int, stop_bit: int, first: bool) -> SymResult:
     o.n_blocks = r.n_blocks
     o.n_syms = r.n_syms
     o.n_placeholders = r.n_placeholders
+    o.block_bits = _arr(r.block_bits, r.n_blocks, np.int64)
     L.orc_sym_free(rp)
     return o
 

@@ -532,9 +532,16 @@ orc_sym_result *orc_symbolic(const uint8_t *in, size_t n, int64_t start_bit, int
   s.first = first;
   bitrd r = {in, n, start_bit, 0};
   int reason = R_OK;
+  size_t bits_cap = 0;
   for (;;) {
     /* stop before the first block that starts at or after the stop bit */
     if (r.pos >= stop_bit) break;
+    /* where each block header begins (RFC 1951 section 3.2.3), as in orc_gunzip's block map */
+    if (grow((void **)&res->block_bits, &bits_cap, (size_t)res->n_blocks + 1, sizeof(int64_t))) {
+      reason = -1;
+      break;
+    }
+    res->block_bits[res->n_blocks] = r.pos;
     int bfinal = 0, btype = 0;
     int64_t nsym = 0;
     int e = inflate_block(&r, &s, &bfinal, &btype, &nsym, 0);
@@ -555,6 +562,7 @@ orc_sym_result *orc_symbolic(const uint8_t *in, size_t n, int64_t start_bit, int
 void orc_sym_free(orc_sym_result *r) {
   if (!r) return;
   free(r->sym);
+  free(r->block_bits);
   free(r);
 }
 

@@ -122,6 +122,7 @@ typedef struct {
   int64_t n_blocks;
   int64_t n_syms;         /* Huffman literal/length symbols, end-of-block included */
   int64_t n_placeholders; /* output symbols >= 0x8000 */
+  int64_t *block_bits;    /* bit offset of every block header decoded, in order (n_blocks entries) */
 } orc_sym_result;
 
 orc_sym_result *orc_symbolic(const uint8_t *in, size_t n, int64_t start_bit, int64_t stop_bit, int first);

@@ -55,7 +55,7 @@ class Result(C.Structure):
                 ("out_needed", C.c_uint64), ("ws_needed", C.c_uint64), ("n_nonempty", C.c_uint32),
                 ("n_repairs", C.c_uint32), ("n_extended", C.c_uint32), ("n_retries", C.c_uint32),
                 ("n_syms", C.c_uint64), ("n_placeholders", C.c_uint64), ("n_blocks", C.c_uint64),
-                ("crc32", C.c_uint32), ("pad", C.c_uint32)]
+                ("crc32", C.c_uint32), ("inflate_waves", C.c_uint32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -117,7 +117,7 @@ EXPORTS = ["gz_plan", "gz_plan_batch", "gz_plan_info", "gz_decompress", "gz_deco
            "gz_server_poll", "gz_server_stats", "gz_server_destroy", "gz_stream_open", "gz_stream_get_info",
            "gz_stream_next", "gz_stream_wait", "gz_stream_checkpoint", "gz_stream_resume", "gz_stream_destroy",
            "gz_plan_probes", "gz_find_blocks", "gz_probe_starts", "gz_stream_open_at", "gz_count_byte",
-           "gz_plan_bgzf"]
+           "gz_plan_bgzf", "gz_chunk_stats"]
 GZ_N_PASSES = N_PASSES = 13
 # defaults of gz_opts (include/gzgpu.h)
 DEFAULT_CHUNK_BYTES = 40 << 10
@@ -140,6 +140,7 @@ def lib():
         L.gz_decompress_batch.argtypes = [vp, vp, C.c_size_t, vp]
         L.gz_result_get.argtypes = [vp, i32, C.POINTER(Result)]
         L.gz_chunk_table.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp]
+        L.gz_chunk_stats.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp]
         L.gz_debug_layout.argtypes = [vp, i32, vp, vp, C.POINTER(vp), C.POINTER(vp)]
         L.gz_plan_destroy.argtypes = [vp]
         L.gz_plan_destroy.restype = None
@@ -296,6 +297,21 @@ class Plan:
         arrs["status"] = st
         arrs["flags"] = fl
         return arrs
+
+    def chunk_stats(self, file: int = 0):
+        """Per-chunk statistics (gz_chunk_stats): codes, placeholders, blocks,
+        the static-check candidate and the block-start search's stage counts."""
+        import numpy as np
+
+        n = self.info.n_chunks
+        a = {k: np.zeros(n, dtype=np.uint64) for k in ("n_syms", "n_placeholders", "scan_cand")}
+        a.update({k: np.zeros(n, dtype=np.uint32) for k in ("n_blocks", "stage1", "stage2", "trial_rej",
+                                                              "confirm_rej")})
+        p = lambda x: C.c_void_p(x.ctypes.data)  # noqa: E731
+        _check(lib().gz_chunk_stats(self._h, file, p(a["n_syms"]), p(a["n_placeholders"]), p(a["n_blocks"]),
+                                    p(a["scan_cand"]), p(a["stage1"]), p(a["stage2"]), p(a["trial_rej"]),
+                                    p(a["confirm_rej"])))
+        return a
 
     def symbols(self, chunk: int, length: int) -> torch.Tensor:
         """The chunk's 16-bit symbols in the workspace (a view; valid until the next launch)."""

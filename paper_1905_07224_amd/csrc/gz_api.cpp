@@ -316,8 +316,11 @@ static int plan_common(gz_plan_t p) {
     // the chunks' capacities are set on the device from their actual spans;
     // their sum is bounded by this
     fd.pool_base = sym_elems;
-    fd.pool_elems = (uint64_t)p->opts.sym_factor * (P + margin + N) + N * (SYM_SLACK + FLUSH_UNIT);
-    p->span.push_back(P + margin + N);
+    // spans to the next candidate (partitioning the payload) plus, at most,
+    // half of every chunk's range (see k_capacity)
+    const uint64_t span_sum = P + margin + N + (P + N) / 2 + N;
+    fd.pool_elems = (uint64_t)p->opts.sym_factor * span_sum + N * (SYM_SLACK + FLUSH_UNIT);
+    p->span.push_back(span_sum);
     sym_elems += align_up(fd.pool_elems, FLUSH_UNIT);
     p->files.push_back(fd);
   }
@@ -862,6 +865,7 @@ int gz_result_get(gz_plan_t p, int file, gz_result *res) {
   res->n_placeholders = s.n_placeholders;
   res->n_blocks = s.n_blocks;
   res->crc32 = s.crc_out;
+  res->inflate_waves = (uint32_t)std::min<uint64_t>(p->chunks.size(), decode_slots(p));
   if (s.overflow) {
     // the workspace of a plan whose symbol factor covers the worst chunk
     r = fetch_chunks(p);
@@ -887,6 +891,28 @@ int gz_chunk_table(gz_plan_t p, int file, uint64_t *start, uint64_t *cand, uint6
     if (out_off) out_off[i] = s.out_off;
     if (status) status[i] = s.status;
     if (flags) flags[i] = s.flags;
+  }
+  return GZ_OK;
+}
+
+int gz_chunk_stats(gz_plan_t p, int file, uint64_t *n_syms, uint64_t *n_placeholders, uint32_t *n_blocks,
+                   uint64_t *scan_cand, uint32_t *stage1, uint32_t *stage2, uint32_t *trial_rej,
+                   uint32_t *confirm_rej) {
+  if (!p || file < 0 || file >= (int)p->files.size()) return GZ_E_ARG;
+  int r = fetch_chunks(p);
+  if (r != GZ_OK) return r;
+  const FileDesc &fd = p->files[file];
+  for (uint32_t i = 0; i < fd.n_chunks; i++) {
+    const ChunkState &s = p->cst[fd.first_chunk + i];
+    const bool ne = s.start != NONE;
+    if (n_syms) n_syms[i] = ne ? s.n_syms : 0;
+    if (n_placeholders) n_placeholders[i] = ne ? s.n_placeholders : 0;
+    if (n_blocks) n_blocks[i] = ne ? s.n_blocks : 0;
+    if (scan_cand) scan_cand[i] = s.cand;
+    if (stage1) stage1[i] = s.stage1;
+    if (stage2) stage2[i] = s.stage2;
+    if (trial_rej) trial_rej[i] = s.trial_rej;
+    if (confirm_rej) confirm_rej[i] = s.confirm_rej;
   }
   return GZ_OK;
 }

@@ -792,7 +792,10 @@ __device__ __forceinline__ bool start_stage2(const Src &s, uint64_t b, TablesLDS
 }
 
 // First candidate in [from, to) that passes the static checks, whole wave.
-__device__ __forceinline__ uint64_t wave_find_start(const Src &s, uint64_t from, uint64_t to, TablesLDS &sh) {
+// *n1 and *n2 (uniform) count the candidates given the table check and the
+// ones that passed it.
+__device__ __forceinline__ uint64_t wave_find_start(const Src &s, uint64_t from, uint64_t to, TablesLDS &sh,
+                                                    uint32_t *n1, uint32_t *n2) {
   const int lane = lane_id();
   for (uint64_t b0 = from; b0 < to; b0 += 64) {
     uint64_t b = b0 + (uint64_t)lane;
@@ -801,7 +804,11 @@ __device__ __forceinline__ uint64_t wave_find_start(const Src &s, uint64_t from,
     while (m) {
       int l = __ffsll((unsigned long long)m) - 1;
       m &= m - 1;
-      if (start_stage2(s, b0 + (uint64_t)l, sh)) return b0 + (uint64_t)l;
+      (*n1)++;
+      if (start_stage2(s, b0 + (uint64_t)l, sh)) {
+        (*n2)++;
+        return b0 + (uint64_t)l;
+      }
     }
   }
   return NONE;

@@ -33,6 +33,7 @@ enum : uint32_t {
   CS_REPAIRED = 8u,     // start replaced by the previous chunk's end
   CS_OVERFLOW = 16u,    // symbol capacity exceeded before the stop
   CS_UNCONFIRMED = 32u, // its deferred confirmation blocks failed (redone by k_redo)
+  CS_CUT = 64u,         // pass 1 outgrew its capacity: symbols stored up to cut_bit only (continued by k_stitch)
 };
 
 // device status codes (same numbers as the public GZ_E_*)
@@ -114,6 +115,18 @@ struct ChunkState {
   uint32_t retries;
   uint32_t valid;          // real history bytes before the chunk, capped at 32768
   uint32_t pad;            // confirmation blocks owed past the stop (deferred), else 0
+  // block-start search statistics (Appendix A's stages), counted where the
+  // search ran (it ends at the first candidate that passes)
+  uint32_t stage1;         // candidates past the cheap header checks, given the full table check
+  uint32_t stage2;         // of those, candidates whose code tables are valid
+  uint32_t trial_rej;      // candidates whose trial block failed (ASCII, size, decoding)
+  uint32_t confirm_rej;    // candidates whose five confirmation blocks failed
+  // CS_CUT: pass 1 outgrew the capacity and stored only the symbols before
+  // cut_bit (a block boundary; len of them, cut_blocks blocks); the stitch
+  // pass continues from there
+  uint64_t cut_bit;
+  uint32_t cut_blocks;
+  uint32_t pad2;
 };
 
 // A chunk with an accepted start, in chunk order (window propagation walks these).

@@ -40,10 +40,15 @@ struct DecodeResult {
   int status;        // D_OK or failure
   bool confirmed;    // the check blocks all passed (or none were asked)
   bool final_seen;
+  bool cut;          // the symbols outgrew the capacity: only those before cut_bit were stored
   uint64_t end;      // stop bit
   uint64_t len;      // symbols up to the stop
   uint32_t blocks;
   uint32_t pending;  // check blocks left for after the stop (deferred confirmation)
+  // with cut: the last block boundary whose symbols all fit, and the symbols,
+  // blocks, codes and (per lane) placeholders before it
+  uint64_t cut_bit, cut_len, cut_syms;
+  uint32_t cut_blocks, cut_nph;
 };
 
 template <int WIN>
@@ -482,23 +487,50 @@ struct Inflater {
   // at the stop and the check blocks still owed are returned in `pending`
   // (the blocks after the stop are the next chunks' first blocks, which
   // those chunks decode with the same checks).
-  __device__ __forceinline__ DecodeResult run(uint64_t start, uint64_t stop, uint32_t check_blocks, bool defer = false) {
+  //
+  // cut_ok: when the symbols outgrow the capacity, the decode goes on to its
+  // stop parsing only (so the checks and the stop are as without the cut),
+  // and the last block boundary whose symbols all fit is reported (res.cut,
+  // cut_*): every symbol before it is stored, and the caller continues from
+  // there once the room is known.
+  __device__ __forceinline__ DecodeResult run(uint64_t start, uint64_t stop, uint32_t check_blocks, bool defer = false,
+                                              bool cut_ok = false) {
     DecodeResult res;
     res.status = D_OK;
     res.confirmed = check_blocks == 0;
     res.final_seen = false;
+    res.cut = false;
     res.end = NONE;
     res.len = 0;
     res.blocks = 0;
     res.pending = 0;
     br.init(start);
     uint32_t nb = 0;
+    // the last block boundary whose symbols fit the capacity (every symbol
+    // below the capacity is stored once the decode has gone past it)
+    res.cut_bit = start;
+    res.cut_len = pos;
+    res.cut_syms = nsyms;
+    res.cut_blocks = 0;
+    res.cut_nph = nph;
     // a block header is at least 3 bits: the remaining bits bound the blocks
     const uint64_t budget = (br.s.end_bits - br.pos) / 3 + 2;
     for (uint64_t it = 0;; it++) {
       if (it > budget) {
         res.status = D_BAD;
         break;
+      }
+      if (!res.cut && res.end == NONE) {
+        if (pos <= cap) {
+          res.cut_bit = br.pos;
+          res.cut_len = pos;
+          res.cut_syms = nsyms;
+          res.cut_blocks = nb;
+          res.cut_nph = nph;
+        } else if (cut_ok) {
+          res.cut = true;
+          emit = false;  // parse only from here: nothing past the boundary is stored
+        }
       }
       if (res.end == NONE && br.pos >= stop) {
         res.end = br.pos;
@@ -613,13 +645,14 @@ __device__ __forceinline__ void inflate_chunk(InflateLDS<WIN> &sh, const FileDes
   // call site of the search, for code size)
   uint64_t search = !first && from != NONE ? from : NONE;
   uint32_t retries = 0;
+  uint32_t n1 = 0, n2 = 0, trial_rej = 0, conf_rej = 0;  // search statistics of this call
   // each retry moves the candidate forward by at least one bit
   const uint64_t max_tries = cd.hi_bit - cd.lo_bit + 2;
   for (uint64_t tries = 0;; tries++) {
     if (search != NONE) {
       Src src;
       src.init(fd.comp, fd.comp_len);
-      b = wave_find_start(src, search, cd.hi_bit, sh.t);
+      b = wave_find_start(src, search, cd.hi_bit, sh.t, &n1, &n2);
       search = NONE;
     }
     if (tries > max_tries) b = NONE;
@@ -633,12 +666,20 @@ __device__ __forceinline__ void inflate_chunk(InflateLDS<WIN> &sh, const FileDes
         cs[c].retries = retries;
         cs[c].status = ST_OK;
         cs[c].pad = 0;
+        cs[c].stage1 += n1;
+        cs[c].stage2 += n2;
+        cs[c].trial_rej += trial_rej;
+        cs[c].confirm_rej += conf_rej;
       }
       return;
     }
     inflater_setup(inf, fd, cd, pool);
-    // a probe stops after the first block (and its confirmation)
-    DecodeResult r = inf.run(b, (fd.mode & FD_PROBE) ? b + 1 : stop, first ? 0u : 6u, defer);
+    // a probe stops after the first block (and its confirmation); other
+    // chunks that outgrow their capacity stop at a block boundary and are
+    // continued by the stitch pass, with the room of the empty chunks after
+    // them (a rejected candidate leaves its chunk empty)
+    const bool probe = (fd.mode & FD_PROBE) != 0;
+    DecodeResult r = inf.run(b, probe ? b + 1 : stop, first ? 0u : 6u, defer, !probe);
     if (r.status != D_OK && (first || r.blocks >= 6u)) {
       if (lane == 0) {
         cs[c].start = b;
@@ -649,30 +690,44 @@ __device__ __forceinline__ void inflate_chunk(InflateLDS<WIN> &sh, const FileDes
         cs[c].flags = 0;
         cs[c].retries = retries;
         cs[c].pad = 0;
+        cs[c].stage1 += n1;
+        cs[c].stage2 += n2;
+        cs[c].trial_rej += trial_rej;
+        cs[c].confirm_rej += conf_rej;
       }
       return;
     }
     if (r.status == D_OK) {
-      uint32_t ph = wave_sum(inf.nph_stop);
-      bool overflow = inf.over && r.len > cd.sym_cap;
+      // a cut decode keeps what was stored: the stitch pass continues it
+      uint32_t ph = wave_sum(r.cut ? r.cut_nph : inf.nph_stop);
+      bool overflow = !r.cut && inf.over && r.len > cd.sym_cap;
       if (lane == 0) {
         cs[c].start = b;
         cs[c].found = b;
         cs[c].end = r.end;
-        cs[c].len = r.len;
+        cs[c].len = r.cut ? r.cut_len : r.len;
+        cs[c].cut_bit = r.cut ? r.cut_bit : NONE;
         cs[c].status = overflow ? ST_CAPACITY : ST_OK;
         cs[c].needed = overflow ? r.len : 0;
-        cs[c].flags = (r.final_seen ? CS_FINAL : 0u) | (overflow ? CS_OVERFLOW : 0u);
+        cs[c].flags = (r.final_seen ? CS_FINAL : 0u) | (overflow ? CS_OVERFLOW : 0u) | (r.cut ? CS_CUT : 0u);
+        // blocks decoded to the stop (the deferred confirmation counts them)
         cs[c].n_blocks = r.blocks;
-        cs[c].n_syms = inf.nsyms;
+        cs[c].cut_blocks = r.cut ? r.cut_blocks : 0u;
+        cs[c].n_syms = r.cut ? r.cut_syms : inf.nsyms;
         cs[c].n_placeholders = ph;
         cs[c].retries = retries;
         cs[c].pad = r.pending;
+        cs[c].stage1 += n1;
+        cs[c].stage2 += n2;
+        cs[c].trial_rej += trial_rej;
+        cs[c].confirm_rej += conf_rej;
       }
       return;
     }
     // the candidate failed the trial decode or the confirmation: next one
     retries++;
+    if (r.blocks == 0) trial_rej++;
+    else conf_rej++;
     search = b + 1;
   }
 }
@@ -700,6 +755,13 @@ __global__ void k_init(ChunkState *cs, uint32_t n_chunks, FileState *fs, uint32_
     z.retries = 0;
     z.valid = 0;
     z.pad = 0;
+    z.stage1 = 0;
+    z.stage2 = 0;
+    z.trial_rej = 0;
+    z.confirm_rej = 0;
+    z.cut_bit = NONE;
+    z.cut_blocks = 0;
+    z.pad2 = 0;
     cs[i] = z;
   }
   if (i < n_files) {
@@ -753,8 +815,14 @@ __global__ __launch_bounds__(256) void k_scan(const FileDesc *files, const Chunk
     wave_sync();
     const uint64_t cur = uni64(__hip_atomic_load(cand, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
     const uint64_t b = (uint32_t)lane < k ? (uint64_t)q[lane] : NONE;
-    const bool ok = b < cur && lane_tables_ok(s, b, cltab[wave], lane);
+    const bool tried = b < cur;
+    const bool ok = tried && lane_tables_ok(s, b, cltab[wave], lane);
     const uint64_t m = __ballot(ok);
+    const uint32_t n_tried = (uint32_t)__builtin_popcountll(__ballot(tried));
+    if (lane == 0 && n_tried) {
+      atomicAdd(&cs[c].stage1, n_tried);
+      atomicAdd(&cs[c].stage2, (uint32_t)__builtin_popcountll(m));
+    }
     if (m) {
       const uint64_t bb = readlane64(b, __ffsll((unsigned long long)m) - 1);
       if (lane == 0) atomicMin(cand, (unsigned long long)bb);
@@ -811,9 +879,12 @@ __global__ __launch_bounds__(256) void k_scan(const FileDesc *files, const Chunk
 // ---------------------------------------------------------------------------
 // k_capacity: one workgroup per file.  A chunk decodes from its start to the
 // next chunk start found by the scan, so its symbol capacity is sized from
-// that span: factor * span bytes + slack, rounded to the flush unit.  The
-// spans partition the payload, so the file's pool of
-// factor * (P + N) + N * (slack + unit) symbols always suffices.
+// that span: factor * span bytes + slack, rounded to the flush unit.  When
+// that candidate fails its trial block it may lie inside a block, and the
+// chunk decodes to the end of that block, so the span counts at least half
+// the chunk's own compressed range (blocks are far shorter than that at the
+// default chunk sizes).  The spans partition the payload, so the file's pool
+// of factor * (1.5 P + 2 N) + N * (slack + unit) symbols always suffices.
 // ---------------------------------------------------------------------------
 
 __global__ __launch_bounds__(256) void k_capacity(const FileDesc *files, ChunkDesc *chunks, const ChunkState *cs,
@@ -855,7 +926,10 @@ __global__ __launch_bounds__(256) void k_capacity(const FileDesc *files, ChunkDe
       if (s != NONE && s < end_bit) {
         const uint64_t e = nxt[tid] < end_bit ? nxt[tid] : end_bit;
         // a probe's one block: at most the stop margin of compressed bytes
-        const uint64_t span = (fd.mode & FD_PROBE) ? STOP_MARGIN_BYTES : e > s ? (e - s + 7) / 8 : 1;
+        const ChunkDesc &cd = chunks[c0 + i];
+        const uint64_t half = (cd.hi_bit - cd.lo_bit + 15) / 16;
+        const uint64_t to_next = e > s ? (e - s + 7) / 8 : 1;
+        const uint64_t span = (fd.mode & FD_PROBE) ? STOP_MARGIN_BYTES : to_next > half ? to_next : half;
         cap = ((uint64_t)factor * span + SYM_SLACK + FLUSH_UNIT - 1) / FLUSH_UNIT * FLUSH_UNIT;
       }
       chunks[c0 + i].sym_cap = cap;
@@ -990,36 +1064,56 @@ __global__ __launch_bounds__(64) void k_redo(const FileDesc *files, const ChunkD
     const uint64_t s0 = uni64(cs[c].start);
     const uint32_t r0 = uni(cs[c].retries);
     inflate_chunk<WIN>(sh, files, chunks, cs, pool, c, false, s0 + 1);
-    if (lane_id() == 0) cs[c].retries += r0 + 1;
+    if (lane_id() == 0) {
+      cs[c].retries += r0 + 1;
+      cs[c].confirm_rej += 1;
+    }
   });
 }
 
-// Continue chunk c from its recorded end until the first block at or past `stop`.
+// Symbols that chunk c may hold once the accepted starts are final: its own
+// region and those of the empty chunks after it, up to the region of `next`,
+// the next chunk with a start (pool regions lie in chunk order, back to
+// back).  A candidate rejected after the regions were sized leaves its chunk
+// empty, and the chunk before it decodes on through that chunk's range.
+__device__ __forceinline__ uint64_t region_to_next(const FileDesc &fd, const ChunkDesc *chunks, uint32_t c,
+                                                   uint32_t next) {
+  const uint64_t end = next < fd.first_chunk + fd.n_chunks ? chunks[next].sym_off : fd.pool_base + fd.pool_elems;
+  return end > chunks[c].sym_off ? end - chunks[c].sym_off : 0;
+}
+
+// Continue chunk c from its recorded end (a cut chunk: from the last block
+// boundary whose symbols were stored) until the first block at or past
+// `stop`, with room for `cap` symbols.
 template <int WIN>
 __device__ void extend_chunk(InflateLDS<WIN> &sh, const FileDesc &fd, const ChunkDesc &cd, ChunkState *cs,
-                             uint16_t *pool, uint32_t c, uint64_t stop) {
+                             uint16_t *pool, uint32_t c, uint64_t stop, uint64_t cap) {
   const int lane = lane_id();
   Inflater<WIN> inf(sh);
   inflater_setup(inf, fd, cd, pool);
+  inf.cap = cap;
+  const bool cut = (uni(cs[c].flags) & CS_CUT) != 0;
   const uint64_t len = uni64(cs[c].len);
-  const uint64_t e = uni64(cs[c].end);
+  const uint64_t e = cut ? uni64(cs[c].cut_bit) : uni64(cs[c].end);
+  const uint32_t nb0 = cut ? uni(cs[c].cut_blocks) : uni(cs[c].n_blocks);
   // bring the recent history back into the ring
   const uint64_t h0 = len > (uint64_t)WIN ? len - WIN : 0;
   for (uint64_t p = h0 + (uint64_t)lane; p < len; p += 64)
-    sh.ring[p & (WIN - 1)] = p < cd.sym_cap ? inf.D[p] : (uint16_t)0;
+    sh.ring[p & (WIN - 1)] = p < cap ? inf.D[p] : (uint16_t)0;
   wave_sync();
   inf.pos = len;
   inf.flushed = len & ~(uint64_t)(Inflater<WIN>::UNIT - 1);
   DecodeResult r = inf.run(e, stop, 0u);
   uint32_t ph = wave_sum(inf.nph_stop);
   if (lane == 0) {
-    bool overflow = inf.over && r.len > cd.sym_cap;
+    bool overflow = inf.over && r.len > cap;
     cs[c].end = r.end;
     cs[c].len = r.len;
-    cs[c].n_blocks += r.blocks;
+    cs[c].n_blocks = nb0 + r.blocks;
     cs[c].n_syms += inf.nsyms;
     cs[c].n_placeholders += ph;
-    cs[c].flags |= CS_EXTENDED | (r.final_seen ? CS_FINAL : 0u) | (overflow ? CS_OVERFLOW : 0u);
+    cs[c].flags = (cs[c].flags & ~CS_FINAL) | CS_EXTENDED | (r.final_seen ? CS_FINAL : 0u) |
+                  (overflow ? CS_OVERFLOW : 0u);
     if (r.status != D_OK) cs[c].status = ST_DATA;
     else if (overflow) {
       cs[c].status = ST_CAPACITY;
@@ -1028,17 +1122,19 @@ __device__ void extend_chunk(InflateLDS<WIN> &sh, const FileDesc &fd, const Chun
   }
 }
 
-// Decode chunk c again from `start` with a placeholder context (repair).
+// Decode chunk c again from `start` with a placeholder context (repair),
+// with room for `cap` symbols.
 template <int WIN>
 __device__ void redecode_chunk(InflateLDS<WIN> &sh, const FileDesc &fd, const ChunkDesc &cd, ChunkState *cs,
-                               uint16_t *pool, uint32_t c, uint64_t start, uint64_t stop) {
+                               uint16_t *pool, uint32_t c, uint64_t start, uint64_t stop, uint64_t cap) {
   const int lane = lane_id();
   Inflater<WIN> inf(sh);
   inflater_setup(inf, fd, cd, pool);
+  inf.cap = cap;
   DecodeResult r = inf.run(start, stop, 0u);
   uint32_t ph = wave_sum(inf.nph_stop);
   if (lane == 0) {
-    bool overflow = inf.over && r.len > cd.sym_cap;
+    bool overflow = inf.over && r.len > cap;
     cs[c].start = start;
     cs[c].end = r.end;
     cs[c].len = r.len;
@@ -1054,7 +1150,9 @@ __device__ void redecode_chunk(InflateLDS<WIN> &sh, const FileDesc &fd, const Ch
 // ---------------------------------------------------------------------------
 // k_stitch: a chunk stopped at the next chunk's scan candidate; if the next
 // accepted start is later (the candidate failed its trial decode, or the next
-// chunks are empty), continue to it.
+// chunks are empty), continue to it.  A chunk that outgrew its capacity in
+// pass 1 (CS_CUT) continues from its last stored block boundary, with the
+// room of the empty chunks after it.
 // ---------------------------------------------------------------------------
 
 template <int WIN>
@@ -1063,7 +1161,9 @@ __global__ __launch_bounds__(64) void k_stitch(const FileDesc *files, const Chun
   __shared__ InflateLDS<WIN> sh;
   // a chunk continues when the next accepted start lies past its end
   auto short_of_next = [&](uint32_t c) {
-    if (cs[c].start == NONE || cs[c].status != ST_OK || (cs[c].flags & CS_FINAL)) return false;
+    if (cs[c].start == NONE || cs[c].status != ST_OK) return false;
+    if (cs[c].flags & CS_CUT) return true;  // pass 1 stored only part of it
+    if (cs[c].flags & CS_FINAL) return false;
     const FileDesc &fd = files[chunks[c].file];
     const uint64_t nf = next_start(fd, cs, c, true, nullptr);
     return cs[c].end < nf || nf == NONE;
@@ -1071,8 +1171,9 @@ __global__ __launch_bounds__(64) void k_stitch(const FileDesc *files, const Chun
   sparse_chunks(&ctr->stitch_next, n, short_of_next, [&](uint32_t c) {
     const ChunkDesc cd = chunks[c];
     const FileDesc fd = files[cd.file];
-    const uint64_t nf = uni64(next_start(fd, cs, c, true, nullptr));
-    extend_chunk<WIN>(sh, fd, cd, cs, pool, c, nf);
+    uint32_t nx;
+    const uint64_t nf = uni64(next_start(fd, cs, c, true, &nx));
+    extend_chunk<WIN>(sh, fd, cd, cs, pool, c, nf, region_to_next(fd, chunks, c, uni(nx)));
   });
 }
 
@@ -1147,7 +1248,7 @@ __global__ __launch_bounds__(256) void k_finalize(const FileDesc *files, const C
             cs[j].status = ST_OK;
           }
         } else {
-          redecode_chunk<WIN>(sh, fd, chunks[j], cs, pool, j, cur, stop);
+          redecode_chunk<WIN>(sh, fd, chunks[j], cs, pool, j, cur, stop, region_to_next(fd, chunks, j, uni(nx)));
         }
       }
       const int32_t sj_status = uni(cs[j].status);

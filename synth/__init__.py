@@ -44,6 +44,7 @@ __all__ = [
     "word_stream",
     "random_dna",
     "gzip_member",
+    "gzip_member_indexed",
     "make",
     "cache_dir",
 ]
@@ -51,7 +52,14 @@ __all__ = [
 _ACGT = np.frombuffer(b"ACGT", dtype=np.uint8)
 
 
+def _digits(out, pos, vals, nd):
+    """Write the nd decimal digits of vals at out[pos .. pos + nd - 1]."""
+    for d in range(nd):
+        out[pos + d] = (vals // (10 ** (nd - 1 - d))) % 10 + 48
+
+
 def _fastq_batch(rng, k0, n, read_lens):
+    """n records, numbered from k0, laid out with array operations."""
     lens = rng.choice(np.asarray(read_lens, dtype=np.int64), size=n)
     tot = int(lens.sum())
     bases = _ACGT[rng.integers(0, 4, size=tot, dtype=np.uint8)]
@@ -61,43 +69,97 @@ def _fastq_batch(rng, k0, n, read_lens):
     qual = (np.clip(np.rint(q), 2, 40) + 33).astype(np.uint8)
     xs = rng.integers(1000, 30001, size=n)
     ys = rng.integers(1000, 100001, size=n)
-    bb = bases.tobytes()
-    qb = qual.tobytes()
-    parts = []
-    pos = 0
-    for j in range(n):
-        k = k0 + j
-        L = int(lens[j])
-        lane = 1 + (k // 1000000) % 8
-        tile = 1101 + (k // 10000) % 100
-        parts.append(
-            b"@SIM:1:%d:%d:%d:%d\n%s\n+\n%s\n"
-            % (lane, tile, xs[j], ys[j], bb[pos:pos + L], qb[pos:pos + L])
-        )
-        pos += L
-    return b"".join(parts)
+    k = k0 + np.arange(n, dtype=np.int64)
+    lane = 1 + (k // 1000000) % 8
+    tile = 1101 + (k // 10000) % 100
+    xd = np.where(xs >= 10000, 5, 4)
+    yd = np.where(ys >= 100000, 6, np.where(ys >= 10000, 5, 4))
+    # "@SIM:1:" lane ":" tile ":" x ":" y "\n", read "\n+\n", quality "\n"
+    hdr = 7 + 1 + 1 + 4 + 1 + xd + 1 + yd + 1
+    rec = hdr + lens + 3 + lens + 1
+    start = np.concatenate(([0], np.cumsum(rec)[:-1]))
+    out = np.empty(int(rec.sum()), dtype=np.uint8)
+    out[start[:, None] + np.arange(7)] = np.frombuffer(b"@SIM:1:", dtype=np.uint8)
+    out[start + 7] = lane + 48
+    out[start + 8] = ord(":")
+    _digits(out, start + 9, tile, 4)
+    out[start + 13] = ord(":")
+    p = start + 14
+    for nd in (4, 5):
+        m = xd == nd
+        _digits(out, p[m], xs[m], nd)
+    p = p + xd
+    out[p] = ord(":")
+    p = p + 1
+    for nd in (4, 5, 6):
+        m = yd == nd
+        _digits(out, p[m], ys[m], nd)
+    p = p + yd
+    out[p] = 10
+    rs = p + 1  # first base of each read
+    boff = np.concatenate(([0], np.cumsum(lens)[:-1]))
+    for L in np.unique(lens):
+        m = lens == L
+        ar = np.arange(L)
+        out[rs[m][:, None] + ar] = bases[boff[m][:, None] + ar]
+        out[(rs[m] + L + 3)[:, None] + ar] = qual[boff[m][:, None] + ar]
+    out[rs + lens] = 10
+    out[rs + lens + 1] = ord("+")
+    out[rs + lens + 2] = 10
+    out[rs + 2 * lens + 3] = 10
+    return out.tobytes()
+
+
+# Records are generated in blocks of FASTQ_BLOCK records; block b draws from
+# the generator seeded with (seed, b) and holds records b*FASTQ_BLOCK onward,
+# so blocks are independent and large inputs are made by a pool of threads
+# while the bytes do not depend on the pool's size.
+FASTQ_BLOCK = 16384
+
+
+def _fastq_block(job):
+    seed, b, read_lens = job
+    return _fastq_batch(np.random.default_rng([seed, b]), b * FASTQ_BLOCK, FASTQ_BLOCK, read_lens)
+
+
+def _pool_map(fn, jobs):
+    """fn over jobs in a pool of at most 16 threads (the block generators are
+    array operations, which run outside the interpreter lock)."""
+    if len(jobs) <= 2:
+        return [fn(j) for j in jobs]
+    nw = min(16, os.cpu_count() or 1, len(jobs))
+    with ThreadPoolExecutor(max_workers=nw) as ex:
+        return list(ex.map(fn, jobs))
+
+
+def _blocks_until(make_jobs, fn, target_bytes: int, est_block_bytes: float):
+    """Blocks 0, 1, ... (made in parallel) until their total reaches target_bytes."""
+    out, size, b = [], 0, 0
+    while size < target_bytes:
+        n = max(1, int((target_bytes - size) / est_block_bytes) + 1)
+        parts = _pool_map(fn, make_jobs(b, b + n))
+        for part in parts:
+            if size >= target_bytes:
+                break
+            out.append(part)
+            size += len(part)
+            b += 1
+    return out, size
 
 
 def fastq_like(target_bytes: int, seed: int, read_lens=(150,)) -> bytes:
     """Whole FASTQ-like records until the size reaches ``target_bytes``."""
-    rng = np.random.default_rng(seed)
-    out = []
-    size = 0
-    k = 0
-    mean_rec = 40 + 2 * float(np.mean(read_lens)) + 3
-    while size < target_bytes:
-        n = int(max(16, min(200000, (target_bytes - size) / mean_rec + 16)))
-        b = _fastq_batch(rng, k, n, read_lens)
-        k += n
-        if size + len(b) >= target_bytes:
-            # keep whole records only, stop at the first record end >= target
-            need = target_bytes - size
-            cut = b.find(b"\n@SIM", max(0, need - 1))
-            if cut >= 0:
-                b = b[: cut + 1]
-        out.append(b)
-        size += len(b)
-    return b"".join(out)
+    read_lens = tuple(int(x) for x in read_lens)
+    est = FASTQ_BLOCK * (31 + 2 * float(np.mean(read_lens)))
+    parts, size = _blocks_until(lambda b0, b1: [(seed, b, read_lens) for b in range(b0, b1)], _fastq_block,
+                                max(1, target_bytes), est)
+    last = parts[-1]
+    need = target_bytes - (size - len(last))
+    # keep whole records only: stop at the first record end at or past the target
+    cut = last.find(b"\n@SIM", max(0, need - 1))
+    if cut >= 0:
+        parts[-1] = last[: cut + 1]
+    return b"".join(parts)
 
 
 def _vocabulary(rng, n_words=50000):
@@ -106,55 +168,72 @@ def _vocabulary(rng, n_words=50000):
     return letters, lens
 
 
-def word_stream(target_bytes: int, seed: int, n_words: int = 50000, s: float = 1.1) -> bytes:
-    """Zipf word stream with punctuation and ~80-column lines."""
-    rng = np.random.default_rng(seed)
-    letters, wlens = _vocabulary(rng, n_words)
+WORD_BLOCK = 1 << 20  # tokens per block; block b draws from the generator seeded with (seed, b + 1)
+
+
+def _line_ends(tl):
+    """Greedy line breaking of tokens of lengths tl (separator excluded): a
+    line takes tokens while it is shorter than 80 characters, and the token
+    that brings it to 80 or more ends it with a newline.  Returns a mask of
+    the tokens followed by a newline.  With C the prefix sums of the token
+    lengths plus separators, the line that starts at token j ends before
+    token nxt[j], the first m with C[m] >= C[j] + 81; the line starts are the
+    chain 0, nxt[0], nxt[nxt[0]], ..., found by doubling (log2 rounds)."""
+    n = tl.size
+    C = np.concatenate(([0], np.cumsum(tl.astype(np.int64) + 1)))
+    nxt = np.searchsorted(C, C[:n] + 81, side="left")  # in [j + 1, n + 1]
+    jump = np.append(np.minimum(nxt, n), n)  # n: past the end (absorbing)
+    starts = np.zeros(1, dtype=np.int64)
+    while True:
+        new = jump[starts]
+        new = new[new < n]
+        if new.size == 0:
+            break
+        starts = np.concatenate((starts, new))
+        jump = jump[jump]
+    ends = nxt[starts] - 1
+    mask = np.zeros(n, dtype=bool)
+    mask[ends[ends < n]] = True
+    return mask
+
+
+def _word_block(job):
+    seed, b, n_words, s = job
+    letters, wlens = _vocabulary(np.random.default_rng(seed), n_words)
     ranks = np.arange(1, n_words + 1, dtype=np.float64)
     p = ranks ** (-s)
     cdf = np.cumsum(p / p.sum())
     punct = np.frombuffer(b".,;:!?", dtype=np.uint8)
-    out = []
-    size = 0
-    line = 0
-    while size < target_bytes:
-        n = int(min(4_000_000, max(1024, (target_bytes - size) / 6 + 1024)))
-        tok = np.searchsorted(cdf, rng.random(n), side="right")
-        tok = np.minimum(tok, n_words - 1)
-        has_p = rng.random(n) < 0.05
-        pch = punct[rng.integers(0, len(punct), size=n)]
-        tl = wlens[tok] + has_p  # token length without separator
-        # greedy line breaking: newline after the token that brings the line to >= 80
-        tl_list = tl.tolist()
-        sep_nl = bytearray(n)
-        for j, L in enumerate(tl_list):
-            line += L
-            if line >= 80:
-                sep_nl[j] = 1
-                line = 0
-            else:
-                line += 1
-        sep = np.where(np.frombuffer(bytes(sep_nl), dtype=np.uint8) == 1, ord("\n"), ord(" ")).astype(np.uint8)
-        full = tl + 1
-        starts = np.concatenate(([0], np.cumsum(full)[:-1]))
-        total = int(full.sum())
-        buf = np.empty(total, dtype=np.uint8)
-        wl = wlens[tok]
-        for j in range(12):
-            m = wl > j
-            buf[starts[m] + j] = letters[tok[m], j]
-        pm = has_p
-        buf[starts[pm] + wl[pm]] = pch[pm]
-        buf[starts + tl] = sep
-        b = buf.tobytes()
-        if size + len(b) >= target_bytes:
-            need = target_bytes - size
-            cut = b.find(b"\n", max(0, need - 1))
-            if cut >= 0:
-                b = b[: cut + 1]
-        out.append(b)
-        size += len(b)
-    return b"".join(out)
+    rng = np.random.default_rng([seed, b + 1])
+    n = WORD_BLOCK
+    tok = np.minimum(np.searchsorted(cdf, rng.random(n), side="right"), n_words - 1)
+    has_p = rng.random(n) < 0.05
+    pch = punct[rng.integers(0, len(punct), size=n)]
+    wl = wlens[tok]
+    tl = wl + has_p  # token length without separator
+    sep = np.where(_line_ends(tl), ord("\n"), ord(" ")).astype(np.uint8)
+    full = tl + 1
+    starts = np.concatenate(([0], np.cumsum(full)[:-1]))
+    buf = np.empty(int(full.sum()), dtype=np.uint8)
+    for j in range(12):
+        m = wl > j
+        buf[starts[m] + j] = letters[tok[m], j]
+    buf[starts[has_p] + wl[has_p]] = pch[has_p]
+    buf[starts + tl] = sep
+    return buf.tobytes()
+
+
+def word_stream(target_bytes: int, seed: int, n_words: int = 50000, s: float = 1.1) -> bytes:
+    """Zipf word stream with punctuation and ~80-column lines (each block of
+    WORD_BLOCK tokens starts a new line)."""
+    parts, size = _blocks_until(lambda b0, b1: [(seed, b, n_words, s) for b in range(b0, b1)], _word_block,
+                                max(1, target_bytes), 7.0 * WORD_BLOCK)
+    last = parts[-1]
+    need = target_bytes - (size - len(last))
+    cut = last.find(b"\n", max(0, need - 1))
+    if cut >= 0:
+        parts[-1] = last[: cut + 1]
+    return b"".join(parts)
 
 
 def random_dna(n: int, seed: int) -> bytes:
@@ -193,11 +272,27 @@ def gzip_member(
     mtime: int = 0,
 ) -> bytes:
     """One gzip member (RFC 1952) of ``data`` compressed by zlib."""
+    return gzip_member_indexed(data, level, segment_bytes, threads, strategy, mtime)[0]
+
+
+def gzip_member_indexed(
+    data: bytes,
+    level: int = 6,
+    segment_bytes: int = 64 << 20,
+    threads: int | None = None,
+    strategy: int = zlib.Z_DEFAULT_STRATEGY,
+    mtime: int = 0,
+):
+    """gzip_member, and the bit offset in the member where the first block of
+    each compression segment begins (the encoder's own record: segment k > 0
+    starts right after the sync flush that ends segment k - 1, so each offset
+    is a block boundary of the member, and segment k's first output byte is
+    data[k * segment_bytes])."""
     xfl = 2 if level == 9 else (4 if level == 1 else 0)
     header = b"\x1f\x8b\x08\x00" + struct.pack("<I", mtime) + bytes([xfl, 255])
     n = len(data)
     if n <= segment_bytes:
-        body = _deflate_segment(data, level, None, True, strategy)
+        parts = [_deflate_segment(data, level, None, True, strategy)]
     else:
         mv = memoryview(data)
         cuts = list(range(0, n, segment_bytes)) + [n]
@@ -208,9 +303,13 @@ def gzip_member(
         nt = threads or min(16, os.cpu_count() or 1)
         with ThreadPoolExecutor(max_workers=nt) as ex:
             parts = list(ex.map(lambda j: _deflate_segment(j[0], level, j[1], j[2], strategy), jobs))
-        body = b"".join(parts)
+    seg_bits = []
+    off = len(header)
+    for p in parts:
+        seg_bits.append(8 * off)
+        off += len(p)
     trailer = struct.pack("<II", zlib.crc32(data) & 0xFFFFFFFF, n & 0xFFFFFFFF)
-    return header + body + trailer
+    return header + b"".join(parts) + trailer, seg_bits
 
 
 def cache_dir() -> str:
@@ -239,33 +338,48 @@ def _gen(kind, size, seed, kw):
     raise ValueError(kind)
 
 
-def make(kind: str, size: int, seed: int, level: int, use_cache: bool = True, **kw):
-    """Return (raw_text, gzip_bytes) for a generated workload, cached on disk."""
+SEGMENT_BYTES = 64 << 20  # input bytes per compression segment of large members
+CACHE_MAX_BYTES = int(os.environ.get("GZGPU_CACHE_MAX", str(3 << 29)))
+_RAW_MEMO: dict = {}  # the last generated text, kept for the next level of the same text
+
+
+def make(kind: str, size: int, seed: int, level: int, use_cache: bool = True, index: bool = False, **kw):
+    """Return (raw_text, gzip_bytes) for a generated workload, cached on disk;
+    with index=True also the encoder's segment start bits (gzip_member_indexed)."""
     tag = f"{kind}_{size}_{seed}_{level}_" + "_".join(f"{k}{v}" for k, v in sorted(kw.items()))
     tag = tag.replace(" ", "").replace("(", "").replace(")", "").replace(",", "-")
     if use_cache:
         d = cache_dir()
-        pr, pg = os.path.join(d, tag + ".raw"), os.path.join(d, tag + ".gz")
-        if os.path.exists(pr) and os.path.exists(pg):
+        pr, pg, pi = (os.path.join(d, tag + e) for e in (".raw", ".gz", ".idx"))
+        if os.path.exists(pr) and os.path.exists(pg) and os.path.exists(pi):
             with open(pr, "rb") as f:
                 raw = f.read()
             with open(pg, "rb") as f:
                 gz = f.read()
-            return raw, gz
-    raw = _gen(kind, size, seed, kw)
-    gz = gzip_member(raw, level)
-    if use_cache:
-        for p, b in ((pr, raw), (pg, gz)):
+            with open(pi) as f:
+                seg = [int(x) for x in f.read().split()]
+            return (raw, gz, seg) if index else (raw, gz)
+    key = (kind, size, seed, tuple(sorted(kw.items())))
+    if _RAW_MEMO.get("key") == key:
+        raw = _RAW_MEMO["raw"]  # the same text at another level (the level sweep)
+    else:
+        _RAW_MEMO.clear()
+        raw = _gen(kind, size, seed, kw)
+        _RAW_MEMO.update(key=key, raw=raw)
+    gz, seg = gzip_member_indexed(raw, level, SEGMENT_BYTES)
+    # inputs above the cache limit are made again rather than written out
+    if use_cache and size <= CACHE_MAX_BYTES:
+        for p, b in ((pr, raw), (pg, gz), (pi, " ".join(map(str, seg)).encode())):
             tmp = p + ".tmp%d" % os.getpid()
             with open(tmp, "wb") as f:
                 f.write(b)
             os.replace(tmp, p)
-    return raw, gz
+    return (raw, gz, seg) if index else (raw, gz)
 
 
-def workload(name: str, use_cache: bool = True):
+def workload(name: str, use_cache: bool = True, index: bool = False):
     kind, size, seed, level, kw = WORKLOADS[name]
-    return make(kind, size, seed, level, use_cache=use_cache, **kw)
+    return make(kind, size, seed, level, use_cache=use_cache, index=index, **kw)
 
 
 def bgzf_member(data: bytes, level: int = 6) -> bytes:

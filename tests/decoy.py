@@ -183,3 +183,75 @@ def too_far_member(seed: int = 7, head_bytes: int = 3000, tail_blocks: int = 8, 
 def expand_len(tokens):
     """Bytes that a token list produces (only their count matters here)."""
     return b"".join(bytes([t]) if isinstance(t, int) else bytes(t[0]) for t in tokens)
+
+
+def trial_fail_member(seed: int = 3, real_before: int = 3, real_after: int = 6, real_bytes: int = 4000,
+                      stored_bytes: int = 40000):
+    """A member with one stored block of ASCII text whose payload starts with
+    a small dynamic block (about 300 bytes of output): its header and code
+    tables pass the static checks, its trial block is too small (not more
+    than 1 KiB), and the rest of the payload holds no block start.  A chunk
+    whose range starts inside that payload ends up empty after the rejection,
+    and the chunk before it decodes through the whole stored block, far more
+    than the span to the rejected candidate.  Returns (member bytes, output
+    bytes, bit offset of the rejected candidate)."""
+    small = BitWriter()
+    small_text = ascii_text(300, seed * 7919)
+    dynamic_block(small, Tokenizer(small_text).tokens(len(small_text)), final=False)
+    head = small.getvalue()
+    pad = ascii_text(stored_bytes - len(head), seed * 7919 + 1)
+    payload = head + pad
+    texts = [ascii_text(real_bytes, seed * 100 + k) for k in range(real_before + real_after)]
+    out = b"".join(texts[:real_before]) + payload + b"".join(texts[real_before:])
+    tk = Tokenizer(out)
+    bw = BitWriter()
+    pos = 0
+    cand = None
+    for k in range(real_before + real_after + 1):
+        if k == real_before:
+            tk.skip(pos + len(payload))
+            cand = HEADER_BITS + ((bw.nbits + 3 + 7) // 8) * 8 + 32
+            stored_block(bw, payload, final=False)
+            pos += len(payload)
+            continue
+        t = texts[k if k < real_before else k - 1]
+        dynamic_block(bw, tk.tokens(pos + len(t)), final=k == real_before + real_after)
+        pos += len(t)
+    return gzip_wrap(bw.getvalue(), out), out, cand
+
+
+def dense_block_member(seed: int = 5, dense_bytes: int = 36000, mutate: float = 0.02, good_after: int = 5,
+                       tail_blocks: int = 8, real_bytes: int = 4000):
+    """A member whose dynamic block D compresses far better than the rest
+    (repeated 100-byte lines with a few changed characters), followed by
+    good_after ordinary text blocks, a block with one non-ASCII literal (B),
+    and tail_blocks ordinary blocks.  Every block between D and B fails the
+    block-start confirmation (B lies within their five confirmation blocks)
+    and B fails its trial block, so a chunk whose range holds only those
+    blocks ends up empty, and the chunk that starts at D decodes through it.
+    Returns (member bytes, output bytes, bit offsets of D and of all block
+    headers)."""
+    rng = np.random.default_rng(seed)
+    line = bytearray(ascii_text(100, seed * 31)[:99] + b"\n")
+    dense = bytearray()
+    while len(dense) < dense_bytes:
+        for i in np.nonzero(rng.random(99) < mutate)[0]:
+            line[int(i)] = 97 + int(rng.integers(0, 26))
+        dense += line
+    dense = bytes(dense[:dense_bytes])
+    head = [ascii_text(real_bytes, seed * 100 + k) for k in range(6)]
+    mid = [ascii_text(real_bytes, seed * 100 + 10 + k) for k in range(good_after)]
+    bad = bytearray(ascii_text(real_bytes, seed * 100 + 30))
+    bad[len(bad) // 2] = 0xFF
+    tail = [ascii_text(real_bytes, seed * 100 + 40 + k) for k in range(tail_blocks)]
+    parts = head + [dense] + mid + [bytes(bad)] + tail
+    out = b"".join(parts)
+    tk = Tokenizer(out)
+    bw = BitWriter()
+    bits = []
+    pos = 0
+    for i, t in enumerate(parts):
+        bits.append(HEADER_BITS + bw.nbits)
+        dynamic_block(bw, tk.tokens(pos + len(t)), final=i == len(parts) - 1)
+        pos += len(t)
+    return gzip_wrap(bw.getvalue(), out), out, bits[len(head)], bits

@@ -28,7 +28,7 @@ class Result(C.Structure):
                 ("out_needed", C.c_uint64), ("ws_needed", C.c_uint64), ("n_nonempty", C.c_uint32),
                 ("n_repairs", C.c_uint32), ("n_extended", C.c_uint32), ("n_retries", C.c_uint32),
                 ("n_syms", C.c_uint64), ("n_placeholders", C.c_uint64), ("n_blocks", C.c_uint64),
-                ("crc32", C.c_uint32), ("pad", C.c_uint32)]
+                ("crc32", C.c_uint32), ("inflate_waves", C.c_uint32)]
 
 
 _lib = None
@@ -49,6 +49,7 @@ def lib():
         _lib.gz_decompress.argtypes = [vp, vp, C.c_size_t, vp, C.c_size_t, vp]
         _lib.gz_result_get.argtypes = [vp, C.c_int, C.POINTER(Result)]
         _lib.gz_chunk_table.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp, vp, vp]
+        _lib.gz_chunk_stats.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp, vp, vp, vp]
         _lib.gz_plan_destroy.argtypes = [vp]
         _lib.gz_plan_destroy.restype = None
         _lib.emu_set_sync_limit.argtypes = [C.c_uint64]
@@ -90,6 +91,12 @@ def run(comp: bytes, n_chunks: int, out_cap=None, sync_limit=0, **opts):
     L.gz_chunk_table(h, 0, p(tab["start"]), p(tab["cand"]), p(tab["end"]), p(tab["len"]), p(tab["out_off"]),
                      p(sts), p(fl))
     tab["status"], tab["flags"] = sts, fl
+    for k in ("n_syms", "n_placeholders", "scan_cand"):
+        tab[k] = np.zeros(n, dtype=np.uint64)
+    for k in ("n_blocks", "stage1", "stage2", "trial_rej", "confirm_rej"):
+        tab[k] = np.zeros(n, dtype=np.uint32)
+    assert L.gz_chunk_stats(h, 0, p(tab["n_syms"]), p(tab["n_placeholders"]), p(tab["n_blocks"]), p(tab["scan_cand"]),
+                            p(tab["stage1"]), p(tab["stage2"]), p(tab["trial_rej"]), p(tab["confirm_rej"])) == 0
     L.gz_plan_destroy(h)
     return r.status, out[: r.out_len].tobytes(), r, tab
 

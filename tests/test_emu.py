@@ -466,6 +466,11 @@ def test_emu_false_starts_repaired(orc, final_last, n):
         assert np.array_equal(tab[k][ne].astype(np.int64), getattr(ref, "off" if k == "out_off" else k)[ne]), k
     assert r.n_repairs == ref.n_repairs
     assert r.n_placeholders == int(ref.placeholders.sum())
+    # per-chunk statistics: placeholders of the accepted decodes, and every
+    # rejected candidate counted at the stage that rejected it
+    assert np.array_equal(tab["n_placeholders"][ne].astype(np.int64), ref.placeholders[ne])
+    assert int(tab["trial_rej"].sum()) + int(tab["confirm_rej"].sum()) == r.n_retries
+    assert (tab["stage2"][1:][ne[1:]] >= 1).all() and (tab["stage1"] >= tab["stage2"]).all()
     repaired = (tab["flags"] & 8) != 0
     assert np.array_equal(np.nonzero(repaired)[0], np.nonzero((ref.cand != ref.start) & ne)[0])
     assert set(found[repaired].tolist()) <= set(decoy_bits)
@@ -483,3 +488,42 @@ def test_emu_too_far_across_chunks(orc):
         assert ref.status == orc.E_DATA
         st, out, r, tab = E.run(gz, n, out_cap=64 << 10, sync_limit=3_000_000_000)
         assert st == -4, (n, st)
+
+
+def _same_as_oracle(orc, gz, raw, n):
+    ref = orc.pugz(gz, n)
+    assert ref.status == orc.OK and ref.out.tobytes() == raw
+    st, out, r, tab = E.run(gz, n, out_cap=len(raw) + 64, sync_limit=3_000_000_000)
+    assert st == 0 and out == raw
+    assert np.array_equal(_starts(tab), ref.start)
+    ne = ref.start >= 0
+    assert np.array_equal(tab["end"][ne].astype(np.int64), ref.end[ne])
+    assert np.array_equal(tab["len"][ne].astype(np.int64), ref.len[ne])
+    assert r.n_placeholders == int(ref.placeholders.sum())
+    return tab
+
+
+@pytest.mark.parametrize("case", ["first-cut", "extend-over-empty", "dense-cut-a", "dense-cut-b"])
+def test_emu_room_of_empty_chunks(orc, case):
+    """A candidate rejected after the symbol regions were sized leaves its
+    chunk empty, and the chunk before it decodes through that chunk's range:
+    it continues into the empty chunk's region (the stitch pass), and when
+    even its own first blocks outgrow its region, pass 1 stops at the last
+    block boundary that fits and the stitch pass continues from there.  Same
+    starts, ends, lengths and bytes as the oracle, with no capacity error."""
+    import decoy
+
+    if case == "first-cut":
+        gz, raw, _ = decoy.trial_fail_member(real_before=3)
+        tab = _same_as_oracle(orc, gz, raw, 12)
+        assert tab["flags"][0] & 64 and tab["trial_rej"][1] == 1  # chunk 0 cut, chunk 1's candidate rejected
+    elif case == "extend-over-empty":
+        gz, raw, _ = decoy.trial_fail_member(real_before=10, stored_bytes=65000)
+        tab = _same_as_oracle(orc, gz, raw, 16)
+        assert tab["flags"][1] & 4 and tab["len"][1] == 89000 and (tab["flags"][2] & 2)
+    else:
+        gz, raw, dbit, bits = decoy.dense_block_member(dense_bytes=40000, mutate=0.02)
+        n = 8 if case == "dense-cut-a" else 12
+        tab = _same_as_oracle(orc, gz, raw, n)
+        k = int(np.nonzero(_starts(tab) == dbit)[0][0])
+        assert k >= 1 and tab["flags"][k] & 64 and tab["flags"][k + 1] & 2

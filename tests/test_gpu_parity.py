@@ -341,3 +341,48 @@ def test_too_far_across_chunks(orc):
         with pytest.raises(_gz().GzError) as ei:
             plan.run()
         assert ei.value.code == -4
+
+
+@pytest.mark.parametrize("case", ["trial-fail-3", "trial-fail-10", "dense"])
+def test_room_of_empty_chunks(orc, case):
+    """Candidates rejected after the symbol regions were sized (tests/decoy.py):
+    the chunk before decodes on through the empty chunk's range, within its
+    region and the empty chunks' regions, stopping early in pass 1 when even
+    its first blocks do not fit.  Every chunk count where the oracle succeeds
+    gives the oracle's starts, ends, lengths and bytes without a capacity
+    error (a plain launch, no re-plan)."""
+    import decoy
+
+    if case == "trial-fail-3":
+        gz, raw, _ = decoy.trial_fail_member(real_before=3)
+    elif case == "trial-fail-10":
+        gz, raw, _ = decoy.trial_fail_member(real_before=10, stored_bytes=65000)
+    else:
+        gz, raw, _, _ = decoy.dense_block_member(dense_bytes=40000, mutate=0.02)
+    cuts = 0
+    for n in range(2, 40):
+        ref = orc.pugz(gz, n)
+        assert ref.status == orc.OK
+        _say(case, "chunks", n)
+        plan = _gz().Plan(_dev(gz), n)
+        out = torch.empty(len(raw) + 64, dtype=torch.uint8, device="cuda:0")
+        plan.launch(out)
+        r = plan.result()
+        if case == "dense" and r.status == _gz().GZ_E_CAPACITY:
+            # the dense block can outgrow even the empty chunks' room: the
+            # plan is made again with a larger symbol factor
+            got = plan.run().cpu().numpy().tobytes()
+            assert got == raw
+            r = plan.result()
+            out = None
+        assert r.status == 0, (n, r.status)
+        if out is not None:
+            assert out[: r.out_len].cpu().numpy().tobytes() == raw
+        tab = plan.chunk_table()
+        assert np.array_equal(_starts(tab), ref.start), n
+        ne = ref.start >= 0
+        assert np.array_equal(tab["end"][ne].astype(np.int64), ref.end[ne])
+        assert np.array_equal(tab["len"][ne].astype(np.int64), ref.len[ne])
+        # pass 1 cut short (64), or continued into empty chunks' room (4)
+        cuts += int(((tab["flags"] & (64 if case != "trial-fail-10" else 4)) != 0).sum())
+    assert cuts >= 1

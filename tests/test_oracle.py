@@ -726,3 +726,25 @@ def test_pugz_too_far_found_by_translation(orc):
     # the whole member as one chunk: the first chunk has an empty context
     p = orc.pugz(gz, 1)
     assert p.status == orc.E_DATA and p.reason == "TOO_FAR"
+
+
+def test_symbolic_block_bits(orc, decoy_case):
+    """The symbolic pass records where each block it decodes begins: from the
+    payload, the encoder's own block chain (and the sequential decoder's
+    block map); from an encoder segment boundary of a pigz-style member, the
+    rest of the sequential decoder's block map up to the stop."""
+    gz, raw, real_bits, decoy_bits = decoy_case
+    s = orc.symbolic(gz, real_bits[0], 1 << 62, first=True)
+    assert s.status == orc.OK and s.final_reached
+    assert s.block_bits.tolist() == real_bits
+    data = synth.fastq_like(3 << 20, 77)
+    comp, seg = synth.gzip_member_indexed(data, 6, segment_bytes=1 << 20)
+    g = orc.gunzip(comp)
+    assert g.status == orc.OK
+    for k in range(len(seg)):
+        stop = seg[k + 1] if k + 1 < len(seg) else 1 << 62
+        s = orc.symbolic(comp, seg[k], stop, first=(k == 0))
+        assert s.status == orc.OK
+        want = g.block_bit[(g.block_bit >= seg[k]) & (g.block_bit < stop)]
+        assert np.array_equal(s.block_bits, want), k
+        assert s.sym.size == (min((k + 1) << 20, len(data)) - (k << 20))
