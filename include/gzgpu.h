@@ -11,10 +11,10 @@
  *
  * Memory model
  *   - Every buffer handed to these calls is HIP device memory owned by the
- *     caller: compressed input, output and workspace.  The library allocates
- *     no device memory for plans; it keeps a small pinned host copy of each
- *     plan's job table.  A stream holds a 32 KiB window buffer and a server
- *     its arena (below).
+ *     caller: compressed input, output, workspace, and a server's arena.
+ *     The library allocates no device memory; it keeps a small pinned host
+ *     copy of each plan's job table, and a stream a 32 KiB pinned host
+ *     buffer for its carried window.
  *   - The compressed input must stay alive and unmodified until the stream
  *     work of a gz_decompress* call has completed.
  *   - A plan is used by one stream at a time.  Distinct plans (with distinct
@@ -238,9 +238,12 @@ int gz_device_info(int dev, int *n_cu, int *lds_bytes);
  *
  * Memory: the caller provides, per segment, an output buffer and a workspace
  * (gz_stream_get_info gives sizes that fit every segment at the options'
- * symbol factor); the stream allocates one 32 KiB device buffer for the
- * carried window.  The compressed input stays caller-owned and must stay
- * valid while the stream is used.  One stream, one host thread.
+ * symbol factor), both valid until gz_stream_wait returns; the library
+ * allocates no device memory.  The carried window goes from the segment's
+ * workspace to a 32 KiB pinned host buffer of the stream (gz_stream_wait)
+ * and back into the next segment's workspace.  The compressed input stays
+ * caller-owned and must stay valid while the stream is used.  One stream,
+ * one host thread.
  * ------------------------------------------------------------------------ */
 typedef struct gz_stream_s *gz_stream_t;
 
@@ -286,8 +289,8 @@ typedef struct gz_checkpoint {
 } gz_checkpoint;
 
 /* Reads the member header and trailer (small synchronous copies) and
- * allocates the window buffer.  segment_bytes 0: 256 MiB.  Errors: GZ_E_ARG,
- * GZ_E_HEADER, GZ_E_HIP. */
+ * allocates the pinned host window buffer.  segment_bytes 0: 256 MiB.
+ * Errors: GZ_E_ARG, GZ_E_HEADER, GZ_E_HIP. */
 int gz_stream_open(gz_stream_t *stream, const void *d_comp, size_t comp_len, uint64_t segment_bytes,
                    const gz_opts *opts);
 int gz_stream_get_info(gz_stream_t stream, gz_stream_info *info);
@@ -372,18 +375,23 @@ int gz_count_byte(const void *d_buf, uint64_t n, uint32_t value, uint64_t first,
 
 /* ------------------------------------------------------------------------
  * Serving loop (beyond the paper's one-file setting): jobs arrive one at a
- * time, are admitted into batches while their workspaces fit in a device
- * arena of budget_bytes allocated at creation (the HBM budget), and run as
- * batched launch sequences on up to max_inflight streams at once; a finished
- * batch frees its arena block for the jobs queued behind it (continuous
- * batching).  Single-threaded: every call on one server comes from one host
- * thread.  Inputs and outputs stay owned by the caller and must stay valid
- * until the job is reported done.
+ * time and are admitted into batches while two bounds hold: the footprints
+ * of the jobs in flight (compressed input + output capacity + workspace)
+ * stay within the HBM budget, and the batch's workspace fits in the
+ * caller's device arena.  Batches run as batched launch sequences on up to
+ * max_inflight streams at once; a finished batch frees its arena block and
+ * its share of the budget for the jobs queued behind it (continuous
+ * batching).  The library allocates no device memory: the arena, the inputs
+ * and the outputs are the caller's, and must stay valid until the server is
+ * destroyed (the arena) or the job is reported done (its buffers).
+ * Single-threaded: every call on one server comes from one host thread.
  * ------------------------------------------------------------------------ */
 typedef struct gz_server_s *gz_server_t;
 
 typedef struct gz_server_opts {
-  uint64_t budget_bytes;  /* device arena for workspaces (default 96 GiB) */
+  void *arena;            /* device memory for the batches' workspaces, owned by the caller, 256-byte aligned */
+  uint64_t arena_bytes;   /* bytes at arena (at least 4096) */
+  uint64_t budget_bytes;  /* HBM budget of the jobs in flight: inputs + outputs + workspaces (0: arena_bytes) */
   uint32_t max_inflight;  /* batches in flight, one non-blocking stream each (default 4) */
   uint32_t max_batch;     /* jobs per batch (default 64) */
   gz_opts opts;           /* decompression options of every job */
@@ -391,7 +399,8 @@ typedef struct gz_server_opts {
 
 typedef struct gz_done {
   uint64_t tag;           /* as given to gz_server_submit */
-  int32_t status;         /* GZ_OK or a GZ_E_* code (GZ_E_CAPACITY: output too small, or larger than the budget) */
+  int32_t status;         /* GZ_OK or a GZ_E_* code (GZ_E_CAPACITY: output too small, or larger than the
+                             arena or the budget) */
   uint32_t pad;
   uint64_t out_len;       /* decompressed bytes written at d_out */
   double t_submit;        /* seconds since the server was created: submission, */
@@ -402,11 +411,13 @@ typedef struct gz_done {
 typedef struct gz_server_info {
   uint32_t queued, running, finished_unread, pad;
   uint64_t batches;       /* batches launched so far */
-  uint64_t arena_bytes, arena_used, arena_peak;
+  uint64_t arena_bytes, arena_used, arena_peak;  /* workspaces in the arena */
+  uint64_t budget_bytes, resident, resident_peak; /* footprints of the jobs in flight */
   double now;             /* seconds since creation */
 } gz_server_info;
 
-/* Errors: GZ_E_ARG, GZ_E_HIP (the arena or the streams could not be made). */
+/* Errors: GZ_E_ARG (no arena, or one not 256-byte aligned), GZ_E_HIP (the
+ * streams could not be made). */
 int gz_server_create(gz_server_t *server, const gz_server_opts *opts);
 /* Queue one job (plans it alone to estimate its workspace: reads its gzip
  * header and trailer).  Errors: GZ_E_ARG, GZ_E_HEADER, GZ_E_HIP. */

@@ -62,8 +62,8 @@ class Result(C.Structure):
 
 
 class ServerOpts(C.Structure):
-    _fields_ = [("budget_bytes", C.c_uint64), ("max_inflight", C.c_uint32), ("max_batch", C.c_uint32),
-                ("opts", Opts)]
+    _fields_ = [("arena", C.c_void_p), ("arena_bytes", C.c_uint64), ("budget_bytes", C.c_uint64),
+                ("max_inflight", C.c_uint32), ("max_batch", C.c_uint32), ("opts", Opts)]
 
 
 class Done(C.Structure):
@@ -77,7 +77,8 @@ class Done(C.Structure):
 class ServerInfo(C.Structure):
     _fields_ = [("queued", C.c_uint32), ("running", C.c_uint32), ("finished_unread", C.c_uint32),
                 ("pad", C.c_uint32), ("batches", C.c_uint64), ("arena_bytes", C.c_uint64),
-                ("arena_used", C.c_uint64), ("arena_peak", C.c_uint64), ("now", C.c_double)]
+                ("arena_used", C.c_uint64), ("arena_peak", C.c_uint64), ("budget_bytes", C.c_uint64),
+                ("resident", C.c_uint64), ("resident_peak", C.c_uint64), ("now", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
@@ -500,11 +501,19 @@ def autotune(comp, out: torch.Tensor | None = None, stream=None, **opts) -> dict
 
 class Server:
     """The serving loop of gz_server_*: submit jobs (device tensors), poll for
-    finished ones.  The tensors of a job are held until it is reported done."""
+    finished ones.  The tensors of a job are held until it is reported done.
+    The workspace arena (arena_bytes, default: the budget) is a torch tensor
+    owned here and handed to the library."""
 
-    def __init__(self, budget_bytes: int = 0, max_inflight: int = 0, max_batch: int = 0, device=None, **opts):
+    def __init__(self, budget_bytes: int = 0, max_inflight: int = 0, max_batch: int = 0, device=None,
+                 arena_bytes: int = 0, **opts):
         self.device = torch.device(device or "cuda:0")
+        budget_bytes = budget_bytes or (96 << 30)
+        arena_bytes = arena_bytes or budget_bytes
+        self.arena = torch.empty(arena_bytes, dtype=torch.uint8, device=self.device)
         o = ServerOpts()
+        o.arena = C.c_void_p(self.arena.data_ptr())
+        o.arena_bytes = arena_bytes
         o.budget_bytes = budget_bytes
         o.max_inflight = max_inflight
         o.max_batch = max_batch

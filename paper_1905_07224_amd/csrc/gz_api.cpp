@@ -127,6 +127,34 @@ int hip_fail(hipError_t e, const char *what) {
   return GZ_E_HIP;
 }
 
+// Device-to-host copy ordered on `st` only: the host waits for that stream,
+// not for work that other streams have in flight (a plain hipMemcpy may wait
+// for the whole device, which would stall a serving loop on the batches it
+// is running).
+hipError_t copy_to_host(void *dst, const void *src, size_t n, hipStream_t st) {
+  hipError_t e = hipMemcpyAsync(dst, src, n, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  return e;
+}
+
+// A non-blocking stream per device for the small reads made while planning
+// (gzip headers and trailers).
+std::mutex g_ctl_mu;
+hipStream_t g_ctl[64] = {};
+hipError_t control_stream(hipStream_t *st) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> g(g_ctl_mu);
+  if (!g_ctl[dev]) {
+    e = hipStreamCreateWithFlags(&g_ctl[dev], hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+  }
+  *st = g_ctl[dev];
+  return hipSuccess;
+}
+
 }  // namespace
 
 struct gz_plan_s {
@@ -185,6 +213,7 @@ struct gz_plan_s {
   // block-start probes (gz_plan_probes): file f searches [lo, hi) of the one input
   bool probe = false;
   std::vector<uint64_t> probe_lo, probe_hi;
+  bool dry = false;  // sizes only: no pinned job table (the serving loop's estimates)
 };
 
 // Header and trailer of the member at j.d_comp: payload start, CRC-32, ISIZE.
@@ -194,12 +223,15 @@ static int read_member(const gz_job &j, uint32_t f, int64_t *h_out, uint32_t *cr
     return j.d_comp ? GZ_E_HEADER : GZ_E_ARG;
   }
   // header bytes (grown if the optional fields are long) and the trailer
+  hipStream_t ctl = nullptr;
+  hipError_t ce = control_stream(&ctl);
+  if (ce != hipSuccess) return hip_fail(ce, "control stream");
   size_t hn = (size_t)std::min<uint64_t>(j.comp_len, 4096);
   std::vector<uint8_t> hb;
   int64_t h = -1;
   for (;;) {
     hb.resize(hn);
-    hipError_t e = hipMemcpy(hb.data(), j.d_comp, hn, hipMemcpyDeviceToHost);
+    hipError_t e = copy_to_host(hb.data(), j.d_comp, hn, ctl);
     if (e != hipSuccess) return hip_fail(e, "reading the gzip header");
     h = parse_gzip_header(hb.data(), hn);
     if (h >= 0 || hn == j.comp_len) break;
@@ -210,7 +242,7 @@ static int read_member(const gz_job &j, uint32_t f, int64_t *h_out, uint32_t *cr
     return GZ_E_HEADER;
   }
   uint8_t tr[8];
-  hipError_t e = hipMemcpy(tr, (const uint8_t *)j.d_comp + j.comp_len - 8, 8, hipMemcpyDeviceToHost);
+  hipError_t e = copy_to_host(tr, (const uint8_t *)j.d_comp + j.comp_len - 8, 8, ctl);
   if (e != hipSuccess) return hip_fail(e, "reading the gzip trailer");
   *h_out = h;
   *crc = (uint32_t)tr[0] | ((uint32_t)tr[1] << 8) | ((uint32_t)tr[2] << 16) | ((uint32_t)tr[3] << 24);
@@ -368,12 +400,15 @@ static int plan_common(gz_plan_t p) {
   o = align_up(o + nseg * WINDOW, 256);
   L.win_off = o;
   o = align_up(o + (uint64_t)N * WINDOW, 256);
+  L.carry_off = o;
+  o = align_up(o + (p->seg.on ? WINDOW : 0), 256);
   L.sym_off = o;
   L.sym_elems = sym_elems;
   o = align_up(o + sym_elems * 2, 256);
   L.total = o;
   // pinned copy of the job table (kept when a re-plan fits in it; the last
   // upload from it has finished before it is rewritten, see launch)
+  if (p->dry) return GZ_OK;
   if (p->pinned && p->pinned_bytes >= L.table_bytes) return GZ_OK;
   if (p->pinned) {
     if (p->upload_pending) {
@@ -430,7 +465,46 @@ static int make_plan(gz_plan_t *plan, const gz_job *jobs, int n, const gz_opts *
   return GZ_OK;
 }
 
+static void drop_graph(gz_plan_t p);
+
 extern "C" {
+
+// Internal to the library (the serving loop): the workspace a batch of jobs
+// needs, without creating a plan object (no pinned memory).
+int gzi_plan_ws(const gz_job *jobs, int n, const gz_opts *opts, uint64_t *ws_bytes) {
+  if (!jobs || n <= 0 || !ws_bytes) return GZ_E_ARG;
+  gz_plan_s p;
+  p.dry = true;
+  fill_defaults(&p, opts);
+  if (!valid_ring(p.win)) return GZ_E_ARG;
+  p.jobs.assign(jobs, jobs + n);
+  const int r = plan_common(&p);
+  if (r == GZ_OK) *ws_bytes = p.lay.total;
+  return r;
+}
+
+// Internal to the library (the serving loop): plan a batch into an existing
+// plan object whose last launch has finished, keeping its pinned job table
+// and events (allocating and freeing pinned memory may wait for the device).
+// *plan NULL: a new plan.
+int gzi_replan(gz_plan_t *plan, const gz_job *jobs, int n, const gz_opts *opts) {
+  if (!plan || !jobs || n <= 0) return GZ_E_ARG;
+  if (!*plan) return make_plan(plan, jobs, n, opts);
+  gz_plan_t p = *plan;
+  if (p->upload_pending) {
+    (void)hipEventSynchronize(p->upload_done);
+    p->upload_pending = false;
+  }
+  drop_graph(p);
+  p->launched = p->fetched = p->fetched_chunks = false;
+  p->timed = false;
+  const bool timing_events = p->opts.timing != 0;
+  fill_defaults(p, opts, false);
+  p->opts.timing = timing_events ? p->opts.timing : 0;
+  if (!valid_ring(p->win)) return GZ_E_ARG;
+  p->jobs.assign(jobs, jobs + n);
+  return plan_common(p);
+}
 
 int gz_plan(gz_plan_t *plan, const void *d_comp, size_t comp_len, int n_chunks, const gz_opts *opts) {
   if (!d_comp || comp_len == 0 || n_chunks < 0) return GZ_E_ARG;
@@ -501,7 +575,9 @@ int gz_plan_bgzf(gz_plan_t *plan, const void *d_comp, const void *h_comp, size_t
   const uint8_t *hb = (const uint8_t *)h_comp;
   if (!hb) {
     copy.resize(comp_len);
-    hipError_t e = hipMemcpy(copy.data(), d_comp, comp_len, hipMemcpyDeviceToHost);
+    hipStream_t ctl = nullptr;
+    hipError_t e = control_stream(&ctl);
+    if (e == hipSuccess) e = copy_to_host(copy.data(), d_comp, comp_len, ctl);
     if (e != hipSuccess) return hip_fail(e, "reading the input");
     hb = copy.data();
   }
@@ -808,7 +884,7 @@ static int fetch(gz_plan_t p) {
   if (e != hipSuccess) return hip_fail(e, "stream synchronize");
   const uint32_t F = (uint32_t)p->files.size();
   p->fst.resize(F);
-  e = hipMemcpy(p->fst.data(), p->ws + p->lay.fstate_off, F * sizeof(FileState), hipMemcpyDeviceToHost);
+  e = copy_to_host(p->fst.data(), p->ws + p->lay.fstate_off, F * sizeof(FileState), p->stream);
   if (e != hipSuccess) return hip_fail(e, "reading file state");
   p->fetched = true;
   p->fetched_chunks = false;
@@ -823,11 +899,10 @@ static int fetch_chunks(gz_plan_t p) {
   if (p->fetched_chunks) return GZ_OK;
   const uint32_t N = (uint32_t)p->chunks.size();
   p->cst.resize(N);
-  hipError_t e = hipMemcpy(p->cst.data(), p->ws + p->lay.cstate_off, (size_t)N * sizeof(ChunkState),
-                           hipMemcpyDeviceToHost);
+  hipError_t e = copy_to_host(p->cst.data(), p->ws + p->lay.cstate_off, (size_t)N * sizeof(ChunkState), p->stream);
   if (e != hipSuccess) return hip_fail(e, "reading chunk state");
   p->cdev.resize(N);
-  e = hipMemcpy(p->cdev.data(), p->ws + p->lay.chunks_off, (size_t)N * sizeof(ChunkDesc), hipMemcpyDeviceToHost);
+  e = copy_to_host(p->cdev.data(), p->ws + p->lay.chunks_off, (size_t)N * sizeof(ChunkDesc), p->stream);
   if (e != hipSuccess) return hip_fail(e, "reading chunk table");
   p->fetched_chunks = true;
   return GZ_OK;
@@ -1102,7 +1177,7 @@ struct gz_stream_s {
   uint64_t seg_bytes = 0;
   int64_t h = 0;
   uint32_t crc = 0, isize = 0;
-  uint8_t *d_win = nullptr;  // carried window, 32 KiB of device memory
+  uint8_t *h_win = nullptr;  // carried window: 32 KiB of pinned host memory, copied into each segment's workspace
   // position after the last finished segment: bytes of all members, and of
   // the current member (its CRC-32, its real history in the window)
   uint64_t bit = 0, out_total = 0, member_out = 0;
@@ -1185,8 +1260,9 @@ int gz_stream_open(gz_stream_t *stream, const void *d_comp, size_t comp_len, uin
   s->job.comp_len = comp_len;
   int r = read_member(s->job, 0, &s->h, &s->crc, &s->isize);
   if (r == GZ_OK) {
-    hipError_t e = hipMalloc((void **)&s->d_win, WINDOW);
-    if (e != hipSuccess) r = hip_fail(e, "stream window buffer");
+    hipError_t e = hipHostMalloc((void **)&s->h_win, WINDOW, hipHostMallocDefault);
+    if (e != hipSuccess) r = hip_fail(e, "stream window buffer (pinned host memory)");
+    else memset(s->h_win, 0, WINDOW);
   }
   if (r != GZ_OK) {
     gz_stream_destroy(s);
@@ -1228,16 +1304,18 @@ int gz_stream_next(gz_stream_t s, void *d_out, size_t out_cap, void *d_ws, size_
     return ws && ws_bytes < p->lay.total ? GZ_E_CAPACITY : GZ_E_ARG;
   }
   // the first chunk's window slot holds the carried window (nothing else
-  // writes that slot before window propagation reads it)
+  // writes that slot before window propagation reads it); the pinned copy is
+  // rewritten only after this segment has finished
   uint8_t *slot = ws + p->lay.win_off + (uint64_t)p->files[0].first_chunk * WINDOW;
   hipError_t e;
-  if (wv > 0 && (e = hipMemcpyAsync(slot, s->d_win, WINDOW, hipMemcpyDeviceToDevice, st)) != hipSuccess)
+  if (wv > 0 && (e = hipMemcpyAsync(slot, s->h_win, WINDOW, hipMemcpyHostToDevice, st)) != hipSuccess)
     return hip_fail(e, "carried window");
   r = launch(p, ws, ws_bytes, st);
   if (r == GZ_OK) {
-    // the next window: the last 32 KiB of (carried window ++ this output)
+    // the next window: the last 32 KiB of (carried window ++ this output),
+    // into the workspace's carry area (read back by gz_stream_wait)
     e = gzk_carry((const FileDesc *)(ws + p->lay.files_off), (const FileState *)(ws + p->lay.fstate_off), slot,
-                  s->d_win, st);
+                  ws + p->lay.carry_off, st);
     if (e != hipSuccess) r = hip_fail(e, "carry");
   }
   if (r != GZ_OK) return r;
@@ -1263,6 +1341,9 @@ int gz_stream_wait(gz_stream_t s, gz_segment_result *res) {
   res->out_needed = g.out_needed;
   res->member = s->member;
   if (g.status == GZ_OK) {
+    // the window after this segment, from the workspace's carry area
+    hipError_t e = copy_to_host(s->h_win, s->cur->ws + s->cur->lay.carry_off, WINDOW, s->cur->stream);
+    if (e != hipSuccess) return hip_fail(e, "reading the carried window");
     s->bit = fst.end_bit;
     s->out_total += g.out_len;
     s->member_out += g.out_len;
@@ -1318,10 +1399,7 @@ int gz_stream_checkpoint(gz_stream_t s, gz_checkpoint *cp) {
   cp->valid = s->valid;
   cp->done = s->done ? 1u : 0u;
   cp->flags = s->inside ? 1u : 0u;
-  if (s->valid > 0) {
-    hipError_t e = hipMemcpy(cp->window, s->d_win, WINDOW, hipMemcpyDeviceToHost);
-    if (e != hipSuccess) return hip_fail(e, "reading the window");
-  }
+  if (s->valid > 0) memcpy(cp->window, s->h_win, WINDOW);
   return GZ_OK;
 }
 
@@ -1332,10 +1410,7 @@ int gz_stream_resume(gz_stream_t s, const gz_checkpoint *cp) {
   if (cp->bit < lo || cp->bit > hi || cp->valid > WINDOW || (cp->flags & ~1u) || cp->member_out > cp->out_total ||
       cp->valid != (inside ? WINDOW : (uint32_t)std::min<uint64_t>(cp->member_out, WINDOW)))
     return GZ_E_ARG;
-  if (cp->valid > 0) {
-    hipError_t e = hipMemcpy(s->d_win, cp->window, WINDOW, hipMemcpyHostToDevice);
-    if (e != hipSuccess) return hip_fail(e, "writing the window");
-  }
+  if (cp->valid > 0) memcpy(s->h_win, cp->window, WINDOW);
   s->bit = cp->bit;
   s->out_total = cp->out_total;
   s->member_out = cp->member_out;
@@ -1360,13 +1435,7 @@ int gz_stream_open_at(gz_stream_t *stream, const void *d_comp, size_t comp_len, 
     return GZ_E_ARG;
   }
   // the undetermined context: 32768 copies of the marker
-  std::vector<uint8_t> w(WINDOW, (uint8_t)marker);
-  hipError_t e = hipMemcpy(s->d_win, w.data(), WINDOW, hipMemcpyHostToDevice);
-  if (e != hipSuccess) {
-    gz_stream_destroy(s);
-    *stream = nullptr;
-    return hip_fail(e, "writing the window");
-  }
+  memset(s->h_win, (int)marker, WINDOW);
   s->bit = block_bit;
   s->inside = true;
   s->valid = WINDOW;
@@ -1379,7 +1448,7 @@ void gz_stream_destroy(gz_stream_t s) {
     if (s->pending) (void)hipStreamSynchronize(s->cur->stream);
     gz_plan_destroy(s->cur);
   }
-  if (s->d_win) (void)hipFree(s->d_win);
+  if (s->h_win) (void)hipHostFree(s->h_win);
   delete s;
 }
 

@@ -182,6 +182,7 @@ struct Layout {
   uint64_t maps_off;       // uint16[2][S][32768] propagation segment maps and their prefix compositions, S = ceil(N / 64)
   uint64_t segwin_off;     // uint8[S][32768] input window of each propagation segment
   uint64_t win_off;        // uint8[N][32768] resolved windows
+  uint64_t carry_off;      // uint8[32768] the window after the last chunk (bounded-memory streaming)
   uint64_t sym_off;        // uint16 symbol pool
   uint64_t sym_elems;
   uint64_t total;

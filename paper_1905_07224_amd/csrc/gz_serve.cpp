@@ -1,9 +1,10 @@
 // Serving loop over the two-pass path: jobs (a compressed input already in
 // device memory, and an output buffer) are queued, admitted into batches
-// while their workspaces fit in a fixed device arena (the HBM budget), and
-// run as batched launch sequences on a few streams at once; a batch that
-// finishes frees its arena block for the jobs queued behind it.  See
-// include/gzgpu.h.
+// while their footprints (input, output and workspace) fit in the HBM budget
+// and their workspaces fit in the caller's device arena, and run as batched
+// launch sequences on a few streams at once; a batch that finishes frees its
+// arena block and its share of the budget for the jobs queued behind it.
+// The library allocates no device memory here.  See include/gzgpu.h.
 #include <hip/hip_runtime.h>
 #include <string.h>
 
@@ -15,6 +16,12 @@
 #include <vector>
 
 #include "../../include/gzgpu.h"
+
+// internal to the library (gz_api.cpp): sizing without a plan object, and
+// re-planning a finished plan in place (no pinned memory allocated or freed,
+// which could wait for the device while other batches run)
+extern "C" int gzi_plan_ws(const gz_job *jobs, int n, const gz_opts *opts, uint64_t *ws_bytes);
+extern "C" int gzi_replan(gz_plan_t *plan, const gz_job *jobs, int n, const gz_opts *opts);
 
 namespace {
 
@@ -77,6 +84,7 @@ struct Job {
   uint64_t out_cap;
   uint64_t tag;
   uint64_t ws;       // workspace of this job planned alone (admission estimate)
+  uint64_t foot() const { return comp_len + out_cap + ws; }  // device bytes while it is in flight
   uint32_t factor;   // symbol capacity factor (raised after a capacity failure)
   double t_submit;
   double t_start;
@@ -86,6 +94,7 @@ struct Batch {
   gz_plan_t plan = nullptr;
   std::vector<Job> jobs;
   uint64_t off = 0, bytes = 0;
+  uint64_t foot = 0;  // inputs + outputs + the batch's workspace
   int slot = 0;
 };
 
@@ -103,10 +112,12 @@ struct gz_server_s {
   std::vector<hipStream_t> streams;
   std::vector<hipEvent_t> events;
   std::vector<bool> busy;
+  std::vector<gz_plan_t> plans;  // one per stream, re-planned for each batch it runs
   std::deque<Job> queue;
   std::vector<Batch> running;
   std::vector<gz_done> done;  // finished, not yet returned by poll
   uint64_t n_batches = 0;
+  uint64_t resident = 0, resident_peak = 0;  // footprint of the batches in flight
 };
 
 namespace {
@@ -115,14 +126,10 @@ int plan_ws(const Job &j, const gz_opts &base, uint64_t *ws) {
   gz_opts o = base;
   o.sym_factor = j.factor;
   o.timing = 0;
-  gz_plan_t p = nullptr;
-  int r = gz_plan(&p, j.comp, j.comp_len, 0, &o);
-  if (r != GZ_OK) return r;
-  gz_info inf;
-  gz_plan_info(p, &inf);
-  gz_plan_destroy(p);
-  *ws = inf.ws_bytes;
-  return GZ_OK;
+  gz_job g{};
+  g.d_comp = j.comp;
+  g.comp_len = j.comp_len;
+  return gzi_plan_ws(&g, 1, &o, ws);
 }
 
 void finish_job(gz_server_t s, const Job &j, int status, uint64_t out_len) {
@@ -159,8 +166,9 @@ void reap(gz_server_t s) {
       }
       finish_job(s, j, r == GZ_OK ? res.status : r, r == GZ_OK ? res.out_len : 0);
     }
-    gz_plan_destroy(B.plan);
+    // the plan stays with its stream for the next batch
     s->arena.release(B.off, B.bytes);
+    s->resident -= B.foot;
     s->busy[B.slot] = false;
     s->running.erase(s->running.begin() + (long)b);
   }
@@ -178,19 +186,23 @@ int admit(gz_server_t s) {
       }
     if (slot < 0) return GZ_OK;
     const uint64_t room = s->arena.largest();
-    if (s->queue.front().ws + 4096 > s->arena.size) {
-      // larger than the whole budget: it can never run
+    if (s->queue.front().ws + 4096 > s->arena.size || s->queue.front().foot() + 4096 > s->o.budget_bytes) {
+      // larger than the whole arena or budget: it can never run
       Job j = s->queue.front();
       s->queue.pop_front();
       j.t_start = now_s(s->t0);
       finish_job(s, j, GZ_E_CAPACITY, 0);
       continue;
     }
-    // the longest FIFO prefix whose summed estimates fit (table overhead aside)
+    // the longest FIFO prefix whose summed workspaces fit the arena and whose
+    // footprints fit what the budget has left (table overhead aside)
+    const uint64_t left = s->o.budget_bytes - s->resident;
     size_t n = 0;
-    uint64_t sum = 0;
-    while (n < s->queue.size() && n < s->o.max_batch && sum + s->queue[n].ws + 4096 * (n + 1) <= room) {
+    uint64_t sum = 0, foot = 0;
+    while (n < s->queue.size() && n < s->o.max_batch && sum + s->queue[n].ws + 4096 * (n + 1) <= room &&
+           foot + s->queue[n].foot() + 4096 * (n + 1) <= left) {
       sum += s->queue[n].ws;
+      foot += s->queue[n].foot();
       n++;
     }
     if (n == 0) return GZ_OK;  // wait for memory
@@ -209,8 +221,8 @@ int admit(gz_server_t s) {
       gz_opts o = s->o.opts;
       o.sym_factor = factor;
       o.timing = 0;
-      gz_plan_t p = nullptr;
-      int r = gz_plan_batch(&p, jobs.data(), (int)n, &o);
+      int r = gzi_replan(&s->plans[slot], jobs.data(), (int)n, &o);
+      gz_plan_t p = s->plans[slot];
       if (r != GZ_OK) {
         if (n > 1) continue;
         Job j = s->queue.front();
@@ -223,7 +235,6 @@ int admit(gz_server_t s) {
       gz_plan_info(p, &inf);
       uint64_t off = 0;
       if (!s->arena.alloc(inf.ws_bytes, &off)) {
-        gz_plan_destroy(p);
         if (n > 1) continue;
         return GZ_OK;  // wait for memory
       }
@@ -231,21 +242,24 @@ int admit(gz_server_t s) {
       B.plan = p;
       B.off = off;
       B.bytes = inf.ws_bytes;
+      B.foot = inf.ws_bytes;
       B.slot = slot;
       const double t = now_s(s->t0);
       for (size_t i = 0; i < n; i++) {
         B.jobs.push_back(s->queue.front());
         B.jobs.back().t_start = t;
+        B.foot += s->queue.front().comp_len + s->queue.front().out_cap;
         s->queue.pop_front();
       }
       r = gz_decompress_batch(p, s->base + off, inf.ws_bytes, s->streams[slot]);
       if (r == GZ_OK && hipEventRecord(s->events[slot], s->streams[slot]) != hipSuccess) r = GZ_E_HIP;
       if (r != GZ_OK) {
         for (const Job &j : B.jobs) finish_job(s, j, r, 0);
-        gz_plan_destroy(p);
         s->arena.release(off, inf.ws_bytes);
         return r;
       }
+      s->resident += B.foot;
+      s->resident_peak = std::max(s->resident_peak, s->resident);
       s->busy[slot] = true;
       s->running.push_back(std::move(B));
       s->n_batches++;
@@ -263,17 +277,18 @@ int gz_server_create(gz_server_t *srv, const gz_server_opts *opts) {
   *srv = nullptr;
   gz_server_t s = new (std::nothrow) gz_server_s();
   if (!s) return GZ_E_ARG;
-  if (opts) s->o = *opts;
-  if (!s->o.budget_bytes) s->o.budget_bytes = 96ull << 30;
+  if (!opts || !opts->arena || opts->arena_bytes < 4096 || ((uintptr_t)opts->arena & (ALIGN - 1))) {
+    delete s;
+    return GZ_E_ARG;
+  }
+  s->o = *opts;
+  if (!s->o.budget_bytes) s->o.budget_bytes = s->o.arena_bytes;
   if (!s->o.max_inflight) s->o.max_inflight = 4;
   if (!s->o.max_batch) s->o.max_batch = 64;
   if (!s->o.opts.sym_factor) s->o.opts.sym_factor = 8;
   s->t0 = std::chrono::steady_clock::now();
-  if (hipMalloc((void **)&s->base, s->o.budget_bytes) != hipSuccess) {
-    delete s;
-    return GZ_E_HIP;
-  }
-  s->arena.init(s->o.budget_bytes);
+  s->base = (uint8_t *)s->o.arena;
+  s->arena.init(s->o.arena_bytes);
   for (uint32_t k = 0; k < s->o.max_inflight; k++) {
     hipStream_t st = nullptr;
     hipEvent_t ev = nullptr;
@@ -286,6 +301,7 @@ int gz_server_create(gz_server_t *srv, const gz_server_opts *opts) {
     s->streams.push_back(st);
     s->events.push_back(ev);
     s->busy.push_back(false);
+    s->plans.push_back(nullptr);
   }
   *srv = s;
   return GZ_OK;
@@ -329,6 +345,9 @@ int gz_server_stats(gz_server_t s, gz_server_info *info) {
   info->arena_bytes = s->arena.size;
   info->arena_used = s->arena.used;
   info->arena_peak = s->arena.peak;
+  info->budget_bytes = s->o.budget_bytes;
+  info->resident = s->resident;
+  info->resident_peak = s->resident_peak;
   info->now = now_s(s->t0);
   return GZ_OK;
 }
@@ -336,10 +355,9 @@ int gz_server_stats(gz_server_t s, gz_server_info *info) {
 void gz_server_destroy(gz_server_t s) {
   if (!s) return;
   for (size_t k = 0; k < s->streams.size(); k++) (void)hipStreamSynchronize(s->streams[k]);
-  for (Batch &B : s->running) gz_plan_destroy(B.plan);
+  for (gz_plan_t p : s->plans) gz_plan_destroy(p);
   for (hipEvent_t e : s->events) (void)hipEventDestroy(e);
   for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
-  if (s->base) (void)hipFree(s->base);
   delete s;
 }
 

@@ -102,8 +102,8 @@ def run(comp: bytes, n_chunks: int, out_cap=None, sync_limit=0, **opts):
 
 
 class ServerOpts(C.Structure):
-    _fields_ = [("budget_bytes", C.c_uint64), ("max_inflight", C.c_uint32), ("max_batch", C.c_uint32),
-                ("opts", Opts)]
+    _fields_ = [("arena", C.c_void_p), ("arena_bytes", C.c_uint64), ("budget_bytes", C.c_uint64),
+                ("max_inflight", C.c_uint32), ("max_batch", C.c_uint32), ("opts", Opts)]
 
 
 class Done(C.Structure):
@@ -114,7 +114,8 @@ class Done(C.Structure):
 class ServerInfo(C.Structure):
     _fields_ = [("queued", C.c_uint32), ("running", C.c_uint32), ("finished_unread", C.c_uint32),
                 ("pad", C.c_uint32), ("batches", C.c_uint64), ("arena_bytes", C.c_uint64),
-                ("arena_used", C.c_uint64), ("arena_peak", C.c_uint64), ("now", C.c_double)]
+                ("arena_used", C.c_uint64), ("arena_peak", C.c_uint64), ("budget_bytes", C.c_uint64),
+                ("resident", C.c_uint64), ("resident_peak", C.c_uint64), ("now", C.c_double)]
 
 
 def server_lib():

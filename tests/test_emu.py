@@ -131,10 +131,17 @@ def test_emu_serving_loop_budget_and_order():
     info = E.Info()
     L.gz_plan_info(probe, C.byref(info))
     L.gz_plan_destroy(probe)
-    o.budget_bytes = int(info.ws_bytes * 2.6)
+    # the arena is the caller's (the library allocates no device memory)
+    arena_bytes = int(info.ws_bytes * 2.6)
+    raw_arena = np.zeros(arena_bytes + 512, dtype=np.uint8)
+    arena = raw_arena[(-raw_arena.ctypes.data) % 256:][:arena_bytes]
+    h = C.c_void_p()
+    assert L.gz_server_create(C.byref(h), C.byref(o)) == -1  # GZ_E_ARG: no arena
+    o.arena = C.c_void_p(arena.ctypes.data)
+    o.arena_bytes = arena_bytes
+    o.budget_bytes = 0  # the arena's size
     o.max_inflight = 2
     o.max_batch = 2
-    h = C.c_void_p()
     assert L.gz_server_create(C.byref(h), C.byref(o)) == 0
     for k, (r, c) in enumerate(zip(raws, comps)):
         n = len(synth.gzip_member(r, 6))
@@ -161,7 +168,9 @@ def test_emu_serving_loop_budget_and_order():
     # admitted in submission order, never more workspace than the budget
     starts = [t for _, _, _, t in sorted(done)]
     assert starts == sorted(starts)
-    assert st.arena_peak <= o.budget_bytes and st.batches >= 3
+    assert st.arena_peak <= arena_bytes and st.batches >= 3
+    # the budget counts inputs, outputs and workspaces of the jobs in flight
+    assert 0 < st.resident_peak <= st.budget_bytes == arena_bytes
 
 
 @pytest.mark.parametrize("decode", [0, 1])
@@ -527,3 +536,50 @@ def test_emu_room_of_empty_chunks(orc, case):
         tab = _same_as_oracle(orc, gz, raw, n)
         k = int(np.nonzero(_starts(tab) == dbit)[0][0])
         assert k >= 1 and tab["flags"][k] & 64 and tab["flags"][k + 1] & 2
+
+
+def test_emu_serving_budget_counts_footprints():
+    """With an arena far larger than the budget, admission is bounded by the
+    budget over the jobs' inputs, outputs and workspaces: one job at a time."""
+    import ctypes as C
+
+    L = E.server_lib()
+    raws = [synth.fastq_like(12 << 10, 330 + k) for k in range(3)]
+    gzs = [synth.gzip_member(r, 6) for r in raws]
+    comps = [E.padded(g) for g in gzs]
+    outs = [np.zeros(len(r) + 64, dtype=np.uint8) for r in raws]
+    o = E.ServerOpts()
+    o.opts.chunk_bytes = 4096
+    probe = C.c_void_p()
+    L.gz_plan(C.byref(probe), C.c_void_p(comps[0].ctypes.data), len(gzs[0]), 0, C.byref(o.opts))
+    info = E.Info()
+    L.gz_plan_info(probe, C.byref(info))
+    L.gz_plan_destroy(probe)
+    foot = len(gzs[0]) + outs[0].size + info.ws_bytes
+    arena_bytes = 8 * info.ws_bytes
+    raw_arena = np.zeros(arena_bytes + 512, dtype=np.uint8)
+    arena = raw_arena[(-raw_arena.ctypes.data) % 256:][:arena_bytes]
+    o.arena = C.c_void_p(arena.ctypes.data)
+    o.arena_bytes = arena_bytes
+    o.budget_bytes = int(foot * 1.5)
+    o.max_inflight = 3
+    o.max_batch = 3
+    h = C.c_void_p()
+    assert L.gz_server_create(C.byref(h), C.byref(o)) == 0
+    for k in range(3):
+        assert L.gz_server_submit(h, C.c_void_p(comps[k].ctypes.data), len(gzs[k]), C.c_void_p(outs[k].ctypes.data),
+                                  outs[k].size, k) == 0
+    buf = (E.Done * 8)()
+    done = []
+    for _ in range(50):
+        n = L.gz_server_poll(h, buf, 8)
+        assert n >= 0
+        done += [(buf[i].tag, buf[i].status) for i in range(n)]
+        if len(done) == 3:
+            break
+    st = E.ServerInfo()
+    L.gz_server_stats(h, C.byref(st))
+    L.gz_server_destroy(h)
+    assert sorted(done) == [(0, 0), (1, 0), (2, 0)]
+    assert all(outs[k][: len(raws[k])].tobytes() == raws[k] for k in range(3))
+    assert st.batches == 3 and st.resident_peak <= o.budget_bytes and st.arena_peak < arena_bytes // 2

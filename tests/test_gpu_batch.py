@@ -163,3 +163,46 @@ def test_serving_mix_equals_alone(files):
         assert got == alone[k] == files[k][0]
         assert d["t_submit"] <= d["t_start"] <= d["t_end"]
     assert st["arena_peak"] <= budget and st["batches"] >= 2
+    assert st["resident_peak"] <= budget
+
+
+def test_serving_admits_while_batches_run(files):
+    """Continuous batching: jobs submitted while earlier batches are still on
+    the GPU are admitted into batches that run beside them (a job starts
+    before a job admitted earlier has finished), and each result equals the
+    job decoded alone."""
+    import time
+
+    gz = _gz()
+    _say("serving loop, arrivals during running batches")
+    comps = [_dev(c) for _, c in files]
+    alone = [gz.decompress(c, 0).cpu().numpy().tobytes() for c in comps]
+    srv = gz.Server(budget_bytes=8 << 30, max_inflight=4, max_batch=2)
+    outs, want, running_at_submit = {}, {}, []
+    order = [4, 3, 4, 3, 2, 1, 0, 4, 3, 2, 1, 0]
+    done = []
+    t0 = time.time()
+    for tag, k in enumerate(order):
+        outs[tag] = torch.zeros(len(files[k][0]) + 32, dtype=torch.uint8, device="cuda:0")
+        want[tag] = k
+        if tag >= 2:
+            # later jobs arrive while what was admitted before is on the GPU
+            while srv.stats()["running"] == 0 and time.time() - t0 < 30:
+                done += srv.poll()
+            running_at_submit.append(srv.stats()["running"])
+        srv.submit(comps[k], outs[tag], tag)
+        done += srv.poll()
+    while len(done) < len(order) and time.time() - t0 < 60:
+        done += srv.poll()
+        time.sleep(0.0002)
+    srv.close()
+    assert len(done) == len(order)
+    for d in done:
+        k = want[d["tag"]]
+        assert d["status"] == 0
+        assert outs[d["tag"]][: d["out_len"]].cpu().numpy().tobytes() == alone[k] == files[k][0]
+    assert all(r > 0 for r in running_at_submit)
+    by = {d["tag"]: d for d in done}
+    overlap = [(a, b) for a in by for b in by if b > a and by[b]["t_submit"] > by[a]["t_start"]
+               and by[b]["t_start"] < by[a]["t_end"]]
+    assert overlap, "no job was admitted while an earlier one ran"
