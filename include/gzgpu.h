@@ -127,6 +127,20 @@ int gz_plan_info(gz_plan_t plan, gz_info *info);
  * GZ_E_CAPACITY (ws_bytes too small), GZ_E_HIP. */
 int gz_decompress(gz_plan_t plan, void *d_out, size_t out_cap, void *d_ws, size_t ws_bytes, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * as gz_decompress, with the workspace taken from a static device array of
+ * GZ_SCRATCH_BYTES bytes that each GPU the library runs on holds until the
+ * process ends.  Allocates nothing.  The plan must belong to the current
+ * device.  Every call on one GPU uses that GPU's one array, so calls that
+ * overlap on one GPU race (use it from one stream at a time); each call
+ * clears what it reads before writing it, so nothing carries over from the
+ * last call.  Errors: GZ_E_ARG (a batch, probe or stream plan, or another
+ * device), GZ_E_CAPACITY (the plan's ws_bytes above GZ_SCRATCH_BYTES),
+ * GZ_E_HIP. */
+#define GZ_SCRATCH_BYTES 268435456 /* 256 MiB */
+int gz_decompress_static(gz_plan_t plan, void *d_out, size_t out_cap, void *stream);
+
 /* Enqueue the path for every file of a batch plan, outputs at the jobs'
  * d_out.  One launch per pass covers all files and chunks. */
 int gz_decompress_batch(gz_plan_t plan, void *d_ws, size_t ws_bytes, void *stream);

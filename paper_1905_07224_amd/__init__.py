@@ -118,8 +118,9 @@ EXPORTS = ["gz_plan", "gz_plan_batch", "gz_plan_info", "gz_decompress", "gz_deco
            "gz_server_poll", "gz_server_stats", "gz_server_destroy", "gz_stream_open", "gz_stream_get_info",
            "gz_stream_next", "gz_stream_wait", "gz_stream_checkpoint", "gz_stream_resume", "gz_stream_destroy",
            "gz_plan_probes", "gz_find_blocks", "gz_probe_starts", "gz_stream_open_at", "gz_count_byte",
-           "gz_plan_bgzf", "gz_chunk_stats"]
+           "gz_plan_bgzf", "gz_chunk_stats", "gz_decompress_static"]
 GZ_N_PASSES = N_PASSES = 13
+GZ_SCRATCH_BYTES = 256 << 20  # static workspace of gz_decompress_static, per GPU
 # defaults of gz_opts (include/gzgpu.h)
 DEFAULT_CHUNK_BYTES = 40 << 10
 DEFAULT_WINDOW = 1024
@@ -142,6 +143,7 @@ def lib():
         L.gz_result_get.argtypes = [vp, i32, C.POINTER(Result)]
         L.gz_chunk_table.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp]
         L.gz_chunk_stats.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.gz_decompress_static.argtypes = [vp, vp, C.c_size_t, vp]
         L.gz_debug_layout.argtypes = [vp, i32, vp, vp, C.POINTER(vp), C.POINTER(vp)]
         L.gz_plan_destroy.argtypes = [vp]
         L.gz_plan_destroy.restype = None
@@ -262,6 +264,14 @@ class Plan:
         with torch.cuda.device(self.device):
             _check(lib().gz_decompress(self._h, optr, ocap, C.c_void_p(ws.data_ptr()), ws.numel(),
                                        _stream_handle(stream)))
+
+    def launch_static(self, out: torch.Tensor | None, stream=None):
+        """Like launch(), with the library's static per-GPU workspace
+        (gz_decompress_static: nothing is allocated)."""
+        optr = C.c_void_p(out.data_ptr()) if out is not None and out.numel() else C.c_void_p()
+        ocap = out.numel() if out is not None else 0
+        with torch.cuda.device(self.device):
+            _check(lib().gz_decompress_static(self._h, optr, ocap, _stream_handle(stream)))
 
     def launch_graph(self, out: torch.Tensor | None, stream):
         """Like launch(), through the plan's captured HIP graph (captured again

@@ -40,6 +40,7 @@ hipError_t gzk_propagate(uint32_t, const uint32_t *, const AccEntry *, uint8_t *
 hipError_t gzk_translate(uint32_t, const FileDesc *, const ChunkDesc *, const ChunkState *, FileState *,
                          const uint64_t *, uint32_t, const uint8_t *, const uint16_t *, Counters *, hipStream_t);
 hipError_t gzk_carry(const FileDesc *, const FileState *, const uint8_t *, uint8_t *, hipStream_t);
+hipError_t gzk_scratch(void **);
 hipError_t gzk_count_byte(const uint8_t *, uint64_t, uint32_t, uint64_t, uint64_t, unsigned long long *, uint64_t,
                           hipStream_t);
 }
@@ -805,6 +806,29 @@ int gz_decompress(gz_plan_t p, void *d_out, size_t out_cap, void *d_ws, size_t w
   p->files[0].out = (uint8_t *)d_out;
   p->files[0].out_cap = d_out ? out_cap : 0;
   return launch(p, (uint8_t *)d_ws, ws_bytes, (hipStream_t)stream);
+}
+
+static_assert(SCRATCH_BYTES == GZ_SCRATCH_BYTES, "static workspace size");
+
+int gz_decompress_static(gz_plan_t p, void *d_out, size_t out_cap, void *stream) {
+  if (!p || p->files.size() != 1 || p->probe || p->seg.on) return GZ_E_ARG;
+  if (!d_out && out_cap) return GZ_E_ARG;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != p->device) {
+    snprintf(g_err, sizeof(g_err), "the plan belongs to device %d, the current device is %d", p->device, dev);
+    return GZ_E_ARG;
+  }
+  if (p->lay.total > SCRATCH_BYTES) {
+    snprintf(g_err, sizeof(g_err), "workspace of %llu bytes exceeds the static workspace of %llu bytes",
+             (unsigned long long)p->lay.total, (unsigned long long)SCRATCH_BYTES);
+    return GZ_E_CAPACITY;
+  }
+  void *ws = nullptr;
+  const hipError_t e = gzk_scratch(&ws);
+  if (e != hipSuccess) return hip_fail(e, "static workspace address");
+  p->files[0].out = (uint8_t *)d_out;
+  p->files[0].out_cap = d_out ? out_cap : 0;
+  return launch(p, (uint8_t *)ws, SCRATCH_BYTES, (hipStream_t)stream);
 }
 
 int gz_decompress_batch(gz_plan_t p, void *d_ws, size_t ws_bytes, void *stream) {

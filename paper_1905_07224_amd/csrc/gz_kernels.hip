@@ -14,6 +14,7 @@
 //   k_translate  pass 2b: every U_j replaced by w_i[j], written to the output
 #include <hip/hip_runtime.h>
 
+#include <mutex>
 #include <type_traits>
 
 #include "gz_device.h"
@@ -1918,7 +1919,39 @@ __global__ __launch_bounds__(256) void k_count_byte(const uint8_t *__restrict__ 
 
 using namespace gzgpu;
 
+// ---------------------------------------------------------------------------
+// Workspace for the entry point that allocates nothing (gz_decompress_static):
+// a static device array, one per GPU the library runs on, held until the
+// process ends.  Host code must not use the array's name as an address: the
+// device address of each GPU's copy is looked up once per device, with that
+// device current, and cached.
+// ---------------------------------------------------------------------------
+
+static __device__ __align__(256) uint8_t scratch[SCRATCH_BYTES];
+
+namespace {
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[64] = {};
+}  // namespace
+
 extern "C" {
+
+// The current device's scratch address (looked up on the first call there).
+hipError_t gzk_scratch(void **ptr) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *q = nullptr;
+    e = hipGetSymbolAddress(&q, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = q;
+  }
+  *ptr = g_scratch_ptr[dev];
+  return hipSuccess;
+}
 
 hipError_t gzk_init(ChunkState *cs, uint32_t n_chunks, FileState *fs, uint32_t n_files, Counters *ctr,
                     hipStream_t st) {

@@ -583,3 +583,30 @@ def test_emu_serving_budget_counts_footprints():
     assert sorted(done) == [(0, 0), (1, 0), (2, 0)]
     assert all(outs[k][: len(raws[k])].tobytes() == raws[k] for k in range(3))
     assert st.batches == 3 and st.resident_peak <= o.budget_bytes and st.arena_peak < arena_bytes // 2
+
+
+def test_emu_static_workspace_entry_point():
+    """gz_decompress_static (the entry point that allocates nothing) on the
+    CPU executor: the same bytes and chunk starts as gz_decompress, twice in a
+    row, the second input smaller."""
+    import ctypes as C
+
+    L = E.lib()
+    L.gz_decompress_static.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]
+    for k, raw in enumerate([synth.fastq_like(96 << 10, 340), synth.word_stream(40 << 10, 341)]):
+        comp = synth.gzip_member(raw, 6)
+        st, want, r, tab = E.run(comp, 3, out_cap=len(raw) + 64)
+        assert st == 0 and want == raw
+        store = E.padded(comp)
+        h = C.c_void_p()
+        assert L.gz_plan(C.byref(h), C.c_void_p(store.ctypes.data), len(comp), 3, C.byref(E.Opts())) == 0
+        out = np.full(len(raw) + 64, 0xAB, dtype=np.uint8)
+        assert L.gz_decompress_static(h, C.c_void_p(out.ctypes.data), out.size, None) == 0
+        res = E.Result()
+        assert L.gz_result_get(h, 0, C.byref(res)) == 0
+        starts = np.zeros(3, dtype=np.uint64)
+        assert L.gz_chunk_table(h, 0, C.c_void_p(starts.ctypes.data), None, None, None, None, None, None) == 0
+        L.gz_plan_destroy(h)
+        assert res.status == 0 and out[: res.out_len].tobytes() == raw
+        assert (out[res.out_len:] == 0xAB).all()
+        assert np.array_equal(starts, tab["start"]), k
