@@ -183,6 +183,22 @@ struct WaveBits {
 #pragma unroll
     for (int i = 0; i < 6; i++) q[i] = (uint32_t)((((uint64_t)w[i + 1] << 32) | w[i]) >> sh);
   }
+  // Per lane k: the 64 stream bits from pos + k (wa) and from pos + 64 + k
+  // (wb), gathered with one ds_bpermute per dword from the lanes that hold
+  // them (dwords D .. D + 6 of pos lie in the window after refill(), and
+  // lanes are indexed by dword mod 64, so the low 32 bits of the position
+  // suffice).  All vector work: no value goes through scalar registers.
+  __device__ __forceinline__ void lane_windows(uint64_t &wa, uint64_t &wb) {
+    refill();
+    const uint32_t ak = (uint32_t)pos + 8u * s.mis + (uint32_t)lane_id();
+    const uint32_t sh = ak & 31u;
+    const uint32_t d = ak >> 5;
+    uint32_t x[5];
+#pragma unroll
+    for (int i = 0; i < 5; i++) x[i] = (uint32_t)__builtin_amdgcn_ds_bpermute((int)(((d + (uint32_t)i) & 63u) << 2), (int)win);
+    wa = ((uint64_t)__builtin_amdgcn_alignbit(x[2], x[1], sh) << 32) | __builtin_amdgcn_alignbit(x[1], x[0], sh);
+    wb = ((uint64_t)__builtin_amdgcn_alignbit(x[4], x[3], sh) << 32) | __builtin_amdgcn_alignbit(x[3], x[2], sh);
+  }
   __device__ __forceinline__ void skip(uint32_t n) { pos += n; }
   __device__ __forceinline__ bool past_end() const { return pos > s.end_bits; }
 };

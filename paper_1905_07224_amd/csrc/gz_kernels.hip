@@ -272,12 +272,14 @@ struct Inflater {
   // Token words of one lookup round (per lane k: the token that would start
   // at bit offset k): bits 7..0 the bits it uses (at most 48), bits 16..8
   // its output length (1: a literal), bits 31..17 the literal byte or the
-  // match distance minus one (0..32767).  The low 17 bits are what a token
-  // adds to the walk's packed (output symbols << 8 | bit offset) counter.
-  // A special token has length 511, so that adding it ends any walk, and
-  // its kind in bits 31..17 (end-of-block: its code length in bits 7..0).
-  static constexpr uint32_t TOK_STEP = 0x1FFFFu;
-  static constexpr uint32_t TOK_SPECIAL = 511u << 8;
+  // match distance minus one (0..32767).  The walk adds whole token words to
+  // its packed (output symbols << 8 | bit offset) counter: the low 17 bits
+  // hold the counter (fewer than 64 + 258 symbols, offsets below 256), the
+  // bits above only collect the payloads and are never read.  A special
+  // token has length 448: added to fewer than 64 symbols it sets bits 14..16
+  // of the counter, which ends any walk, and stays below bit 17; its kind is
+  // in bits 31..17 (end-of-block: its code length in bits 7..0).
+  static constexpr uint32_t TOK_SPECIAL = 448u << 8;
   static constexpr uint32_t TOK_EOB = TOK_SPECIAL | (1u << 17);
   static constexpr uint32_t TOK_SLOW = TOK_SPECIAL | (2u << 17);   // longer code, or invalid: decoded alone
   static constexpr uint32_t TOK_ASCII = TOK_SPECIAL | (3u << 17);  // non-ASCII literal in a checked block
@@ -328,6 +330,12 @@ struct Inflater {
   // lane finds its token (the last start at or before it) and takes its
   // source from the token's word.  CHECK: literals must be ASCII text
   // (block-start trial and confirmation).
+  //
+  // A batch is not tied to a round: when the walk reaches the end of a round
+  // before the batch has 64 symbols, the next round is decoded and the walk
+  // goes on filling the same batch, so that the per-batch work (source
+  // selection, pointer jumping, ring and HBM stores) is paid once per 64
+  // symbols and not once per round.
   template <bool CHECK>
   __device__ int huffman(uint64_t size_cap, uint64_t blk0) {
     const int lane = lane_id();
@@ -335,23 +343,20 @@ struct Inflater {
     uint32_t off = 0;   // bit offset of the walk from br.pos, where the round was decoded
     bool need = true;   // a round to be decoded at br.pos + off
     uint32_t rem = 0, mdist = 0;  // part of a match still to be produced
-    // a batch consumes at least one bit or produces 64 symbols (<= 258 per
-    // code): the remaining bits bound the batches
+    // the batch being assembled: start lanes' token words, symbols so far,
+    // and whether it began with the rest of a match (open: being assembled)
+    uint32_t word = 0, jr = 0, cont = 0;
+    bool open = false;
+    // an iteration consumes at least one bit or produces 64 symbols (<= 258
+    // per code): the remaining bits bound the iterations
     const uint64_t budget = 8ull * (br.s.end_bits - br.pos + 64);
     for (uint64_t it = 0;; it++) {
       if (it > budget) return D_BAD;
       if (need) {
         br.pos += off;
-        uint32_t q[6];
-        br.view192(q);
-        const bool lo_half = lane < 32;
-        const uint32_t sh = (uint32_t)lane & 31u;
-        // offsets k (dwords 0..3) and k + 64 (dwords 2..5)
-        const uint32_t a0 = lo_half ? q[0] : q[1], a1 = lo_half ? q[1] : q[2], a2 = lo_half ? q[2] : q[3];
-        const uint32_t b2 = lo_half ? q[4] : q[5];
-        const uint32_t b0 = a2, b1 = lo_half ? q[3] : q[4];
-        const uint64_t wa = ((uint64_t)__builtin_amdgcn_alignbit(a2, a1, sh) << 32) | __builtin_amdgcn_alignbit(a1, a0, sh);
-        const uint64_t wb = ((uint64_t)__builtin_amdgcn_alignbit(b2, b1, sh) << 32) | __builtin_amdgcn_alignbit(b1, b0, sh);
+        // the 64 bits at offsets k and k + 64
+        uint64_t wa, wb;
+        br.lane_windows(wa, wb);
         token_pair<CHECK>(wa, wb, tok0, tok1);
         off = 0;
         need = false;
@@ -359,42 +364,53 @@ struct Inflater {
       // start lanes of the batch's tokens, and each start lane's token word
       // (the rest of a match begun in the last batch is the token at lane 0)
       // (a token word is never 0, so the start lanes are where word != 0)
-      uint32_t word = 0;
-      uint32_t jr = 0;  // output symbols of the tokens walked so far
-      const uint32_t cont = min(rem, 1u);  // (an integer, not a lane mask)
-      if (rem) {
-        word = (uint32_t)GZ_WRITELANE((int)((2u << 8) | ((mdist - 1u) << 17)), 0, 0);
-        jr = rem;
+      if (!open) {
+        word = 0;
+        jr = 0;  // output symbols of the tokens walked so far
+        cont = min(rem, 1u);  // (an integer, not a lane mask)
+        if (rem) {
+          word = (uint32_t)GZ_WRITELANE((int)((2u << 8) | ((mdist - 1u) << 17)), 0, 0);
+          jr = rem;
+        }
+        open = true;
       }
       // acc = jr << 8 | off; offsets below 64 come from tok0, the rest from
       // tok1 (a walk never returns below an offset it passed, so the two
       // halves are two loops).  Each step writes the token's word at lane jr
-      // and adds its step; a special token adds 511 symbols, which ends the
+      // and adds the word; a special token adds 448 symbols, which ends the
       // walk, and is taken back out below.
       uint32_t acc = (jr << 8) | off;
       uint32_t t = 0;  // the last token walked
-      if ((acc & 0xFFFFC0C0u) == 0u) {
+      if ((acc & 0x1C0C0u) == 0u) {
         do {
           t = (uint32_t)__builtin_amdgcn_readlane((int)tok0, (int)(acc & 63u));
-          word = (uint32_t)GZ_WRITELANE((int)t, (int)(acc >> 8), (int)word);
-          acc += t & TOK_STEP;
-        } while ((acc & 0xFFFFC0C0u) == 0u);
+          word = (uint32_t)GZ_WRITELANE((int)t, (int)((acc >> 8) & 63u), (int)word);
+          acc += t;
+        } while ((acc & 0x1C0C0u) == 0u);
       }
-      if ((acc & 0xFFFFC080u) == 0u) {
+      if ((acc & 0x1C080u) == 0u) {
         do {
           t = (uint32_t)__builtin_amdgcn_readlane((int)tok1, (int)(acc & 63u));
-          word = (uint32_t)GZ_WRITELANE((int)t, (int)(acc >> 8), (int)word);
-          acc += t & TOK_STEP;
-        } while ((acc & 0xFFFFC080u) == 0u);
+          word = (uint32_t)GZ_WRITELANE((int)t, (int)((acc >> 8) & 63u), (int)word);
+          acc += t;
+        } while ((acc & 0x1C080u) == 0u);
       }
       uint32_t x = 0;  // the special token that stopped the walk, else 0
       if (tok_special(t)) {
         x = t;
-        acc -= t & TOK_STEP;
-        word = (uint32_t)GZ_WRITELANE(0, (int)(acc >> 8), (int)word);
+        acc -= t;
+        word = (uint32_t)GZ_WRITELANE(0, (int)((acc >> 8) & 63u), (int)word);
       }
-      jr = acc >> 8;
+      jr = (acc >> 8) & 511u;
       off = acc & 255u;
+      if (x == 0u && jr < 64u && off >= 128u) {
+        // the round is used up before the batch is full: the next round
+        // continues the same batch
+        need = true;
+        if (br.pos + off > br.s.end_bits) return D_TRUNC;
+        continue;
+      }
+      open = false;
       const uint64_t starts = __ballot(word != 0u);
       // a token running past the batch continues in the next one (its
       // word is at the last start lane)

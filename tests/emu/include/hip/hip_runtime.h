@@ -100,6 +100,9 @@ static inline uint32_t __builtin_amdgcn_alignbit(uint32_t hi, uint32_t lo, uint3
   return (uint32_t)((((uint64_t)hi << 32) | lo) >> (s & 31u));
 }
 #define __builtin_amdgcn_readlane(v, l) ((int)emu_wave_sync(EMU_READLANE, (uint32_t)(v), (uint64_t)(l)))
+// ds_bpermute(byte address, v): the v of lane (address / 4) mod 64
+#define __builtin_amdgcn_ds_bpermute(a, v) \
+  ((int)emu_wave_sync(EMU_SHFL, (uint64_t)(uint32_t)(v), (uint64_t)(((uint32_t)(a) >> 2) & 63u)))
 #define __builtin_amdgcn_readfirstlane(v) ((int)emu_wave_sync(EMU_FIRSTLANE, (uint32_t)(v), 0))
 #define __builtin_amdgcn_s_waitcnt(x) ((void)0)
 #define __builtin_amdgcn_wave_barrier() ((void)emu_wave_sync(EMU_WAVEBAR, 0, 0))
