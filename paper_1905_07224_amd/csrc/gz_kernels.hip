@@ -348,12 +348,16 @@ struct Inflater {
     uint32_t word = 0, jr = 0, cont = 0;
     bool open = false;
     // an iteration consumes at least one bit or produces 64 symbols (<= 258
-    // per code): the remaining bits bound the iterations
-    const uint64_t budget = 8ull * (br.s.end_bits - br.pos + 64);
-    for (uint64_t it = 0;; it++) {
-      if (it > budget) return D_BAD;
+    // per code): the remaining bits bound the iterations (a 32-bit count:
+    // even a 4 GiB output takes far fewer than 2^32 iterations)
+    const uint64_t budget64 = 8ull * (br.s.end_bits - br.pos + 64);
+    const uint32_t budget = budget64 < 0xFFFFFFFFull ? (uint32_t)budget64 : 0xFFFFFFFFu;
+    for (uint32_t it = 0;; it++) {
+      if (it >= budget) return D_BAD;
       if (need) {
         br.pos += off;
+        // past the end of the input (the bit reader reads zeros there)
+        if (br.past_end()) return D_TRUNC;
         // the 64 bits at offsets k and k + 64
         uint64_t wa, wb;
         br.lane_windows(wa, wb);
@@ -407,7 +411,6 @@ struct Inflater {
         // the round is used up before the batch is full: the next round
         // continues the same batch
         need = true;
-        if (br.pos + off > br.s.end_bits) return D_TRUNC;
         continue;
       }
       open = false;
@@ -456,8 +459,8 @@ struct Inflater {
       } else if (off >= 128u) {
         need = true;
       }
-      if (br.pos + off > br.s.end_bits) return D_TRUNC;
-      if (pos - blk0 >= size_cap) return D_SIZE;
+      // only the trial block (a checked block) has a size bound
+      if (CHECK && pos - blk0 >= size_cap) return D_SIZE;
     }
   }
 
