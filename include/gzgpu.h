@@ -54,7 +54,7 @@ typedef struct gz_opts {
   uint64_t chunk_bytes;   /* nominal compressed bytes per chunk when n_chunks == 0 (default 40 KiB) */
   uint32_t sym_factor;    /* symbol capacity per chunk = sym_factor * compressed bytes + slack (default 8) */
   uint32_t window_syms;   /* LDS history ring per decoding wave, in symbols: 512, 1024, 2048, 4096, 8192, 16384
-                             or 32768 (default 1024); match sources further back are read from HBM.
+                             or 32768 (default 512); match sources further back are read from HBM.
                              Any other value: GZ_E_ARG */
   uint32_t scan_groups;   /* workgroups that search one chunk's start in parallel (default: 4096 / chunks, 1..64) */
   uint32_t inflate_waves_per_cu; /* persistent inflate grid = this * CU count (default: occupancy) */
@@ -154,8 +154,8 @@ int gz_decompress_batch(gz_plan_t plan, void *d_ws, size_t ws_bytes, void *strea
  * Errors as gz_decompress_batch. */
 int gz_decompress_graph(gz_plan_t plan, void *d_ws, size_t ws_bytes, void *stream);
 
-/* Choose opts.chunk_bytes (32 KiB .. 1 MiB) and opts.window_syms (1024,
- * 2048 or 4096) for one file by timing each candidate on it (two runs each,
+/* Choose opts.chunk_bytes (32 KiB .. 1 MiB) and opts.window_syms (512,
+ * 1024 or 2048) for one file by timing each candidate on it (two runs each,
  * the second timed with HIP events on `stream`), and cache the choice per
  * (device, compressed-size class, compression-ratio class) for the process;
  * a cached choice returns at once.  *best: in, the other options; out, the
@@ -386,6 +386,45 @@ int gz_stream_open_at(gz_stream_t *stream, const void *d_comp, size_t comp_len, 
  * (window 0, value above 255), GZ_E_HIP. */
 int gz_count_byte(const void *d_buf, uint64_t n, uint32_t value, uint64_t first, uint64_t window, uint64_t *d_counts,
                   uint64_t n_counts, void *stream);
+
+/* DNA-like sequences in partly undetermined text (Appendix B), and the
+ * sequence-resolved test of Section VI-B.  Scanning left to right, every
+ * maximal substring T D+ (U+ D+)* T is taken, where D is a nucleotide letter
+ * (upper-case A, C, G, T or N), U an undetermined element and T a newline
+ * or an undetermined element; the earliest start wins, then the longest
+ * match from it, and the search resumes after the closing T (so a newline
+ * that closes one sequence does not open the next).  A sequence is the
+ * match without its two T's; sequences shorter than min_len are dropped
+ * after the search.
+ *   d_buf, n      the text: elem_bytes 1, bytes in which the value `marker`
+ *                 is undetermined (the output of a random-access stream,
+ *                 Section IV-B); elem_bytes 2, 16-bit symbols in which every
+ *                 value of 256 and above is undetermined (pass-1 symbols,
+ *                 Section VI-C; marker ignored).  n below 2^32.
+ *   d_seqs        the first max_seqs sequences, in order (may be NULL when
+ *                 max_seqs is 0); *d_n_seqs receives the total found.
+ *   d_bounds      n_ranges + 1 ascending positions (e.g. the output offsets of
+ *                 DEFLATE blocks); a sequence counts in the range holding its
+ *                 first nucleotide.  d_range_stats gets 3 words per range:
+ *                 sequences, sequences holding an undetermined element, and
+ *                 1 when the first is at least `threshold` and the second 0
+ *                 (the range is sequence-resolved).  n_ranges 0: no ranges.
+ *   d_ws          gz_extract_dna_ws(n) bytes, 256-byte aligned.
+ * Every buffer is device memory owned by the caller; the call only enqueues
+ * on `stream`.  Errors: GZ_E_ARG (elem_bytes not 1 or 2, n too large, a
+ * marker above 255 or equal to a nucleotide letter or newline, a missing
+ * buffer), GZ_E_CAPACITY (ws_bytes too small), GZ_E_HIP. */
+typedef struct gz_dna_seq {
+  uint64_t start;           /* position of the first nucleotide */
+  uint32_t len;             /* elements in the sequence */
+  uint32_t n_undetermined;  /* undetermined elements inside it */
+} gz_dna_seq;
+
+uint64_t gz_extract_dna_ws(uint64_t n);
+int gz_extract_dna(const void *d_buf, uint64_t n, uint32_t elem_bytes, uint32_t marker, uint32_t min_len,
+                   gz_dna_seq *d_seqs, uint64_t max_seqs, uint64_t *d_n_seqs, const uint64_t *d_bounds,
+                   uint32_t n_ranges, uint32_t threshold, uint32_t *d_range_stats, void *d_ws, size_t ws_bytes,
+                   void *stream);
 
 /* ------------------------------------------------------------------------
  * Serving loop (beyond the paper's one-file setting): jobs arrive one at a

@@ -118,12 +118,12 @@ EXPORTS = ["gz_plan", "gz_plan_batch", "gz_plan_info", "gz_decompress", "gz_deco
            "gz_server_poll", "gz_server_stats", "gz_server_destroy", "gz_stream_open", "gz_stream_get_info",
            "gz_stream_next", "gz_stream_wait", "gz_stream_checkpoint", "gz_stream_resume", "gz_stream_destroy",
            "gz_plan_probes", "gz_find_blocks", "gz_probe_starts", "gz_stream_open_at", "gz_count_byte",
-           "gz_plan_bgzf", "gz_chunk_stats", "gz_decompress_static"]
+           "gz_plan_bgzf", "gz_chunk_stats", "gz_decompress_static", "gz_extract_dna_ws", "gz_extract_dna"]
 GZ_N_PASSES = N_PASSES = 13
 GZ_SCRATCH_BYTES = 256 << 20  # static workspace of gz_decompress_static, per GPU
 # defaults of gz_opts (include/gzgpu.h)
 DEFAULT_CHUNK_BYTES = 40 << 10
-DEFAULT_WINDOW = 1024
+DEFAULT_WINDOW = 512
 
 
 def lib():
@@ -175,11 +175,15 @@ def lib():
         L.gz_probe_starts.argtypes = [vp, vp, vp]
         L.gz_stream_open_at.argtypes = [C.POINTER(vp), vp, C.c_size_t, u64, C.c_uint32, u64, C.POINTER(Opts)]
         L.gz_count_byte.argtypes = [vp, u64, C.c_uint32, u64, u64, vp, u64, vp]
+        L.gz_extract_dna_ws.argtypes = [u64]
+        L.gz_extract_dna_ws.restype = u64
+        L.gz_extract_dna.argtypes = [vp, u64, C.c_uint32, C.c_uint32, C.c_uint32, vp, u64, vp, vp, C.c_uint32,
+                                     C.c_uint32, vp, vp, C.c_size_t, vp]
         L.gz_plan_bgzf.argtypes = [C.POINTER(vp), vp, vp, C.c_size_t, vp, C.c_size_t, C.POINTER(Opts),
                                    C.POINTER(u64), C.POINTER(C.c_uint32)]
         for name in EXPORTS:
             if name not in ("gz_plan_destroy", "gz_strerror", "gz_pass_name", "gz_server_destroy",
-                            "gz_stream_destroy"):
+                            "gz_stream_destroy", "gz_extract_dna_ws"):
                 getattr(L, name).restype = i32
         _lib = L
     return _lib
@@ -715,6 +719,61 @@ def count_byte(buf: torch.Tensor, value: int, window: int, counts: torch.Tensor,
     with torch.cuda.device(buf.device):
         _check(lib().gz_count_byte(C.c_void_p(buf.data_ptr()), buf.numel(), int(value), int(first), int(window),
                                    C.c_void_p(counts.data_ptr()), counts.numel(), _stream_handle(stream)))
+
+
+class DnaSeq(C.Structure):
+    _fields_ = [("start", C.c_uint64), ("len", C.c_uint32), ("n_undetermined", C.c_uint32)]
+
+
+DNA_SEQ_DTYPE = [(f, np_t) for (f, _), np_t in zip(DnaSeq._fields_, ("<u8", "<u4", "<u4"))]
+
+
+def extract_dna(buf: torch.Tensor, marker: int | None = None, min_len: int = 1, bounds=None, threshold: int = 1,
+                max_seqs: int | None = None, stream=None):
+    """DNA-like sequences of a partly undetermined text (gz_extract_dna,
+    Appendix B).  buf: a uint8 device tensor whose value `marker` is
+    undetermined, or 16-bit symbols (int16/uint16) whose values of 256 and
+    above are.  bounds: n_ranges + 1 ascending positions, or None.  Returns
+    (numpy array of gz_dna_seq records, total found, numpy array of
+    (sequences, with undetermined, resolved) per range or None)."""
+    import numpy as np
+
+    if not buf.is_cuda or not buf.is_contiguous():
+        raise ValueError("buf must be a contiguous device tensor")
+    elem = buf.element_size()
+    if elem not in (1, 2):
+        raise ValueError("buf must hold bytes or 16-bit symbols")
+    if elem == 1 and marker is None:
+        raise ValueError("a byte buffer needs its marker value")
+    n = buf.numel()
+    dev = buf.device
+    if max_seqs is None:
+        max_seqs = (n + 2) // 3
+    rec_bytes = C.sizeof(DnaSeq)
+    seqs = torch.empty(max(1, max_seqs) * rec_bytes, dtype=torch.uint8, device=dev)
+    n_seqs = torch.zeros(1, dtype=torch.int64, device=dev)
+    nr = 0
+    b = st = None
+    if bounds is not None:
+        b = torch.as_tensor(np.asarray(bounds, dtype=np.int64)).to(dev)
+        nr = b.numel() - 1
+        st = torch.empty(max(1, 3 * nr), dtype=torch.int32, device=dev)
+    ws_bytes = int(lib().gz_extract_dna_ws(n))
+    ws = torch.empty(ws_bytes + 256, dtype=torch.uint8, device=dev)
+    off = (-ws.data_ptr()) % 256
+    with torch.cuda.device(dev):
+        h = _stream_handle(stream)
+        _check(lib().gz_extract_dna(C.c_void_p(buf.data_ptr()), n, elem, int(marker or 0), int(min_len),
+                                    C.c_void_p(seqs.data_ptr()), int(max_seqs), C.c_void_p(n_seqs.data_ptr()),
+                                    C.c_void_p(b.data_ptr()) if b is not None else None, nr, int(threshold),
+                                    C.c_void_p(st.data_ptr()) if st is not None else None,
+                                    C.c_void_p(ws.data_ptr() + off), ws_bytes, h))
+        (torch.cuda.current_stream() if stream is None else stream).synchronize()
+    total = int(n_seqs.item())
+    k = min(total, max_seqs)
+    rec = np.frombuffer(seqs[: rec_bytes * k].cpu().numpy().tobytes(), dtype=DNA_SEQ_DTYPE)
+    stats = st[: 3 * nr].cpu().numpy().astype(np.int64).reshape(nr, 3) if st is not None else None
+    return rec, total, stats
 
 
 def undetermined_profile(comp, bit: int, window: int, marker: int = 0, segment_bytes: int = 0,

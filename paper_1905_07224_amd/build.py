@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libgzgpu.so")
-SOURCES = ["gz_kernels.hip", "gz_api.cpp", "gz_serve.cpp"]
+SOURCES = ["gz_kernels.hip", "gz_dna.hip", "gz_api.cpp", "gz_serve.cpp"]
 ARCH = os.environ.get("GZGPU_ARCH", "gfx950")
 
 

@@ -43,6 +43,9 @@ hipError_t gzk_carry(const FileDesc *, const FileState *, const uint8_t *, uint8
 hipError_t gzk_scratch(void **);
 hipError_t gzk_count_byte(const uint8_t *, uint64_t, uint32_t, uint64_t, uint64_t, unsigned long long *, uint64_t,
                           hipStream_t);
+uint64_t gzk_dna_ws(uint64_t);
+hipError_t gzk_dna(const void *, uint64_t, uint32_t, uint32_t, uint32_t, gz_dna_seq *, uint64_t, uint64_t *,
+                   const uint64_t *, uint32_t, uint32_t, uint32_t *, uint8_t *, hipStream_t);
 }
 
 namespace {
@@ -672,6 +675,25 @@ int gz_count_byte(const void *d_buf, uint64_t n, uint32_t value, uint64_t first,
   return e == hipSuccess ? GZ_OK : hip_fail(e, "count");
 }
 
+uint64_t gz_extract_dna_ws(uint64_t n) { return gzk_dna_ws(n); }
+
+int gz_extract_dna(const void *d_buf, uint64_t n, uint32_t elem_bytes, uint32_t marker, uint32_t min_len,
+                   gz_dna_seq *d_seqs, uint64_t max_seqs, uint64_t *d_n_seqs, const uint64_t *d_bounds,
+                   uint32_t n_ranges, uint32_t threshold, uint32_t *d_range_stats, void *d_ws, size_t ws_bytes,
+                   void *stream) {
+  const bool bad_marker = elem_bytes == 1 && (marker > 255 || marker == '\n' || marker == 'A' || marker == 'C' ||
+                                              marker == 'G' || marker == 'T' || marker == 'N');
+  if ((elem_bytes != 1 && elem_bytes != 2) || n >= (1ull << 32) || bad_marker || (!d_buf && n) || !d_n_seqs ||
+      (!d_seqs && max_seqs) || (n_ranges && (!d_bounds || !d_range_stats)) || !d_ws || ((uintptr_t)d_ws & 255u)) {
+    snprintf(g_err, sizeof(g_err), "gz_extract_dna: invalid argument");
+    return GZ_E_ARG;
+  }
+  if (ws_bytes < gzk_dna_ws(n)) return GZ_E_CAPACITY;
+  hipError_t e = gzk_dna(d_buf, n, elem_bytes, marker, min_len, d_seqs, max_seqs, d_n_seqs, d_bounds, n_ranges,
+                         threshold, d_range_stats, (uint8_t *)d_ws, (hipStream_t)stream);
+  return e == hipSuccess ? GZ_OK : hip_fail(e, "extract");
+}
+
 int gz_plan_info(gz_plan_t p, gz_info *info) {
   if (!p || !info) return GZ_E_ARG;
   memset(info, 0, sizeof(*info));
@@ -1085,7 +1107,7 @@ namespace {
 std::mutex g_tune_mu;
 std::map<std::tuple<int, int, int>, gz_opts> g_tune;
 const uint64_t k_tune_chunks[] = {32ull << 10, 40ull << 10, 64ull << 10, 128ull << 10, 256ull << 10, 1ull << 20};
-const uint32_t k_tune_rings[] = {1024, 2048, 4096};
+const uint32_t k_tune_rings[] = {512, 1024, 2048};
 }  // namespace
 
 int gz_autotune(const void *d_comp, size_t comp_len, void *d_out, size_t out_cap, void *d_ws, size_t ws_bytes,

@@ -9,7 +9,7 @@ constexpr uint32_t WINDOW = 32768;       // DEFLATE history (RFC 1951 section 2;
 constexpr uint32_t FLUSH_UNIT = 512;     // symbols moved from LDS to HBM at a time
 constexpr uint32_t TRANSLATE_TILE = 8192;
 constexpr uint32_t SYM_SLACK = 2048;     // symbols added to every chunk's capacity
-constexpr uint32_t DEFAULT_RING = 1024;  // symbols of LDS history per decoding wave
+constexpr uint32_t DEFAULT_RING = 512;   // symbols of LDS history per decoding wave
 constexpr uint64_t DEFAULT_CHUNK_BYTES = 40 << 10;  // nominal compressed bytes per chunk
 constexpr uint64_t SCRATCH_BYTES = 256ull << 20;    // static workspace of gz_decompress_static, per GPU
 // LDS bytes of one decoding wave (tables + a ring of `win` 16-bit symbols), upper bound

@@ -12,8 +12,8 @@ ROOT = os.path.dirname(os.path.dirname(HERE))
 CSRC = os.path.join(ROOT, "paper_1905_07224_amd", "csrc")
 LIB = os.path.join(HERE, "libgzemu.so")
 # stage2_diff.cpp includes gz_kernels.hip (one translation unit for the kernels)
-SRCS = [os.path.join(HERE, "stage2_diff.cpp"), os.path.join(CSRC, "gz_api.cpp"), os.path.join(CSRC, "gz_serve.cpp"),
-        os.path.join(HERE, "emu_rt.cpp")]
+SRCS = [os.path.join(HERE, "stage2_diff.cpp"), os.path.join(CSRC, "gz_dna.hip"), os.path.join(CSRC, "gz_api.cpp"),
+        os.path.join(CSRC, "gz_serve.cpp"), os.path.join(HERE, "emu_rt.cpp")]
 CXX = "/opt/rocm/lib/llvm/bin/clang++" if os.path.exists("/opt/rocm/lib/llvm/bin/clang++") else "clang++"
 
 

@@ -329,3 +329,39 @@ def bgzf_run(comp: bytes, **opts):
         sts.append(r.status)
     L.gz_plan_destroy(h)
     return 0, out[: n_out.value].tobytes(), sts
+
+
+def dna_run(buf, marker=0, min_len=1, bounds=None, threshold=1, max_seqs=None):
+    """gz_extract_dna on the CPU executor: (list of (start, len, undetermined),
+    total, per-range stats or None)."""
+    L = lib()
+    vp = C.c_void_p
+    L.gz_extract_dna_ws.argtypes = [C.c_uint64]
+    L.gz_extract_dna_ws.restype = C.c_uint64
+    L.gz_extract_dna.argtypes = [vp, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, vp, C.c_uint64, vp, vp,
+                                 C.c_uint32, C.c_uint32, vp, vp, C.c_size_t, vp]
+    L.emu_set_sync_limit(0)
+    a = np.ascontiguousarray(buf)
+    elem = a.dtype.itemsize
+    n = a.size
+    if max_seqs is None:
+        max_seqs = (n + 2) // 3
+    seqs = np.zeros(max(1, max_seqs), dtype=[("start", "<u8"), ("len", "<u4"), ("nu", "<u4")])
+    total = np.zeros(1, dtype=np.uint64)
+    nr = 0
+    b = st = None
+    if bounds is not None:
+        b = np.asarray(bounds, dtype=np.uint64)
+        nr = b.size - 1
+        st = np.full(max(1, 3 * nr), 7, dtype=np.uint32)
+    wsb = int(L.gz_extract_dna_ws(n))
+    raw_ws = np.full(wsb + 512, 0xA5, dtype=np.uint8)
+    off = (-raw_ws.ctypes.data) % 256
+    ws = raw_ws[off:off + wsb]
+    p = lambda x: vp(x.ctypes.data) if x is not None else None  # noqa: E731
+    r = L.gz_extract_dna(vp(a.ctypes.data) if n else None, n, elem, marker, min_len, p(seqs), max_seqs, p(total),
+                         p(b), nr, threshold, p(st), p(ws), wsb, None)
+    assert r == 0, r
+    k = min(int(total[0]), max_seqs)
+    out = [(int(s["start"]), int(s["len"]), int(s["nu"])) for s in seqs[:k]]
+    return out, int(total[0]), (st[: 3 * nr].reshape(nr, 3).astype(np.int64) if st is not None else None)

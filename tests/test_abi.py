@@ -83,7 +83,7 @@ def test_struct_layout_matches_c_compiler(tmp_path):
     structs = {"gz_opts": gz.Opts, "gz_job": gz.Job, "gz_info": gz.Info, "gz_result": gz.Result,
                "gz_server_opts": gz.ServerOpts, "gz_done": gz.Done, "gz_server_info": gz.ServerInfo,
                "gz_stream_info": gz.StreamInfo, "gz_segment_result": gz.SegmentResult,
-               "gz_checkpoint": gz.Checkpoint}
+               "gz_checkpoint": gz.Checkpoint, "gz_dna_seq": gz.DnaSeq}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "gzgpu.h"', "int main(void) {"]
     for cname, cls in structs.items():
         lines.append(f'  printf("{cname} sizeof %zu\\n", sizeof({cname}));')
@@ -110,3 +110,13 @@ def test_output_size_guess_uses_isize_modulus():
 
     assert gz._out_guess(1000, 500) == 1000
     assert gz._out_guess(5, 10 << 30) == 5 + (3 << 32)  # 12 GiB+5 is the first value >= the floor
+
+
+def test_extractor_workspace_query_is_64_bit(libpath):
+    """gz_extract_dna_ws returns a 64-bit size (16 bytes per element at most,
+    above 4 GiB for large texts) through the binding."""
+    import paper_1905_07224_amd as gz
+
+    big = gz.lib().gz_extract_dna_ws(600_000_000)
+    assert big > 1 << 32 and big <= 17 * 600_000_000
+    assert gz.lib().gz_extract_dna_ws(0) > 0

@@ -610,3 +610,54 @@ def test_emu_static_workspace_entry_point():
         assert res.status == 0 and out[: res.out_len].tobytes() == raw
         assert (out[res.out_len:] == 0xAB).all()
         assert np.array_equal(starts, tab["start"]), k
+
+
+def _cls_bytes(s):
+    cb = {"D": ord("A"), "U": 0, "L": 10, "O": ord("x")}
+    return np.array([cb[c] for c in s], np.uint8)
+
+
+def test_emu_extract_dna_random_class_strings():
+    """The device extractor (Appendix B) on random class strings spanning many
+    tiles and groups of runs equals the oracle, as bytes with a marker and as
+    16-bit symbols; also a chain of newline-shared runs across groups, an
+    empty buffer, a buffer without runs, and the sequence cap."""
+    from oracle import dna
+
+    rng = np.random.default_rng(1)
+    for n, alpha in ((5000, "DDDDULLO"), (40000, "DDDDULLO"), (30000, "DDUUL")):
+        a = _cls_bytes("".join(rng.choice(list(alpha), n)))
+        want = dna.extract(a, 0, 1)
+        got, tot, _ = E.dna_run(a, 0, 1)
+        assert got == want and tot == len(want)
+        sym = np.where(a == 0, 0x8000 + rng.integers(0, 32768, n), a).astype(np.uint16)
+        got, tot, _ = E.dna_run(sym, 0, 3)
+        assert got == dna.extract(sym, min_len=3)
+    a = _cls_bytes("L" + "DL" * 70000)
+    got, tot, _ = E.dna_run(a, 0, 1)
+    assert got == dna.extract(a, 0, 1) and tot == 35000
+    assert E.dna_run(np.zeros(0, np.uint8), 0, 1)[:2] == ([], 0)
+    assert E.dna_run(_cls_bytes("OLOLLO" * 100), 0, 1)[:2] == ([], 0)
+    got, tot, _ = E.dna_run(a, 0, 1, max_seqs=10)
+    assert tot == 35000 and got == dna.extract(a, 0, 1)[:10]
+
+
+def test_emu_extract_dna_fastq_ranges():
+    """FASTQ-like text with undetermined headers, qualities and bases: the
+    sequences and the per-range (sequence-resolved) statistics equal the
+    oracle's."""
+    from oracle import dna
+
+    raw = np.frombuffer(synth.fastq_like(300 << 10, 17), np.uint8)
+    rng = np.random.default_rng(2)
+    und = rng.random(raw.size) < np.where(np.arange(raw.size) < raw.size * 6 // 10, 0.2, 0.0)
+    sym = np.where(und, 0x8000 + rng.integers(0, 32768, raw.size), raw).astype(np.uint16)
+    bounds = np.linspace(0, raw.size, 9).astype(np.int64)
+    want = dna.extract(sym, min_len=50)
+    got, tot, st = E.dna_run(sym, 0, 50, bounds=bounds, threshold=20)
+    assert got == want and tot == len(want)
+    assert np.array_equal(st, dna.range_stats(want, bounds, 20))
+    assert st[:, 2].any() and not st[:, 2].all()
+    b8 = np.where(und, 0, raw).astype(np.uint8)
+    got, _, st8 = E.dna_run(b8, 0, 50, bounds=bounds, threshold=20)
+    assert got == want and np.array_equal(st8, st)

@@ -2,7 +2,7 @@
 
 The 1 GiB FASTQ-like member at level 6 (read lengths 100 and 150), decoded in
 the launch configuration the benchmark times (library defaults: 40 KiB
-chunks, 1024-symbol LDS ring, about 12 000 chunks), is compared with the
+chunks, 512-symbol LDS ring, about 12 000 chunks), is compared with the
 oracle's sequential gunzip byte for byte.  Chunk starts and ends must be
 block boundaries of the oracle's block map with the oracle's output offsets,
 and a seeded sample of chunks must have exactly the oracle's pass-1 symbols
