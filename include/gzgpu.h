@@ -62,7 +62,10 @@ typedef struct gz_opts {
   uint32_t timing;        /* nonzero: record a HIP event at every pass boundary (see gz_pass_times) */
   uint32_t confirm_decode; /* nonzero: confirmation blocks a chunk owes past its stop are always decoded
                               on their own instead of taken from the next chunks (same result; tests) */
-  uint32_t reserved[5];
+  uint32_t binary;        /* nonzero: binary input (Section VIII): chunk starts are searched with the checks
+                             of Appendix A except the ASCII test of the literals; the output is exact
+                             either way (the stitch check repairs any wrong start) */
+  uint32_t reserved[4];
 } gz_opts;
 
 /* One file of a batch. */

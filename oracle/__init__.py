@@ -89,6 +89,8 @@ def lib():
         L.orc_sym_free.argtypes = [C.POINTER(_Sym)]
         L.orc_pugz.restype = C.POINTER(_Pugz)
         L.orc_pugz.argtypes = [u8p, C.c_size_t, C.c_int]
+        L.orc_pugz_mode.restype = C.POINTER(_Pugz)
+        L.orc_pugz_mode.argtypes = [u8p, C.c_size_t, C.c_int, C.c_int]
         L.orc_pugz_free.argtypes = [C.POINTER(_Pugz)]
         L.orc_crc32.restype = C.c_uint32
         L.orc_crc32.argtypes = [C.c_uint32, u8p, C.c_size_t]
@@ -98,6 +100,10 @@ def lib():
         L.orc_block_predicate.argtypes = [u8p, C.c_size_t, C.c_int64, C.POINTER(C.c_int)]
         L.orc_find_start.restype = C.c_int64
         L.orc_find_start.argtypes = [u8p, C.c_size_t, C.c_int64, C.c_int64, C.c_int]
+        L.orc_block_predicate_mode.restype = C.c_int
+        L.orc_block_predicate_mode.argtypes = [u8p, C.c_size_t, C.c_int64, C.c_int, C.POINTER(C.c_int)]
+        L.orc_find_start_mode.restype = C.c_int64
+        L.orc_find_start_mode.argtypes = [u8p, C.c_size_t, C.c_int64, C.c_int64, C.c_int, C.c_int]
         L.orc_parse_header.restype = C.c_int
         L.orc_parse_header.argtypes = [u8p, C.c_size_t, C.POINTER(C.c_size_t), C.POINTER(C.c_int)]
         _lib = L
@@ -203,27 +209,29 @@ def block_static(data, bit: int):
     return bool(ok), REASONS.get(r.value, r.value)
 
 
-def block_predicate(data, bit: int):
+def block_predicate(data, bit: int, binary: bool = False):
+    """Appendix A's checks at one bit (binary: without the ASCII test)."""
     a, p, n = _buf(data)
     r = C.c_int(0)
-    ok = lib().orc_block_predicate(p, n, bit, C.byref(r))
+    ok = lib().orc_block_predicate_mode(p, n, bit, 0 if binary else 1, C.byref(r))
     return bool(ok), REASONS.get(r.value, r.value)
 
 
-def find_start(data, lo_bit: int, hi_bit: int, static_only: bool = False) -> int:
+def find_start(data, lo_bit: int, hi_bit: int, static_only: bool = False, binary: bool = False) -> int:
     a, p, n = _buf(data)
-    return int(lib().orc_find_start(p, n, lo_bit, hi_bit, 1 if static_only else 0))
+    return int(lib().orc_find_start_mode(p, n, lo_bit, hi_bit, 1 if static_only else 0, 0 if binary else 1))
 
 
 class PugzResult:
     pass
 
 
-def pugz(data, n_chunks: int) -> PugzResult:
-    """The two-pass method on the CPU: per-chunk starts, ends, lengths, windows, output."""
+def pugz(data, n_chunks: int, binary: bool = False) -> PugzResult:
+    """The two-pass method on the CPU: per-chunk starts, ends, lengths, windows,
+    output (binary: block starts searched without the ASCII test)."""
     a, p, n = _buf(data)
     L = lib()
-    rp = L.orc_pugz(p, n, n_chunks)
+    rp = L.orc_pugz_mode(p, n, n_chunks, 0 if binary else 1)
     r = rp.contents
     o = PugzResult()
     o.status = r.status

@@ -604,6 +604,12 @@ int orc_block_static(const uint8_t *in, size_t n, int64_t bit, int *reason) {
 }
 
 int orc_block_predicate(const uint8_t *in, size_t n, int64_t bit, int *reason) {
+  return orc_block_predicate_mode(in, n, bit, 1, reason);
+}
+
+/* Binary inputs (Section VIII lists them as a limitation): the same checks
+ * without the ASCII test of the literals. */
+int orc_block_predicate_mode(const uint8_t *in, size_t n, int64_t bit, int ascii, int *reason) {
   int e;
   if (!orc_block_static(in, n, bit, &e)) {
     if (reason) *reason = e;
@@ -612,7 +618,7 @@ int orc_block_predicate(const uint8_t *in, size_t n, int64_t bit, int *reason) {
   sink s;
   memset(&s, 0, sizeof(s));
   s.mode = SINK_CHECK;
-  s.ascii_only = 1;
+  s.ascii_only = ascii;
   s.size_cap = MAX_BLOCK;
   bitrd r = {in, n, bit, 0};
   int bfinal, btype;
@@ -630,8 +636,12 @@ int orc_block_predicate(const uint8_t *in, size_t n, int64_t bit, int *reason) {
 }
 
 int64_t orc_find_start(const uint8_t *in, size_t n, int64_t lo, int64_t hi, int static_only) {
+  return orc_find_start_mode(in, n, lo, hi, static_only, 1);
+}
+
+int64_t orc_find_start_mode(const uint8_t *in, size_t n, int64_t lo, int64_t hi, int static_only, int ascii) {
   for (int64_t b = lo; b < hi; b++) {
-    int ok = static_only ? orc_block_static(in, n, b, NULL) : orc_block_predicate(in, n, b, NULL);
+    int ok = static_only ? orc_block_static(in, n, b, NULL) : orc_block_predicate_mode(in, n, b, ascii, NULL);
     if (ok) return b;
   }
   return -1;
@@ -656,7 +666,9 @@ void orc_pugz_free(orc_pugz_result *r) {
   free(r);
 }
 
-orc_pugz_result *orc_pugz(const uint8_t *in, size_t n, int N) {
+orc_pugz_result *orc_pugz(const uint8_t *in, size_t n, int N) { return orc_pugz_mode(in, n, N, 1); }
+
+orc_pugz_result *orc_pugz_mode(const uint8_t *in, size_t n, int N, int ascii) {
   orc_pugz_result *res = (orc_pugz_result *)calloc(1, sizeof(*res));
   if (!res || N < 1) return res;
   res->n_chunks = N;
@@ -694,7 +706,7 @@ orc_pugz_result *orc_pugz(const uint8_t *in, size_t n, int N) {
   /* block starts: chunk 0 at the payload's first bit, others searched */
   res->start[0] = res->cand[0] = (int64_t)h * 8;
   for (int i = 1; i < N; i++) {
-    res->cand[i] = orc_find_start(in, n, res->nominal[i] * 8, res->nominal[i + 1] * 8, 0);
+    res->cand[i] = orc_find_start_mode(in, n, res->nominal[i] * 8, res->nominal[i + 1] * 8, 0, ascii);
     res->start[i] = res->cand[i];
   }
 

@@ -137,8 +137,11 @@ void orc_sym_free(orc_sym_result *r);
  * reason (R_*) or R_OK. */
 int orc_block_static(const uint8_t *in, size_t n, int64_t bit, int *reason);
 int orc_block_predicate(const uint8_t *in, size_t n, int64_t bit, int *reason);
+/* ascii 0: binary inputs, the same checks without the ASCII test. */
+int orc_block_predicate_mode(const uint8_t *in, size_t n, int64_t bit, int ascii, int *reason);
 /* Smallest b in [lo, hi) passing the predicate (static only if static_only), or -1. */
 int64_t orc_find_start(const uint8_t *in, size_t n, int64_t lo, int64_t hi, int static_only);
+int64_t orc_find_start_mode(const uint8_t *in, size_t n, int64_t lo, int64_t hi, int static_only, int ascii);
 
 /* The whole two-pass method of Section VI-C on the CPU, single member.
  * Chunk i covers compressed bytes [nom_i, nom_{i+1}) of the payload with
@@ -168,6 +171,8 @@ typedef struct {
 } orc_pugz_result;
 
 orc_pugz_result *orc_pugz(const uint8_t *in, size_t n, int n_chunks);
+/* ascii 0: the block-start search of binary inputs (no ASCII test). */
+orc_pugz_result *orc_pugz_mode(const uint8_t *in, size_t n, int n_chunks, int ascii);
 void orc_pugz_free(orc_pugz_result *r);
 
 #ifdef __cplusplus

@@ -303,7 +303,7 @@ static int plan_common(gz_plan_t p) {
     if (p->probe) {
       // one chunk searching [probe_lo, probe_hi) bits; it decodes one block
       // and its confirmation
-      fd.mode = FD_PROBE;
+      fd.mode = FD_PROBE | (p->opts.binary ? FD_BINARY : 0u);
       fd.stop_bit = p->probe_hi[f];
       fd.first_chunk = (uint32_t)p->chunks.size();
       fd.n_chunks = 1;
@@ -332,6 +332,7 @@ static int plan_common(gz_plan_t p) {
       fd.win_valid = p->seg.win_valid;
       fd.mode = p->seg.mode;
     }
+    if (p->opts.binary) fd.mode |= FD_BINARY;
     const uint64_t P = hi > lo ? hi - lo : 1;
     uint64_t N = j.n_chunks > 0 ? (uint64_t)j.n_chunks : (P + p->opts.chunk_bytes - 1) / p->opts.chunk_bytes;
     N *= std::max<uint32_t>(1, p->opts.waves_per_chunk);

@@ -87,6 +87,7 @@ enum : uint32_t {
   FD_PROBE = 1u,    // block-start probe: one chunk, decodes its first block (plus the confirmation)
   FD_NOCHECK = 2u,  // decoding began inside the member: the trailer's CRC-32 and ISIZE do not apply
   FD_MEMBERS = 4u,  // more members may follow: the trailer is the 8 bytes after the final block
+  FD_BINARY = 8u,   // binary input: block-start checks without the ASCII test of the literals
 };
 
 struct ChunkDesc {

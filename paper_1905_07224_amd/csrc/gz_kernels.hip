@@ -81,6 +81,7 @@ struct Inflater {
   uint32_t nph;      // per lane placeholder count
   uint32_t nph_stop; // per lane placeholder count at the stop (symbols of D_i only)
   bool first;        // empty context
+  bool ascii;        // checked blocks reject literals outside the ASCII set (text input)
   bool over;         // capacity exceeded somewhere
   bool emit;         // false: blocks past the stop are only parsed and counted
 
@@ -125,7 +126,7 @@ struct Inflater {
       bool bad = false;
       if (k < n) {
         uint32_t c = br.s.byte(fb + k);
-        bad = check && !ascii_text(c);
+        bad = check && ascii && !ascii_text(c);
         if (emit) sh.ring[(pos + (uint32_t)lane) & RMASK] = (uint16_t)c;
       }
       if (__ballot(bad)) return D_ASCII;
@@ -243,7 +244,7 @@ struct Inflater {
     const uint32_t kind = (e >> 4) & 15u, cl = e & 15u;
     nsyms++;
     if ((kind & 7u) == K_LIT) {
-      if (check && kind == K_LITX) return D_ASCII;
+      if (check && ascii && kind == K_LITX) return D_ASCII;
       *lit = (e >> 8) & 255u;
       *len_out = 0;
       br.skip(cl);
@@ -291,7 +292,7 @@ struct Inflater {
   // length's extra bits).  Straight-line code: every case is computed and
   // one is selected.
   template <bool CHECK>
-  __device__ __forceinline__ static uint32_t token_word(uint64_t w, uint32_t e, uint32_t ed) {
+  __device__ __forceinline__ static uint32_t token_word(uint64_t w, uint32_t e, uint32_t ed, bool ascii) {
     const uint32_t w0 = (uint32_t)w;
     const uint32_t kind = (e >> 4) & 15u, cl = e & 15u, ex = (e >> 8) & 15u;
     const uint32_t u = cl + ex;
@@ -299,7 +300,7 @@ struct Inflater {
     const uint32_t len = (e >> 16) + ((w0 >> cl) & ((1u << ex) - 1u));
     const uint32_t dist = (ed >> 16) + ((uint32_t)(w >> (u + dl)) & ((1u << dex) - 1u));
     uint32_t wl = cl | (1u << 8) | (((e >> 8) & 255u) << 17);
-    if (CHECK) wl = kind == K_LITX ? TOK_ASCII : wl;
+    if (CHECK) wl = (kind == K_LITX && ascii) ? TOK_ASCII : wl;
     const uint32_t wm = ((ed >> 4) & 15u) == K_LEN ? (u + dl + dex) | (len << 8) | ((dist - 1u) << 17) : TOK_SLOW;
     const uint32_t wo = kind == K_EOB ? (TOK_EOB | cl) : TOK_SLOW;
     return (kind & 7u) == K_LIT ? wl : kind == K_LEN ? wm : wo;
@@ -315,8 +316,8 @@ struct Inflater {
     const uint32_t ua = (ea & 15u) + ((ea >> 8) & 15u), ub = (eb & 15u) + ((eb >> 8) & 15u);
     const uint32_t eda = sh_dist((uint32_t)(wa >> ua) & DMASK);
     const uint32_t edb = sh_dist((uint32_t)(wb >> ub) & DMASK);
-    ta = token_word<CHECK>(wa, ea, eda);
-    tb = token_word<CHECK>(wb, eb, edb);
+    ta = token_word<CHECK>(wa, ea, eda, ascii);
+    tb = token_word<CHECK>(wb, eb, edb, ascii);
   }
 
   // Huffman-coded block body until end-of-block (section 3.2.5), decoded in
@@ -621,6 +622,7 @@ __device__ __forceinline__ void inflater_setup(Inflater<WIN> &inf, const FileDes
   inf.nph = 0;
   inf.nph_stop = 0;
   inf.first = (cd.flags & (CF_FIRST | CF_CARRIED)) == CF_FIRST;
+  inf.ascii = (fd.mode & FD_BINARY) == 0u;
   inf.over = false;
   inf.emit = true;
   inf.pj = 0;

@@ -253,6 +253,32 @@ def dna_x_string(n: int, seed: int, dna: int = 150, xs: int = 300) -> bytes:
     return a.reshape(-1)[:n].tobytes()
 
 
+def binary_records(n: int, seed: int, noise_every: int = 8, noise_bytes: int = 96 << 10) -> bytes:
+    """Binary data, cut to n bytes: 32-byte records (a little-endian uint32
+    counter, four int16 random walks, a float32 ramp with noise, eight bytes
+    of small flags), with a stretch of uniformly random bytes (compressed as
+    stored blocks) after every `noise_every` stretches of 8192 records."""
+    rng = np.random.default_rng(seed)
+    rec_n = 8192
+    parts, size, k = [], 0, 0
+    while size < n:
+        base = k * rec_n
+        a = np.zeros((rec_n, 32), dtype=np.uint8)
+        a[:, 0:4] = np.arange(base, base + rec_n, dtype="<u4").view(np.uint8).reshape(rec_n, 4)
+        walk = np.cumsum(rng.integers(-3, 4, size=(rec_n, 4)), axis=0).astype("<i2")
+        a[:, 4:12] = walk.view(np.uint8).reshape(rec_n, 8)
+        ramp = (np.arange(base, base + rec_n) * 0.25 + rng.normal(0, 0.01, rec_n)).astype("<f4")
+        a[:, 12:16] = ramp.view(np.uint8).reshape(rec_n, 4)
+        a[:, 16:24] = rng.integers(0, 4, size=(rec_n, 8), dtype=np.uint8)
+        parts.append(a.tobytes())
+        size += a.size
+        k += 1
+        if k % noise_every == 0:
+            parts.append(rng.integers(0, 256, size=noise_bytes, dtype=np.uint8).tobytes())
+            size += noise_bytes
+    return b"".join(parts)[:n]
+
+
 def _deflate_segment(data: bytes, level: int, zdict: bytes | None, last: bool, strategy: int) -> bytes:
     if zdict:
         c = zlib.compressobj(level, zlib.DEFLATED, -15, 9, strategy, zdict=zdict)
@@ -335,6 +361,8 @@ def _gen(kind, size, seed, kw):
         return word_stream(size, seed, **kw)
     if kind == "dna":
         return random_dna(size, seed)
+    if kind == "binary":
+        return binary_records(size, seed)
     raise ValueError(kind)
 
 

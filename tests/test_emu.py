@@ -661,3 +661,28 @@ def test_emu_extract_dna_fastq_ranges():
     b8 = np.where(und, 0, raw).astype(np.uint8)
     got, _, st8 = E.dna_run(b8, 0, 50, bounds=bounds, threshold=20)
     assert got == want and np.array_equal(st8, st)
+
+
+def test_emu_binary_mode(orc):
+    """Binary inputs (Section VIII): with the binary option the chunk starts,
+    ends, lengths and bytes equal the oracle's binary-mode method; without it
+    no chunk after the first finds a start (non-ASCII literals), as in the
+    oracle's text mode, and the output is still the source."""
+    raw = synth.binary_records(300 << 10, 8, noise_every=1, noise_bytes=24 << 10)
+    comp = synth.gzip_member(raw, 6)
+    n = 5
+    ref = orc.pugz(comp, n, binary=True)
+    assert (ref.start >= 0).sum() >= 3
+    assert ref.status == orc.OK and ref.out.tobytes() == raw
+    st, out, r, tab = E.run(comp, n, out_cap=len(raw) + 64, sync_limit=3_000_000_000, binary=1)
+    assert st == 0 and out == raw
+    assert np.array_equal(_starts(tab), ref.start)
+    ne = ref.start >= 0
+    assert np.array_equal(tab["end"][ne].astype(np.int64), ref.end[ne])
+    assert np.array_equal(tab["len"][ne].astype(np.int64), ref.len[ne])
+    assert np.array_equal(tab["out_off"][ne].astype(np.int64), ref.off[ne])
+    assert r.n_placeholders == int(ref.placeholders.sum())
+    txt = orc.pugz(comp, n)
+    st, out, r, tab = E.run(comp, n, out_cap=len(raw) + 64, sync_limit=3_000_000_000)
+    assert st == 0 and out == raw
+    assert np.array_equal(_starts(tab), txt.start) and (txt.start[1:] < 0).all()

@@ -383,3 +383,33 @@ def test_room_of_empty_chunks(orc, case):
         # pass 1 cut short (64), or continued into empty chunks' room (4)
         cuts += int(((tab["flags"] & (64 if case != "trial-fail-10" else 4)) != 0).sum())
     assert cuts >= 1
+
+
+@pytest.mark.parametrize("level", [1, 6, 9])
+def test_binary_mode(orc, level):
+    """Binary inputs (Section VIII), 8 MiB with stored stretches: with the
+    binary option, 24 chunks have the oracle's binary-mode starts, ends,
+    lengths and output offsets and the source's bytes; with the default
+    chunking every accepted start lies on gunzip's block map; in text mode no
+    chunk after the first finds a start and the bytes are still the source."""
+    gz = _gz()
+    raw = synth.binary_records(8 << 20, 30 + level)
+    comp = synth.gzip_member(raw, level)
+    _say("binary 8 MiB level", level)
+    ref = orc.pugz(comp, 24, binary=True)
+    assert ref.status == orc.OK and ref.out.tobytes() == raw
+    got, plan = _run(comp, 24, binary=1)
+    assert got == raw
+    tab = plan.chunk_table()
+    assert np.array_equal(_starts(tab), ref.start)
+    ne = ref.start >= 0
+    for k, v in (("end", ref.end), ("len", ref.len), ("out_off", ref.off)):
+        assert np.array_equal(tab[k][ne].astype(np.int64), v[ne]), k
+    g = orc.gunzip(comp)
+    blocks = set(g.block_bit.tolist())
+    got, plan = _run(comp, 0, binary=1)
+    assert got == raw
+    s = _starts(plan.chunk_table())
+    assert set(s[s >= 0].tolist()) <= blocks and (s >= 0).sum() > len(blocks) // 2
+    got, plan = _run(comp, 24)
+    assert got == raw and (_starts(plan.chunk_table())[1:] < 0).all()

@@ -748,3 +748,44 @@ def test_symbolic_block_bits(orc, decoy_case):
         want = g.block_bit[(g.block_bit >= seg[k]) & (g.block_bit < stop)]
         assert np.array_equal(s.block_bits, want), k
         assert s.sym.size == (min((k + 1) << 20, len(data)) - (k << 20))
+
+
+@pytest.mark.parametrize("level", [1, 6, 9])
+def test_binary_mode_predicate_on_block_map(orc, level):
+    """Binary inputs (Section VIII): every non-final dynamic block of a binary
+    member (gunzip's block map) passes Appendix A's checks without the ASCII
+    test, and fails the text checks on a non-ASCII literal; stored blocks
+    (from the random stretches) and the final block fail both."""
+    raw = synth.binary_records(3 << 20, 5)
+    comp = synth.gzip_member(raw, level)
+    g = orc.gunzip(comp)
+    assert g.status == orc.OK and g.out.tobytes() == raw
+    assert (g.block_type == 0).sum() >= 2 and (g.block_type == 2).sum() >= 20
+    for b, t, f, size in zip(g.block_bit, g.block_type, g.block_final, g.block_out_len):
+        ok_bin, why_bin = orc.block_predicate(comp, int(b), binary=True)
+        ok_txt, why_txt = orc.block_predicate(comp, int(b))
+        assert not ok_txt
+        if t == 2 and not f and 1024 < size < (4 << 20):
+            assert ok_bin, (int(b), why_bin)
+            assert why_txt == "NOT_ASCII"
+        else:
+            assert not ok_bin and why_bin in ("FINAL", "NOT_DYNAMIC", "SIZE")
+
+
+@pytest.mark.parametrize("n", [2, 3, 5, 8, 13])
+def test_binary_mode_pugz(orc, n):
+    """The two-pass method on a binary member: in binary mode every chunk
+    start is a block of the map and the output is the source; in text mode
+    no chunk after the first finds a start, and the first chunk's decode
+    still gives the source."""
+    raw = synth.binary_records(2 << 20, 6)
+    comp = synth.gzip_member(raw, 6)
+    g = orc.gunzip(comp)
+    blocks = set(g.block_bit.tolist())
+    r = orc.pugz(comp, n, binary=True)
+    assert r.status == orc.OK and r.out.tobytes() == raw and r.n_repairs == 0
+    starts = r.start[r.start >= 0]
+    assert set(starts.tolist()) <= blocks and starts.size >= min(n, 10)
+    t = orc.pugz(comp, n)
+    assert t.status == orc.OK and t.out.tobytes() == raw
+    assert (t.start[1:] < 0).all()
