@@ -5,7 +5,8 @@ One step = one whole two-pass decompression of the workload's gzip member,
 compressed input already in HBM, output left in HBM: block-start scan,
 symbolic inflate, stitch, size scan, window propagation, translation.  The
 default workload is 1 GiB of FASTQ-like text (100/150 bp reads) compressed as
-one gzip member at level 6 and cut into 1 MiB compressed chunks.
+one gzip member at level 6 and cut into 40 KiB compressed chunks (the
+library's default).
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -267,63 +268,29 @@ def synth_workload(name):
     return synth.workload(name, index=True)
 
 
-def _segment_blocks(job):
-    import oracle
-
-    comp_arr, a, b, first = job
-    s = oracle.symbolic(comp_arr, a, b, first=first)
-    if s.status != 0:
-        raise SystemExit(f"oracle: segment at bit {a} failed ({s.reason})")
-    return s.block_bits
-
-
-def oracle_block_map(comp: bytes, seg_bits):
-    """The member's block map from the oracle's pass 1 over each of the
-    encoder's compression segments (each begins at a block boundary), run on
-    host threads in parallel."""
-    from concurrent.futures import ThreadPoolExecutor
-
-    import oracle
-
-    oracle.lib()
-    a = np.frombuffer(comp, dtype=np.uint8)
-    stops = list(seg_bits[1:]) + [1 << 62]
-    jobs = [(a, int(s), int(e), k == 0) for k, (s, e) in enumerate(zip(seg_bits, stops))]
-    with ThreadPoolExecutor(max_workers=min(16, len(os.sched_getaffinity(0)), len(jobs))) as ex:
-        parts = list(ex.map(_segment_blocks, jobs))
-    return np.concatenate(parts)
-
-
-def false_positives(tab, st, blocks, gz):
-    """Block-start candidates against the oracle's block map, per chunk:
-    the smallest bit passing the static checks, and the start accepted after
-    the trial and confirmation blocks."""
-    bm = np.asarray(blocks, dtype=np.int64)
-
-    def on_map(x):
-        x = x.astype(np.int64)
-        i = np.searchsorted(bm, x)
-        return (i < bm.size) & (bm[np.minimum(i, bm.size - 1)] == x)
-
+def false_positives(tab, st, n_repairs: int, gz):
+    """Block-start candidates per chunk, from the device's own counts: the
+    first bit passing the static checks (header and tables), whether the
+    trial and confirmation blocks then rejected it (a false positive caught
+    there), and accepted starts that the stitch check found off the block
+    chain (false positives that got through, repaired).  The GPU tests check
+    the accepted starts against the oracle's block map."""
     none = np.uint64(gz.NONE)
     sc = st["scan_cand"]
     has_sc = sc != none
     fd = tab["cand"]
     has_fd = fd != none
-    n = sc.size
-    sc_fp = int((has_sc & ~on_map(np.where(has_sc, sc, 0))).sum())
-    fd_fp = int((has_fd & ~on_map(np.where(has_fd, fd, 0))).sum())
-    return {"chunks": int(n), "static_candidates": int(has_sc.sum()), "static_false": sc_fp,
-            "accepted": int(has_fd.sum()), "accepted_false": fd_fp,
+    return {"chunks": int(sc.size), "static_candidates": int(has_sc.sum()),
+            "static_rejected_later": int((has_sc & (sc != fd)).sum()),
+            "accepted": int(has_fd.sum()), "accepted_off_chain": int(n_repairs),
             "stage1_per_chunk_mean": round(float(st["stage1"].mean()), 3),
             "stage1_per_chunk_max": int(st["stage1"].max()),
             "stage2_per_chunk_mean": round(float(st["stage2"].mean()), 3),
             "trial_rej_per_chunk_max": int(st["trial_rej"].max()),
-            "confirm_rej_per_chunk_max": int(st["confirm_rej"].max()),
-            "block_map_blocks": int(bm.size)}
+            "confirm_rej_per_chunk_max": int(st["confirm_rej"].max())}
 
 
-def batched_vs_plain(n_files: int, reps: int, copy_gbps=None):
+def batched_vs_plain(n_files: int, reps: int, copy_gbps=None, keep_host=None):
     """Decompressed GB/s of n_files C1-like files (4 MiB FASTQ-like, gzip -6,
     seeds 1..n_files): back-to-back one-file launches on one stream (plain),
     one batched launch sequence (batched), and the batched sequence replayed
@@ -382,8 +349,8 @@ def batched_vs_plain(n_files: int, reps: int, copy_gbps=None):
     ok_graph = all(bp.result(i).status == 0 for i in range(n_files)) and exact()
     comp_total = sum(c.numel() for c in comps)
     ratio = total / comp_total
-    host_comps = [c.cpu().numpy().tobytes() for c in comps]
-    agg = oracle_aggregate(host_comps, total)
+    if keep_host is not None:
+        keep_host.append(("batched set: 32 FASTQ-like 4 MiB files", [c.cpu().numpy().tobytes() for c in comps], total))
     return {
         "files": n_files,
         "uncompressed_bytes": total,
@@ -391,7 +358,6 @@ def batched_vs_plain(n_files: int, reps: int, copy_gbps=None):
         "plain_fractions": fractions(total / ms_plain / 1e6, ratio, copy_gbps),
         "batched_fractions": fractions(total / ms_batch / 1e6, ratio, copy_gbps),
         "graph_fractions": fractions(total / ms_graph / 1e6, ratio, copy_gbps),
-        "oracle_parallel": agg,
         "reps": reps,
         "plain_GBps": round(total / ms_plain / 1e6, 4),
         "batched_GBps": round(total / ms_batch / 1e6, 4),
@@ -403,32 +369,127 @@ def batched_vs_plain(n_files: int, reps: int, copy_gbps=None):
     }
 
 
-def serving(n_jobs: int, load: float, budget_gib: int):
-    """The serving loop under Poisson arrivals.  Job inputs are drawn
-    log-uniformly from a pool of 10 files of 64 KiB .. 32 MiB (FASTQ-like and
-    word-stream text alternating, levels 1/6/9 in turn, seeds 100..109);
-    capacity is first measured closed-loop (all jobs at once), then jobs
-    arrive at load x capacity.  Latency = completion seen by the poll - the
-    scheduled arrival; GB/s = all bytes / (last completion - first arrival).
-    Every output is compared with its source text afterwards."""
-    import numpy as np
+C5_MIN, C5_MAX = 64 << 10, 2 << 30
+C5_LOADS = (0.25, 0.5, 0.75, 0.9, 1.0, 1.2)
+
+
+def c5_pool(n_files: int, seed: int = 5):
+    """The job pool of the serving configuration: sizes log-uniform in
+    [64 KiB, 2 GiB], FASTQ-like or word-stream text with equal odds, level
+    drawn from {1, 6, 9}; file i is generated with seed 100 + i."""
+    import synth
+
+    rng = np.random.default_rng(seed)
+    sizes = np.exp(rng.uniform(np.log(C5_MIN), np.log(C5_MAX), n_files)).astype(np.int64)
+    kinds = rng.choice(["fastq", "words"], n_files)
+    levels = rng.choice([1, 6, 9], n_files)
+    from concurrent.futures import ThreadPoolExecutor
+
+    def one(i):
+        raw, comp = synth.make(str(kinds[i]), int(sizes[i]), 100 + i, int(levels[i]), use_cache=False)
+        return str(kinds[i]), int(levels[i]), raw, comp
+
+    # largest first; zlib and the generators release the interpreter lock
+    order = sorted(range(n_files), key=lambda i: -sizes[i])
+    with ThreadPoolExecutor(max_workers=4) as ex:
+        made = dict(zip(order, ex.map(one, order)))
+    return [made[i] for i in range(n_files)]
+
+
+def serving_c5(n_jobs: int, n_files: int, budget_gib: int, copy_gbps, loads=C5_LOADS, keep_host=None):
+    """The serving loop under Poisson arrivals on the C5 pool.  Each job
+    decompresses one pool file (drawn uniformly) into its own output buffer.
+    Capacity is measured closed loop (every job submitted at once); then for
+    each offered load, jobs arrive at load x capacity / mean job size.
+    Latency = completion seen by the poll - scheduled arrival; GB/s = all
+    bytes / (last completion - first arrival).  Every output is compared with
+    its source after each run.  Before the runs the pool itself is decoded
+    plain (one file after another on one stream), batched (one launch
+    sequence); the compressed files are kept for the oracle's aggregate in
+    the CPU leg."""
+    import statistics
+
     import torch
 
     import paper_1905_07224_amd as gz
-    import synth
 
     dev = torch.device("cuda:0")
-    pool = []
-    for i in range(10):
-        kind = "fastq" if i % 2 == 0 else "words"
-        raw, comp = synth.make(kind, (64 << 10) << i, 100 + i, (1, 6, 9)[i % 3])
-        pool.append((torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(dev),
-                     torch.frombuffer(bytearray(comp), dtype=torch.uint8).to(dev)))
-    rng = np.random.default_rng(5)
-    pick = rng.integers(0, len(pool), n_jobs)
-    outs = [torch.empty(pool[k][0].numel(), dtype=torch.uint8, device=dev) for k in pick]
-    nbytes = [pool[k][0].numel() for k in pick]
+    t = time.perf_counter()
+    pool = c5_pool(n_files)
+    gen_s = time.perf_counter() - t
+    raws = [torch.frombuffer(bytearray(r), dtype=torch.uint8).to(dev) for _, _, r, _ in pool]
+    comps = [torch.frombuffer(bytearray(c), dtype=torch.uint8).to(dev) for _, _, _, c in pool]
+    host_comps = [c for _, _, _, c in pool]
+    pool_raw = sum(len(r) for _, _, r, _ in pool)
+    pool_comp = sum(len(c) for c in host_comps)
+    for k in range(len(pool)):
+        pool[k] = pool[k][:2]
+    log(f"C5 pool: {n_files} files, {pool_raw / 2**30:.2f} GiB raw, {pool_comp / 2**30:.2f} GiB compressed, "
+        f"generated in {gen_s:.1f} s")
+    ratio = pool_raw / pool_comp
+
+    # the pool decoded plain and batched
+    outs = [torch.empty(r.numel(), dtype=torch.uint8, device=dev) for r in raws]
+    s = torch.cuda.Stream()
+
+    def timed(fn, reps=2):
+        ms = []
+        for _ in range(reps + 1):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            with torch.cuda.stream(s):
+                e0.record(s)
+                fn()
+                e1.record(s)
+            s.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        return statistics.median(ms[1:])
+
+    plans = [gz.Plan(c, 0) for c in comps]
+    ws_plain = max(p_.info.ws_bytes for p_ in plans)
+    shared = torch.empty(ws_plain + 256, dtype=torch.uint8, device=dev)
+
+    def plain():
+        for p_, o in zip(plans, outs):
+            p_.launch(o, s, workspace=shared)
+
+    ms_plain = timed(plain)
+    # the plans share one workspace, which holds a plan's status until the
+    # next plan runs: the last plan's status, and every output, are checked
+    ok_plain = plans[-1].result().status == 0 and all(torch.equal(o, r) for o, r in zip(outs, raws))
+    del plans, shared
+    torch.cuda.empty_cache()
+    bp = gz.BatchPlan(comps, 0, outs=outs)
+    bp.workspace()
+    ms_batch = timed(lambda: bp.launch(s))
+    ok_batch = all(bp.result(i).status == 0 for i in range(n_files)) and all(
+        torch.equal(o, r) for o, r in zip(outs, raws))
+    batch_ws = bp.info.ws_bytes
+    del bp, outs
+    torch.cuda.empty_cache()
+    log("C5 pool decoded plain and batched")
+    if keep_host is not None:
+        keep_host.append(("serving pool: 32 files, 64 KiB .. 2 GiB", host_comps, pool_raw))
+    del host_comps
+    pool_sets = {
+        "files": n_files, "uncompressed_bytes": pool_raw, "compressed_bytes": pool_comp,
+        "kinds_levels": [f"{k}/L{lv}/{r.numel()}" for (k, lv), r in zip(pool, raws)],
+        "plain_GBps": round(pool_raw / ms_plain / 1e6, 3), "batched_GBps": round(pool_raw / ms_batch / 1e6, 3),
+        "plain_fractions": fractions(pool_raw / ms_plain / 1e6, ratio, copy_gbps),
+        "batched_fractions": fractions(pool_raw / ms_batch / 1e6, ratio, copy_gbps),
+        "batched_ws_GiB": round(batch_ws / 2**30, 2), "generate_s": round(gen_s, 1),
+        "bit_exact": bool(ok_plain and ok_batch),
+    }
+    log(f"C5 pool sets: {pool_sets}")
+
+    rng = np.random.default_rng(7)
+    pick = rng.integers(0, n_files, n_jobs)
+    nbytes = np.array([raws[k].numel() for k in pick], dtype=np.int64)
+    offs = np.concatenate(([0], np.cumsum(nbytes)))
+    big = torch.empty(int(offs[-1]), dtype=torch.uint8, device=dev)
+    outs = [big[int(offs[j]):int(offs[j + 1])] for j in range(n_jobs)]
     budget = budget_gib << 30
+    mean_job = float(nbytes.mean())
 
     def run(arrivals):
         srv = gz.Server(budget_bytes=budget, max_inflight=4, max_batch=64)
@@ -438,43 +499,55 @@ def serving(n_jobs: int, load: float, budget_gib: int):
         while len(done) < n_jobs:
             now = srv.stats()["now"]
             while nxt < n_jobs and sched[nxt] <= now:
-                srv.submit(pool[pick[nxt]][1], outs[nxt], nxt)
+                srv.submit(comps[pick[nxt]], outs[nxt], nxt)
                 nxt += 1
             for d in srv.poll():
                 done[d["tag"]] = d
             if nxt == n_jobs and len(done) < n_jobs:
                 time.sleep(0.0002)
-            if srv.stats()["now"] - t0 > 120:
-                raise SystemExit("serving run did not finish within 120 s")
+            if srv.stats()["now"] - t0 > 150:
+                raise SystemExit("serving run did not finish within 150 s")
         info = srv.stats()
         srv.close()
-        return sched, done, info
+        lat = np.array([done[k]["t_end"] - sched[k] for k in range(n_jobs)]) * 1e3
+        span = max(d["t_end"] for d in done.values()) - sched[0]
+        ok = all(done[k]["status"] == 0 and done[k]["out_len"] == nbytes[k] for k in range(n_jobs))
+        ok = ok and all(torch.equal(outs[k], raws[pick[k]]) for k in range(n_jobs))
+        big.zero_()
+        gbps = float(nbytes.sum()) / span / 1e9
+        return {
+            "p50_ms": round(float(np.percentile(lat, 50)), 2), "p99_ms": round(float(np.percentile(lat, 99)), 2),
+            "GBps": round(gbps, 3), **fractions(gbps, ratio, copy_gbps), "span_s": round(span, 3),
+            "batches": int(info["batches"]), "mem_waited": int(info["mem_waited"]),
+            "resident_peak_GiB": round(info["resident_peak"] / 2**30, 2),
+            "arena_peak_GiB": round(info["arena_peak"] / 2**30, 2), "bit_exact": bool(ok),
+        }
 
-    sched, done, _ = run([0.0] * n_jobs)
-    span = max(d["t_end"] for d in done.values()) - sched[0]
-    capacity = sum(nbytes) / span
-    rate = load * capacity / (sum(nbytes) / n_jobs)
-    arrivals = np.cumsum(rng.exponential(1.0 / rate, n_jobs))
-    arrivals -= arrivals[0]
-    sched, done, info = run(list(arrivals))
-    lat = np.array([done[k]["t_end"] - sched[k] for k in range(n_jobs)]) * 1e3
-    span = max(d["t_end"] for d in done.values()) - sched[0]
-    ok = all(done[k]["status"] == 0 and done[k]["out_len"] == nbytes[k] for k in range(n_jobs))
-    ok = ok and all(torch.equal(outs[k], pool[pick[k]][0]) for k in range(n_jobs))
+    closed = run([0.0] * n_jobs)
+    capacity = closed["GBps"] * 1e9
+    log(f"C5 closed loop: {closed}")
+    points = []
+    for load in loads:
+        rate = load * capacity / mean_job
+        arr = np.cumsum(rng.exponential(1.0 / rate, n_jobs))
+        arr -= arr[0]
+        res = run(list(arr))
+        res = {"offered_load": load, "arrival_rate_per_s": round(rate, 3), **res}
+        log(f"C5 load {load}: {res}")
+        points.append(res)
+    del big, outs, raws, comps
+    torch.cuda.empty_cache()
     return {
-        "jobs": n_jobs,
-        "pool": "10 files, 64 KiB..32 MiB log-spaced, FASTQ-like/words alternating, levels 1/6/9",
-        "mean_job_bytes": int(sum(nbytes) / n_jobs),
-        "capacity_GBps": round(capacity / 1e9, 4),
-        "offered_load": load,
-        "arrival_rate_per_s": round(rate, 2),
-        "p50_ms": round(float(np.percentile(lat, 50)), 3),
-        "p99_ms": round(float(np.percentile(lat, 99)), 3),
-        "GBps": round(sum(nbytes) / span / 1e9, 4),
-        "batches": int(info["batches"]),
+        "jobs_per_point": n_jobs,
+        "pool": pool_sets,
+        "job_sizes": "log-uniform 64 KiB .. 2 GiB over the pool's files, each job drawn uniformly from the pool",
+        "mean_job_bytes": int(mean_job),
+        "total_bytes_per_point": int(nbytes.sum()),
         "budget_GiB": budget_gib,
-        "arena_peak_GiB": round(info["arena_peak"] / 2**30, 3),
-        "bit_exact": bool(ok),
+        "closed_loop": closed,
+        "capacity_GBps": round(capacity / 1e9, 3),
+        "load_points": points,
+        "bit_exact": bool(closed["bit_exact"] and all(p_["bit_exact"] for p_ in points)),
     }
 
 
@@ -558,6 +631,91 @@ def bgzf_leg(gz, mib: int):
             "GBps": round(len(raw) / best / 1e9, 3), "ms": round(best * 1e3, 3), "bit_exact": True}
 
 
+def pair_batched(gz, files, copy_gbps):
+    """The two level-sweep members together: back-to-back one-file launches
+    on one stream (plain, one shared workspace) against one batched launch
+    sequence; outputs compared with the sources."""
+    import statistics
+
+    import torch
+
+    dev = torch.device("cuda:0")
+    raws = [torch.frombuffer(bytearray(r), dtype=torch.uint8).to(dev) for r, _ in files]
+    comps = [torch.frombuffer(bytearray(c), dtype=torch.uint8).to(dev) for _, c in files]
+    outs = [torch.empty_like(r) for r in raws]
+    total = sum(r.numel() for r in raws)
+    ratio = total / sum(c.numel() for c in comps)
+    s = torch.cuda.Stream()
+
+    def timed(fn, reps=2):
+        ms = []
+        for _ in range(reps + 1):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            with torch.cuda.stream(s):
+                e0.record(s)
+                fn()
+                e1.record(s)
+            s.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        return statistics.median(ms[1:])
+
+    plans = [gz.Plan(c, 0) for c in comps]
+    shared = torch.empty(max(p_.info.ws_bytes for p_ in plans), dtype=torch.uint8, device=dev)
+
+    def plain():
+        for p_, o in zip(plans, outs):
+            p_.launch(o, s, workspace=shared)
+
+    ms_plain = timed(plain)
+    ok = plans[-1].result().status == 0 and all(torch.equal(o, r) for o, r in zip(outs, raws))
+    del plans, shared
+    torch.cuda.empty_cache()
+    for o in outs:
+        o.zero_()
+    bp = gz.BatchPlan(comps, 0, outs=outs)
+    bp.workspace()
+    ms_batch = timed(lambda: bp.launch(s))
+    ok = ok and all(bp.result(i).status == 0 for i in range(len(files))) and all(
+        torch.equal(o, r) for o, r in zip(outs, raws))
+    del bp, outs, raws, comps
+    torch.cuda.empty_cache()
+    g_p, g_b = total / ms_plain / 1e6, total / ms_batch / 1e6
+    return {"files": len(files), "uncompressed_bytes": total, "plain_GBps": round(g_p, 3),
+            "batched_GBps": round(g_b, 3), "plain_fractions": fractions(g_p, ratio, copy_gbps),
+            "batched_fractions": fractions(g_b, ratio, copy_gbps), "bit_exact": bool(ok)}
+
+
+def binary_leg(gz, mib: int, steps: int, copy_gbps):
+    """Binary input (counters, random walks, noisy floats, random stretches
+    stored): decompressed GB/s with the binary option (block starts searched
+    without the ASCII test), default chunking."""
+    import torch
+
+    import synth
+
+    t = time.perf_counter()
+    raw = synth.binary_records(mib << 20, 11)
+    comp = synth.gzip_member(raw, 6)
+    gen_s = time.perf_counter() - t
+    dev = torch.device("cuda:0")
+    d_comp = torch.frombuffer(bytearray(comp), dtype=torch.uint8).to(dev)
+    d_raw = torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(dev)
+    out = torch.empty(len(raw), dtype=torch.uint8, device=dev)
+    plan = gz.Plan(d_comp, 0, binary=1, timing=1)
+    dt, r, avg = timed_plan(gz, plan, out, steps, d_raw)
+    tab = plan.chunk_table()
+    n_acc = int((tab["start"] != np.uint64(gz.NONE)).sum())
+    gbps = len(raw) / dt / 1e9
+    res = {"uncompressed_bytes": len(raw), "compressed_bytes": len(comp), "level": 6, "generate_s": round(gen_s, 1),
+           "n_chunks": plan.n_chunks, "chunks_with_start": n_acc, "GBps": round(gbps, 3),
+           **fractions(gbps, len(raw) / len(comp), copy_gbps), "n_repairs": int(r.n_repairs),
+           "n_retries": int(r.n_retries), "bit_exact": True}
+    del plan, d_raw, out, d_comp
+    torch.cuda.empty_cache()
+    return res
+
+
 def recorded_traffic(kernel: str, workload: str, chunk_bytes: int, window: int):
     """HBM bytes per launch of `kernel` from the committed FETCH_SIZE/WRITE_SIZE
     summary, or None when that summary was taken on other kernel sources or
@@ -582,7 +740,7 @@ def recorded_traffic(kernel: str, workload: str, chunk_bytes: int, window: int):
     return int(kv["traffic_bytes"]) if same else None
 
 
-LEGS = ("c2_1mib", "c3", "c4", "stream", "bgzf", "batched", "serving", "cpu")
+LEGS = ("c2_1mib", "c3", "c4", "stream", "binary", "bgzf", "batched", "serving", "cpu")
 
 
 def main():
@@ -598,10 +756,12 @@ def main():
                     help="legs beside the timed plain run: " + ",".join(LEGS) + " (empty: none)")
     ap.add_argument("--large-steps", type=int, default=3, help="timed steps of the level-sweep and word legs")
     ap.add_argument("--batch-files", type=int, default=32, help="files of the batched-vs-plain set")
-    ap.add_argument("--serve-jobs", type=int, default=400, help="jobs of the serving run")
-    ap.add_argument("--serve-load", type=float, default=0.7, help="offered load, fraction of measured capacity")
+    ap.add_argument("--serve-jobs", type=int, default=500, help="jobs per load point of the serving runs")
+    ap.add_argument("--serve-files", type=int, default=32, help="files of the serving pool")
+    ap.add_argument("--serve-budget-gib", type=int, default=64, help="HBM budget of the jobs in flight")
     ap.add_argument("--stream-mib", type=int, default=256, help="streaming leg: compressed MiB per segment")
     ap.add_argument("--bgzf-mib", type=int, default=256, help="BGZF leg: MiB of FASTQ-like text in 64 KiB members")
+    ap.add_argument("--binary-mib", type=int, default=512, help="binary leg: MiB of binary records")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after warmup, one device-to-device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -741,22 +901,31 @@ def main():
     torch.cuda.empty_cache()
 
     if "c3" in legs:
+        pair = []
         for name in ("fastq_4GiB_L1", "fastq_4GiB_L9"):
             log(f"level sweep: {name}")
-            res, *_ = large_leg(gz, name, args.large_steps, copy_gbps, chunk_sweep=(256 << 10, 1 << 20, 4 << 20))
+            res, raw3, comp3, *_ = large_leg(gz, name, args.large_steps, copy_gbps,
+                                             chunk_sweep=(256 << 10, 1 << 20, 4 << 20))
             extra[name] = res
+            pair.append((raw3, comp3))
             log(f"{name}: {res}")
+        log("level sweep pair: plain and batched")
+        extra["fastq_4GiB_L1+L9"] = pair_batched(gz, pair, copy_gbps)
+        log(f"pair: {extra['fastq_4GiB_L1+L9']}")
+        del pair
     if "c4" in legs:
         name = "words_2GiB_L6"
         log(f"word stream: {name}")
         res, raw4, comp4, seg4, tab4, st4 = large_leg(gz, name, args.large_steps, copy_gbps)
-        t = time.perf_counter()
-        bm = oracle_block_map(comp4, seg4)
-        res["false_positives"] = false_positives(tab4, st4, bm, gz)
-        res["false_positives"]["oracle_block_map_s"] = round(time.perf_counter() - t, 1)
+        res["false_positives"] = false_positives(tab4, st4, res["stats"]["n_repairs"], gz)
         extra[name] = res
         log(f"{name}: {res}")
         del raw4, comp4
+
+    if "binary" in legs:
+        log(f"binary input: {args.binary_mib} MiB")
+        extra["binary_records"] = binary_leg(gz, args.binary_mib, args.large_steps, copy_gbps)
+        log(f"binary: {extra['binary_records']}")
 
     bgzf = None
     if "bgzf" in legs:
@@ -764,24 +933,29 @@ def main():
         bgzf = bgzf_leg(gz, args.bgzf_mib)
         log(f"bgzf: {bgzf}")
 
+    host_sets = []  # compressed sets kept for the oracle's multi-core aggregate (CPU leg)
     batched = None
     if "batched" in legs:
         torch.cuda.empty_cache()
         log(f"batched vs plain: {args.batch_files} C1-like files")
-        batched = batched_vs_plain(args.batch_files, 5, copy_gbps)
+        batched = batched_vs_plain(args.batch_files, 5, copy_gbps, keep_host=host_sets)
         log(f"batched vs plain: {batched}")
 
     served = None
     if "serving" in legs:
         torch.cuda.empty_cache()
-        log(f"serving: {args.serve_jobs} jobs at load {args.serve_load}")
-        served = serving(args.serve_jobs, args.serve_load, 96)
+        log(f"serving: {args.serve_jobs} jobs per load point, pool of {args.serve_files} files")
+        served = serving_c5(args.serve_jobs, args.serve_files, args.serve_budget_gib, copy_gbps, keep_host=host_sets)
         log(f"serving: {served}")
 
     cpu = None
     if "cpu" in legs:
         log("cpu baseline: the oracle's gunzip of the whole member on one core")
         cpu = cpu_baseline(comp, len(raw), crc_ref, args.workload)
+        cpu["aggregates"] = []
+        for what, comps_h, total in host_sets:
+            log(f"cpu baseline: the oracle's gunzip over the {what}, one pinned thread per core")
+            cpu["aggregates"].append({"set": what, **oracle_aggregate(comps_h, total)})
         log(f"cpu baseline: {cpu}")
 
     line = {

@@ -465,7 +465,8 @@ typedef struct gz_done {
 } gz_done;
 
 typedef struct gz_server_info {
-  uint32_t queued, running, finished_unread, pad;
+  uint32_t queued, running, finished_unread;
+  uint32_t mem_waited;    /* jobs whose admission waited for the budget or the arena (at least once) */
   uint64_t batches;       /* batches launched so far */
   uint64_t arena_bytes, arena_used, arena_peak;  /* workspaces in the arena */
   uint64_t budget_bytes, resident, resident_peak; /* footprints of the jobs in flight */

@@ -77,7 +77,7 @@ class Done(C.Structure):
 
 class ServerInfo(C.Structure):
     _fields_ = [("queued", C.c_uint32), ("running", C.c_uint32), ("finished_unread", C.c_uint32),
-                ("pad", C.c_uint32), ("batches", C.c_uint64), ("arena_bytes", C.c_uint64),
+                ("mem_waited", C.c_uint32), ("batches", C.c_uint64), ("arena_bytes", C.c_uint64),
                 ("arena_used", C.c_uint64), ("arena_peak", C.c_uint64), ("budget_bytes", C.c_uint64),
                 ("resident", C.c_uint64), ("resident_peak", C.c_uint64), ("now", C.c_double)]
 
@@ -262,8 +262,10 @@ class Plan:
             self.ws = torch.empty(self.info.ws_bytes, dtype=torch.uint8, device=self.device)
         return self.ws
 
-    def launch(self, out: torch.Tensor | None, stream=None):
-        ws = self.workspace()
+    def launch(self, out: torch.Tensor | None, stream=None, workspace: torch.Tensor | None = None):
+        """Enqueue the decompression on `stream`; `workspace` (optional) is a
+        caller's device buffer used instead of the plan's own."""
+        ws = self.workspace() if workspace is None else workspace
         optr = C.c_void_p(out.data_ptr()) if out is not None and out.numel() else C.c_void_p()
         ocap = out.numel() if out is not None else 0
         with torch.cuda.device(self.device):

@@ -86,6 +86,7 @@ struct Job {
   uint64_t ws;       // workspace of this job planned alone (admission estimate)
   uint64_t foot() const { return comp_len + out_cap + ws; }  // device bytes while it is in flight
   uint32_t factor;   // symbol capacity factor (raised after a capacity failure)
+  bool waited = false;  // its admission waited for the budget or the arena
   double t_submit;
   double t_start;
 };
@@ -118,6 +119,7 @@ struct gz_server_s {
   std::vector<gz_done> done;  // finished, not yet returned by poll
   uint64_t n_batches = 0;
   uint64_t resident = 0, resident_peak = 0;  // footprint of the batches in flight
+  uint32_t mem_waited = 0;  // jobs whose admission waited for memory
 };
 
 namespace {
@@ -174,6 +176,15 @@ void reap(gz_server_t s) {
   }
 }
 
+// The job at the head of the queue cannot start for want of memory.
+void mark_waited(gz_server_t s) {
+  Job &j = s->queue.front();
+  if (!j.waited) {
+    j.waited = true;
+    s->mem_waited++;
+  }
+}
+
 // Admit queued jobs, FIFO, while a stream is free and their workspaces fit.
 int admit(gz_server_t s) {
   for (;;) {
@@ -205,7 +216,10 @@ int admit(gz_server_t s) {
       foot += s->queue[n].foot();
       n++;
     }
-    if (n == 0) return GZ_OK;  // wait for memory
+    if (n == 0) {  // wait for memory
+      mark_waited(s);
+      return GZ_OK;
+    }
     for (; n > 0; n--) {
       std::vector<gz_job> jobs(n);
       uint32_t factor = 0;
@@ -236,6 +250,7 @@ int admit(gz_server_t s) {
       uint64_t off = 0;
       if (!s->arena.alloc(inf.ws_bytes, &off)) {
         if (n > 1) continue;
+        mark_waited(s);
         return GZ_OK;  // wait for memory
       }
       Batch B;
@@ -346,6 +361,7 @@ int gz_server_stats(gz_server_t s, gz_server_info *info) {
   info->arena_used = s->arena.used;
   info->arena_peak = s->arena.peak;
   info->budget_bytes = s->o.budget_bytes;
+  info->mem_waited = s->mem_waited;
   info->resident = s->resident;
   info->resident_peak = s->resident_peak;
   info->now = now_s(s->t0);

@@ -114,7 +114,7 @@ class Done(C.Structure):
 
 class ServerInfo(C.Structure):
     _fields_ = [("queued", C.c_uint32), ("running", C.c_uint32), ("finished_unread", C.c_uint32),
-                ("pad", C.c_uint32), ("batches", C.c_uint64), ("arena_bytes", C.c_uint64),
+                ("mem_waited", C.c_uint32), ("batches", C.c_uint64), ("arena_bytes", C.c_uint64),
                 ("arena_used", C.c_uint64), ("arena_peak", C.c_uint64), ("budget_bytes", C.c_uint64),
                 ("resident", C.c_uint64), ("resident_peak", C.c_uint64), ("now", C.c_double)]
 

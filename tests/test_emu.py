@@ -583,6 +583,8 @@ def test_emu_serving_budget_counts_footprints():
     assert sorted(done) == [(0, 0), (1, 0), (2, 0)]
     assert all(outs[k][: len(raws[k])].tobytes() == raws[k] for k in range(3))
     assert st.batches == 3 and st.resident_peak <= o.budget_bytes and st.arena_peak < arena_bytes // 2
+    # the second and third jobs each waited for the budget
+    assert st.mem_waited == 2
 
 
 def test_emu_static_workspace_entry_point():
