@@ -2,16 +2,24 @@
 //
 //   k_init       clear per-chunk and per-file state (a kernel, so the whole
 //                sequence can be captured in a graph)
-//   k_scan       block-start search (Section VI-A, Appendix A): one lane per
-//                candidate bit, survivors checked by the whole wave
+//   k_scan       block-start search (Section VI-A, Appendix A): stage 1 on
+//                every candidate bit (32 per lane per step), stage 2 (the
+//                code tables) on the survivors, one survivor per lane
+//   k_capacity   each chunk's symbol region from the span to the next start
 //   k_inflate    pass 1, decompress(C_i, w_hat_i) (Section VI-C): one wave per
 //                chunk from a persistent work queue, tables and the recent
-//                history in LDS, 16-bit symbols to HBM
+//                history in LDS, 16-bit symbols to HBM; the trial block and
+//                the confirmation blocks of the start checks
+//   k_confirm    confirmation blocks owed past a chunk's stop (deferred)
+//   k_redo       chunks whose deferred confirmation failed search again
 //   k_stitch     chunks whose stop was not the next accepted start continue
 //   k_finalize   stitch check, sequential repair when a start is off the
 //                block chain, output offsets (exclusive scan of |D_i|)
-//   k_propagate  pass 2a: windows resolved chunk after chunk
+//   k_tilescan   translate tiles and the list of chunks with a start
+//   k_prop_*     pass 2a: windows resolved by a scan of composed maps over
+//                segments of 64 chunks
 //   k_translate  pass 2b: every U_j replaced by w_i[j], written to the output
+//   k_crc        CRC-32 of every output (RFC 1952), checked by k_crc_final
 #include <hip/hip_runtime.h>
 
 #include <mutex>
