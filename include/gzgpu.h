@@ -332,6 +332,23 @@ int gz_stream_checkpoint(gz_stream_t stream, gz_checkpoint *cp);
 int gz_stream_resume(gz_stream_t stream, const gz_checkpoint *cp);
 void gz_stream_destroy(gz_stream_t stream);
 
+/* Concatenated gzip members (a "multi-part" file, which Section VIII lists
+ * as a limitation of the paper's tool): every member is decoded by the whole
+ * two-pass path, its chunks in parallel, and checked against its own
+ * trailer; the outputs go back to back at d_out.  A member's end is known
+ * only once its final block is decoded (a gzip header may also occur inside
+ * compressed data), so the members are decoded one after another and the
+ * call waits for each (synchronous, on `stream`).  d_ws == NULL: only
+ * *ws_needed (the workspace for the largest possible member) is set.
+ * *out_len: bytes written; *n_members: members finished.  Errors: GZ_E_ARG,
+ * GZ_E_HEADER (bytes after a member that are not a member), GZ_E_CAPACITY
+ * (d_out full before the input ends, or the workspace too small after a
+ * raised symbol factor: *ws_needed gives the size), the first failing
+ * member's status (GZ_E_DATA, GZ_E_CRC, GZ_E_SIZE), GZ_E_HIP. */
+int gz_decompress_members(const void *d_comp, size_t comp_len, void *d_out, size_t out_cap, void *d_ws,
+                          size_t ws_bytes, const gz_opts *opts, void *stream, uint64_t *out_len,
+                          uint32_t *n_members, uint64_t *ws_needed);
+
 /* BGZF-style input (RFC 1952 members whose extra field holds the 'BC'
  * subfield with the member's size; the paper's experiments excluded such
  * blocked files, Section VII): every member is a file of one batch plan,

@@ -119,7 +119,8 @@ EXPORTS = ["gz_plan", "gz_plan_batch", "gz_plan_info", "gz_decompress", "gz_deco
            "gz_server_poll", "gz_server_stats", "gz_server_destroy", "gz_stream_open", "gz_stream_get_info",
            "gz_stream_next", "gz_stream_wait", "gz_stream_checkpoint", "gz_stream_resume", "gz_stream_destroy",
            "gz_plan_probes", "gz_find_blocks", "gz_probe_starts", "gz_stream_open_at", "gz_count_byte",
-           "gz_plan_bgzf", "gz_chunk_stats", "gz_decompress_static", "gz_extract_dna_ws", "gz_extract_dna"]
+           "gz_plan_bgzf", "gz_chunk_stats", "gz_decompress_static", "gz_extract_dna_ws", "gz_extract_dna",
+           "gz_decompress_members"]
 GZ_N_PASSES = N_PASSES = 13
 GZ_SCRATCH_BYTES = 256 << 20  # static workspace of gz_decompress_static, per GPU
 # defaults of gz_opts (include/gzgpu.h)
@@ -176,6 +177,8 @@ def lib():
         L.gz_probe_starts.argtypes = [vp, vp, vp]
         L.gz_stream_open_at.argtypes = [C.POINTER(vp), vp, C.c_size_t, u64, C.c_uint32, u64, C.POINTER(Opts)]
         L.gz_count_byte.argtypes = [vp, u64, C.c_uint32, u64, u64, vp, u64, vp]
+        L.gz_decompress_members.argtypes = [vp, C.c_size_t, vp, C.c_size_t, vp, C.c_size_t, C.POINTER(Opts), vp,
+                                            C.POINTER(u64), C.POINTER(C.c_uint32), C.POINTER(u64)]
         L.gz_extract_dna_ws.argtypes = [u64]
         L.gz_extract_dna_ws.restype = u64
         L.gz_extract_dna.argtypes = [vp, u64, C.c_uint32, C.c_uint32, C.c_uint32, vp, u64, vp, vp, C.c_uint32,
@@ -722,6 +725,24 @@ def count_byte(buf: torch.Tensor, value: int, window: int, counts: torch.Tensor,
     with torch.cuda.device(buf.device):
         _check(lib().gz_count_byte(C.c_void_p(buf.data_ptr()), buf.numel(), int(value), int(first), int(window),
                                    C.c_void_p(counts.data_ptr()), counts.numel(), _stream_handle(stream)))
+
+
+def decompress_members(comp, out: torch.Tensor, stream=None, **opts):
+    """Concatenated gzip members into `out` (gz_decompress_members: each
+    member by the whole parallel path, members one after another; waits).
+    Returns (bytes written, members).  Raises GzError on failure."""
+    comp = _as_device_bytes(comp)
+    o = _opts(**opts)
+    need = C.c_uint64(0)
+    n_out, n_mem = C.c_uint64(0), C.c_uint32(0)
+    with torch.cuda.device(comp.device):
+        _check(lib().gz_decompress_members(C.c_void_p(comp.data_ptr()), comp.numel(), None, 0, None, 0, C.byref(o),
+                                           None, None, None, C.byref(need)))
+        ws = torch.empty(int(need.value), dtype=torch.uint8, device=comp.device)
+        _check(lib().gz_decompress_members(C.c_void_p(comp.data_ptr()), comp.numel(), C.c_void_p(out.data_ptr()),
+                                           out.numel(), C.c_void_p(ws.data_ptr()), ws.numel(), C.byref(o),
+                                           _stream_handle(stream), C.byref(n_out), C.byref(n_mem), C.byref(need)))
+    return int(n_out.value), int(n_mem.value)
 
 
 class DnaSeq(C.Structure):

@@ -1499,4 +1499,67 @@ void gz_stream_destroy(gz_stream_t s) {
   delete s;
 }
 
+// Concatenated members: a stream whose segments are whole members (the
+// segment size is the whole input, and a segment ends at its member's final
+// block), each decoded by the whole path, written back to back.
+int gz_decompress_members(const void *d_comp, size_t comp_len, void *d_out, size_t out_cap, void *d_ws,
+                          size_t ws_bytes, const gz_opts *opts, void *stream, uint64_t *out_len,
+                          uint32_t *n_members, uint64_t *ws_needed) {
+  if (out_len) *out_len = 0;
+  if (n_members) *n_members = 0;
+  if (!d_comp || comp_len == 0 || (d_ws && (!d_out || out_cap == 0))) return GZ_E_ARG;
+  gz_stream_t s = nullptr;
+  int r = gz_stream_open(&s, d_comp, comp_len, comp_len, opts);
+  if (r != GZ_OK) return r;
+  gz_stream_info info;
+  r = gz_stream_get_info(s, &info);
+  if (r == GZ_OK && ws_needed) *ws_needed = info.ws_bytes;
+  if (r != GZ_OK || !d_ws) {
+    gz_stream_destroy(s);
+    return r;
+  }
+  uint64_t total = 0;
+  uint32_t members = 0;
+  // one segment per member; a capacity retry per segment at most
+  for (uint64_t it = 0; it < 2 * (uint64_t)comp_len + 4; it++) {
+    if (total >= out_cap) {
+      snprintf(g_err, sizeof(g_err), "output full after %llu bytes", (unsigned long long)total);
+      r = GZ_E_CAPACITY;
+      break;
+    }
+    r = gz_stream_next(s, (uint8_t *)d_out + total, out_cap - total, d_ws, ws_bytes, stream);
+    if (r != GZ_OK) break;
+    gz_segment_result res;
+    r = gz_stream_wait(s, &res);
+    if (r != GZ_OK) break;
+    if (res.status == GZ_E_CAPACITY && res.out_needed <= out_cap - total) {
+      // more symbols than planned: the stream raised its factor; retry if
+      // the workspace still suffices
+      r = gz_stream_get_info(s, &info);
+      if (r == GZ_OK && ws_needed) *ws_needed = info.ws_bytes;
+      if (r == GZ_OK && info.ws_bytes <= ws_bytes) continue;
+      if (r == GZ_OK) r = GZ_E_CAPACITY;
+      break;
+    }
+    if (res.status == GZ_E_HEADER && res.member_done) {
+      // the member is whole; the bytes after it are not a member
+      total += res.out_len;
+      members++;
+      r = GZ_E_HEADER;
+      break;
+    }
+    if (res.status != GZ_OK) {
+      r = res.status;
+      break;
+    }
+    total += res.out_len;
+    if (res.member_done) members++;
+    if (res.done) break;
+  }
+  if (out_len) *out_len = total;
+  if (n_members) *n_members = members;
+  gz_stream_destroy(s);
+  return r;
+}
+
 }  // extern "C"

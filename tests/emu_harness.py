@@ -366,3 +366,29 @@ def dna_run(buf, marker=0, min_len=1, bounds=None, threshold=1, max_seqs=None):
     k = min(int(total[0]), max_seqs)
     out = [(int(s["start"]), int(s["len"]), int(s["nu"])) for s in seqs[:k]]
     return out, int(total[0]), (st[: 3 * nr].reshape(nr, 3).astype(np.int64) if st is not None else None)
+
+
+def members_run(comp: bytes, out_cap: int, ws_extra: int = 0, **opts):
+    """gz_decompress_members on the CPU executor: (status, bytes, members)."""
+    L = lib()
+    vp = C.c_void_p
+    L.gz_decompress_members.argtypes = [vp, C.c_size_t, vp, C.c_size_t, vp, C.c_size_t, C.POINTER(Opts), vp,
+                                        C.POINTER(C.c_uint64), C.POINTER(C.c_uint32), C.POINTER(C.c_uint64)]
+    L.emu_set_sync_limit(3_000_000_000)
+    store = padded(comp)
+    buf = store[: len(comp)]
+    o = Opts()
+    for k, v in opts.items():
+        setattr(o, k, v)
+    need, n_out, n_mem = C.c_uint64(), C.c_uint64(), C.c_uint32()
+    st = L.gz_decompress_members(vp(buf.ctypes.data), buf.size, None, 0, None, 0, C.byref(o), None, None, None,
+                                 C.byref(need))
+    if st != 0:
+        return st, b"", 0
+    wsb = need.value + ws_extra
+    raw_ws = np.zeros(wsb + 512, dtype=np.uint8)
+    ws = raw_ws[(-raw_ws.ctypes.data) % 256:][:wsb]
+    out = np.zeros(max(1, out_cap), dtype=np.uint8)
+    st = L.gz_decompress_members(vp(buf.ctypes.data), buf.size, vp(out.ctypes.data), out_cap, vp(ws.ctypes.data),
+                                 wsb, C.byref(o), None, C.byref(n_out), C.byref(n_mem), C.byref(need))
+    return st, out[: n_out.value].tobytes(), n_mem.value

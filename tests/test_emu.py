@@ -433,6 +433,30 @@ def test_emu_stream_multiple_members(orc):
     assert sc[-1][0]["status"] == -6 and sc[-1][0]["member"] == 1
 
 
+def test_emu_decompress_members(orc):
+    """gz_decompress_members: concatenated members (one empty, two
+    BGZF-style) decoded member after member by the whole path give the
+    oracle's gunzip of the whole input; a wrong CRC in the second member
+    gives the oracle's CRC status; a full output gives CAPACITY; a
+    non-member tail gives the oracle's header status."""
+    parts, comps = _members()
+    comp = b"".join(comps)
+    g = orc.gunzip(comp)
+    st, out, n = E.members_run(comp, g.out.size + 16, chunk_bytes=4096)
+    assert st == 0 and out == g.out.tobytes() and n == len(parts)
+    crc_at = len(comps[0]) + len(comps[1]) - 8
+    bc = bytearray(comp)
+    bc[crc_at] ^= 1
+    st, out, n = E.members_run(bytes(bc), g.out.size + 16, chunk_bytes=4096)
+    assert st == -6 and n == 1 and out == b"".join(parts[:1])
+    st, out, n = E.members_run(comp, len(parts[0]) + 10, chunk_bytes=4096)
+    assert st == -5 and out == parts[0]
+    bad = comp + b"\x00garbage"
+    assert orc.gunzip(bad).status == orc.E_HEADER
+    st, out, n = E.members_run(bad, g.out.size + 16, chunk_bytes=4096)
+    assert st == -2 and out == g.out.tobytes() and n == len(parts)
+
+
 def test_emu_bgzf_batch(orc):
     """A BGZF-style file (64 KiB members and the empty end member) decoded
     as one batch of members equals the oracle's gunzip; a member without the

@@ -214,6 +214,40 @@ def test_stream_multiple_members(orc):
     s.close()
 
 
+def test_decompress_members(orc):
+    """gz_decompress_members on concatenated members (an empty one,
+    BGZF-style ones, levels 1/6/9): the oracle's gunzip of the whole input,
+    members counted; a wrong CRC in the second member gives the oracle's
+    status with the first member's bytes; a non-member tail gives the
+    oracle's header status after all members."""
+    import paper_1905_07224_amd as gz
+
+    parts = [synth.fastq_like(5 << 20, 821), synth.word_stream(3 << 20, 822), b"", synth.fastq_like(60 << 10, 823),
+             synth.word_stream(50 << 10, 824), synth.fastq_like(2 << 20, 825)]
+    comps = [synth.gzip_member(parts[0], 6), synth.gzip_member(parts[1], 1), synth.gzip_member(b"", 6),
+             synth.bgzf_member(parts[3], 6), synth.bgzf_member(parts[4], 9), synth.gzip_member(parts[5], 9)]
+    comp = b"".join(comps)
+    g = orc.gunzip(comp)
+    assert g.status == orc.OK and g.n_members == len(parts)
+    _say("members through gz_decompress_members")
+    out = torch.empty(g.out.size + 64, dtype=torch.uint8, device="cuda:0")
+    n, m = gz.decompress_members(comp, out)
+    assert n == g.out.size and m == len(parts)
+    assert np.array_equal(out[:n].cpu().numpy(), g.out)
+    bad = bytearray(comp)
+    bad[len(comps[0]) + len(comps[1]) - 8] ^= 1
+    assert orc.gunzip(bytes(bad)).reason == "CRC"
+    with pytest.raises(gz.GzError) as ei:
+        gz.decompress_members(bytes(bad), out)
+    assert ei.value.code == gz.GZ_E_CRC
+    assert out[:len(parts[0])].cpu().numpy().tobytes() == parts[0]
+    tail = comp + b"\x1f\x8b\x08"
+    assert orc.gunzip(tail).status == orc.E_HEADER
+    with pytest.raises(gz.GzError) as ei:
+        gz.decompress_members(tail, out)
+    assert ei.value.code == gz.GZ_E_HEADER
+
+
 def test_bgzf_batch(orc):
     """A BGZF-style file of 64 KiB members (about 64 MiB) decoded as one
     batch: byte for byte the oracle's gunzip of all members."""
