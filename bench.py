@@ -347,6 +347,15 @@ def batched_vs_plain(n_files: int, reps: int, copy_gbps=None, keep_host=None):
     ok_batch = all(bp.result(i).status == 0 for i in range(n_files)) and exact()
     ms_graph = timed(lambda: bp.launch_graph(s))
     ok_graph = all(bp.result(i).status == 0 for i in range(n_files)) and exact()
+    del bp
+    # the autotuner's choice for the files' class (timed on the first file,
+    # outside the timed region), applied to the whole batch
+    choice = gz.autotune(comps[0])
+    bt = gz.BatchPlan(comps, 0, outs=outs, tuned=1)
+    bt.workspace()
+    ms_tuned = timed(lambda: bt.launch(s))
+    ok_tuned = all(bt.result(i).status == 0 for i in range(n_files)) and exact()
+    del bt
     comp_total = sum(c.numel() for c in comps)
     ratio = total / comp_total
     if keep_host is not None:
@@ -365,7 +374,9 @@ def batched_vs_plain(n_files: int, reps: int, copy_gbps=None, keep_host=None):
         "plain_ms": round(ms_plain, 3),
         "batched_ms": round(ms_batch, 3),
         "graph_ms": round(ms_graph, 3),
-        "bit_exact": bool(ok_plain and ok_batch and ok_graph),
+        "tuned_choice": choice,
+        "tuned_GBps": round(total / ms_tuned / 1e6, 4),
+        "bit_exact": bool(ok_plain and ok_batch and ok_graph and ok_tuned),
     }
 
 

@@ -65,7 +65,10 @@ typedef struct gz_opts {
   uint32_t binary;        /* nonzero: binary input (Section VIII): chunk starts are searched with the checks
                              of Appendix A except the ASCII test of the literals; the output is exact
                              either way (the stitch check repairs any wrong start) */
-  uint32_t reserved[4];
+  uint32_t tuned;         /* nonzero: a file whose (compressed-size, ratio) class gz_autotune has timed on this
+                             device takes the chunk size chosen there (over chunk_bytes), and, unless
+                             window_syms is set, the plan takes the ring chosen for its largest such file */
+  uint32_t reserved[3];
 } gz_opts;
 
 /* One file of a batch. */

@@ -159,6 +159,27 @@ hipError_t control_stream(hipStream_t *st) {
   return hipSuccess;
 }
 
+// The autotuner's choices, per (device, compressed-size class, ratio class):
+// the size class is the bit length of the compressed size, the ratio class
+// four times the compression ratio (ISIZE over payload bytes), at most 64.
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int>, gz_opts> g_tune;
+
+std::tuple<int, int, int> tune_key(int dev, uint64_t comp_len, uint64_t payload, uint32_t isize) {
+  int size_class = 0;
+  while ((comp_len >> size_class) > 1) size_class++;
+  const int ratio_class = (int)std::min<double>(64.0, 4.0 * (double)isize / (double)std::max<uint64_t>(1, payload));
+  return std::make_tuple(dev, size_class, ratio_class);
+}
+
+bool tune_lookup(int dev, uint64_t comp_len, uint64_t payload, uint32_t isize, gz_opts *o) {
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  auto it = g_tune.find(tune_key(dev, comp_len, payload, isize));
+  if (it == g_tune.end()) return false;
+  *o = it->second;
+  return true;
+}
+
 }  // namespace
 
 struct gz_plan_s {
@@ -263,8 +284,12 @@ static uint64_t decode_slots(gz_plan_t p) {
   return (uint64_t)waves_per_cu * (uint64_t)std::max(1, p->n_cu);
 }
 
+static bool valid_ring(uint32_t win);
+
 static int plan_common(gz_plan_t p) {
   const uint32_t F = (uint32_t)p->jobs.size();
+  uint64_t tuned_len = 0;
+  uint32_t tuned_win = 0;
   p->files.clear();
   p->chunks.clear();
   p->span.clear();
@@ -334,7 +359,20 @@ static int plan_common(gz_plan_t p) {
     }
     if (p->opts.binary) fd.mode |= FD_BINARY;
     const uint64_t P = hi > lo ? hi - lo : 1;
-    uint64_t N = j.n_chunks > 0 ? (uint64_t)j.n_chunks : (P + p->opts.chunk_bytes - 1) / p->opts.chunk_bytes;
+    uint64_t cb = p->opts.chunk_bytes;
+    if (p->opts.tuned && !p->seg.on) {
+      // the autotuner's chunk size for this file's class, when it has one;
+      // the ring of the largest such file
+      gz_opts t;
+      if (tune_lookup(p->device, j.comp_len, P, isize, &t) && t.chunk_bytes) {
+        cb = t.chunk_bytes;
+        if (!p->opts.window_syms && j.comp_len >= tuned_len && valid_ring(t.window_syms)) {
+          tuned_len = j.comp_len;
+          tuned_win = t.window_syms;
+        }
+      }
+    }
+    uint64_t N = j.n_chunks > 0 ? (uint64_t)j.n_chunks : (P + cb - 1) / cb;
     N *= std::max<uint32_t>(1, p->opts.waves_per_chunk);
     N = std::max<uint64_t>(1, std::min<uint64_t>(N, P));
     fd.first_chunk = (uint32_t)p->chunks.size();
@@ -361,6 +399,7 @@ static int plan_common(gz_plan_t p) {
     sym_elems += align_up(fd.pool_elems, FLUSH_UNIT);
     p->files.push_back(fd);
   }
+  if (tuned_win) p->win = tuned_win;
   const uint32_t N = (uint32_t)p->chunks.size();
   // workgroups per chunk search: enough for some 4096 in all
   if (!p->opts.scan_groups) p->groups = std::max<uint32_t>(1, std::min<uint32_t>(64, 4096 / std::max<uint32_t>(1, N)));
@@ -1105,8 +1144,6 @@ const char *gz_strerror(int code) {
 // Autotuner: candidate (chunk size, LDS ring) pairs timed on the caller's
 // input; the choice is cached per (device, size class, ratio class).
 namespace {
-std::mutex g_tune_mu;
-std::map<std::tuple<int, int, int>, gz_opts> g_tune;
 const uint64_t k_tune_chunks[] = {32ull << 10, 40ull << 10, 64ull << 10, 128ull << 10, 256ull << 10, 1ull << 20};
 const uint32_t k_tune_rings[] = {512, 1024, 2048};
 }  // namespace
@@ -1126,6 +1163,7 @@ int gz_autotune(const void *d_comp, size_t comp_len, void *d_out, size_t out_cap
       o.chunk_bytes = cb;
       o.window_syms = ring;
       o.timing = 0;
+      o.tuned = 0;
       gz_plan_t pl = nullptr;
       int r = gz_plan(&pl, d_comp, comp_len, 0, &o);
       if (r != GZ_OK) return r;
@@ -1144,10 +1182,7 @@ int gz_autotune(const void *d_comp, size_t comp_len, void *d_out, size_t out_cap
   if (!d_ws) return GZ_OK;  // query only
   int dev = 0;
   (void)hipGetDevice(&dev);
-  int size_class = 0;
-  while ((comp_len >> size_class) > 1) size_class++;
-  const int ratio_class = (int)std::min<double>(64.0, 4.0 * (double)isize / (double)std::max<uint64_t>(1, payload));
-  const auto key = std::make_tuple(dev, size_class, ratio_class);
+  const auto key = tune_key(dev, comp_len, payload, isize);
   {
     std::lock_guard<std::mutex> g(g_tune_mu);
     auto it = g_tune.find(key);

@@ -3,6 +3,8 @@
 Every output is compared byte for byte with the source text and with the
 CPU oracle's two-pass result on the same seeded input.
 """
+import time
+
 import pytest
 
 import synth
@@ -128,6 +130,41 @@ def test_autotune_choice_is_exact_and_cached(orc, files):
     assert t2 - t1 < t1 - t0  # the second answer comes from the cache
     out = gz.decompress(d, 0, **best)
     assert out.cpu().numpy().tobytes() == raw
+
+
+def test_tuned_option_in_batch_and_server(orc, files):
+    """opts.tuned: once gz_autotune has timed a file's class, a batch plans
+    that class's files with the tuned chunk size (files of other classes keep
+    the default), the serving loop too, and the outputs stay the oracle's."""
+    gz = _gz()
+    _say("tuned batch")
+    comps = [_dev(c) for _, c in files]
+    best = gz.autotune(comps[1])
+    want = sum(gz.Plan(c, 0, **(best if k == 1 else {})).n_chunks for k, c in enumerate(comps))
+    outs = _outs(files)
+    bp = gz.BatchPlan(comps, 0, outs=outs, tuned=1)
+    assert bp.info.n_chunks == want
+    bp.launch()
+    for k, (raw, comp) in enumerate(files):
+        r = bp.result(k)
+        assert r.status == 0 and outs[k][:r.out_len].cpu().numpy().tobytes() == raw
+    if best["chunk_bytes"] != gz.DEFAULT_CHUNK_BYTES:
+        assert gz.BatchPlan(comps, 0, outs=outs).info.n_chunks != want
+    srv = gz.Server(budget_bytes=8 << 30, max_inflight=2, max_batch=4, tuned=1)
+    outs = _outs(files)
+    for k, c in enumerate(comps):
+        srv.submit(c, outs[k], k)
+    done = {}
+    for _ in range(20000):
+        for d in srv.poll():
+            done[d["tag"]] = d
+        if len(done) == len(files):
+            break
+        time.sleep(0.001)
+    srv.close()
+    assert sorted(done) == list(range(len(files)))
+    for k, (raw, _) in enumerate(files):
+        assert done[k]["status"] == 0 and outs[k][:len(raw)].cpu().numpy().tobytes() == raw
 
 
 def test_serving_mix_equals_alone(files):
