@@ -47,6 +47,8 @@ extern "C" {
 #define GZ_E_HIP (-9)         /* HIP runtime error */
 #define GZ_E_NOT_READY (-10)  /* gz_result before any gz_decompress on this plan */
 
+#define GZ_START_STORED 2u
+
 /* Options.  An all-zero struct means defaults.  (Section VI-C cuts the payload
  * into n roughly equal parts; Section VI-A and Appendix A give the
  * block-start checks whose constants appear here.) */
@@ -68,7 +70,12 @@ typedef struct gz_opts {
   uint32_t tuned;         /* nonzero: a file whose (compressed-size, ratio) class gz_autotune has timed on this
                              device takes the chunk size chosen there (over chunk_bytes), and, unless
                              window_syms is set, the plan takes the ring chosen for its largest such file */
-  uint32_t reserved[3];
+  uint32_t start_types;   /* block types searched as chunk starts besides dynamic ones (Appendix A rejects
+                             only BTYPE 11): GZ_START_STORED also takes stored blocks whose padding is zero,
+                             LEN/NLEN complements and LEN > 1 KiB.  0: dynamic only.  Fixed blocks are not
+                             offered (GZ_E_ARG): with no table to check, the fixed code resynchronises
+                             inside other blocks and most candidates would be false starts */
+  uint32_t reserved[2];
 } gz_opts;
 
 /* One file of a batch. */

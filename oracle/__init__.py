@@ -66,7 +66,7 @@ class _Pugz(C.Structure):
                 ("cand", C.POINTER(C.c_int64)), ("end", C.POINTER(C.c_int64)),
                 ("len", C.POINTER(C.c_int64)), ("off", C.POINTER(C.c_int64)),
                 ("placeholders", C.POINTER(C.c_int64)), ("valid", C.POINTER(C.c_int64)),
-                ("windows", C.POINTER(C.c_uint8)), ("n_repairs", C.c_int),
+                ("windows", C.POINTER(C.c_uint8)), ("n_repairs", C.c_int), ("n_equivalent", C.c_int),
                 ("out", C.POINTER(C.c_uint8)), ("out_len", C.c_size_t),
                 ("crc_trailer", C.c_uint32), ("isize_trailer", C.c_uint32), ("crc_computed", C.c_uint32)]
 
@@ -91,6 +91,14 @@ def lib():
         L.orc_pugz.argtypes = [u8p, C.c_size_t, C.c_int]
         L.orc_pugz_mode.restype = C.POINTER(_Pugz)
         L.orc_pugz_mode.argtypes = [u8p, C.c_size_t, C.c_int, C.c_int]
+        L.orc_pugz_types.restype = C.POINTER(_Pugz)
+        L.orc_pugz_types.argtypes = [u8p, C.c_size_t, C.c_int, C.c_int, C.c_int]
+        L.orc_block_static_types.restype = C.c_int
+        L.orc_block_static_types.argtypes = [u8p, C.c_size_t, C.c_int64, C.c_int, C.POINTER(C.c_int)]
+        L.orc_block_predicate_types.restype = C.c_int
+        L.orc_block_predicate_types.argtypes = [u8p, C.c_size_t, C.c_int64, C.c_int, C.c_int, C.POINTER(C.c_int)]
+        L.orc_find_start_types.restype = C.c_int64
+        L.orc_find_start_types.argtypes = [u8p, C.c_size_t, C.c_int64, C.c_int64, C.c_int, C.c_int, C.c_int]
         L.orc_pugz_free.argtypes = [C.POINTER(_Pugz)]
         L.orc_crc32.restype = C.c_uint32
         L.orc_crc32.argtypes = [C.c_uint32, u8p, C.c_size_t]
@@ -202,36 +210,43 @@ def symbolic(data, start_bit: int, stop_bit: int, first: bool) -> SymResult:
     return o
 
 
-def block_static(data, bit: int):
+START_DYNAMIC, START_STORED, START_FIXED = 1, 2, 4  # block types accepted as chunk starts
+
+
+def block_static(data, bit: int, types: int = START_DYNAMIC):
     a, p, n = _buf(data)
     r = C.c_int(0)
-    ok = lib().orc_block_static(p, n, bit, C.byref(r))
+    ok = lib().orc_block_static_types(p, n, bit, types, C.byref(r))
     return bool(ok), REASONS.get(r.value, r.value)
 
 
-def block_predicate(data, bit: int, binary: bool = False):
-    """Appendix A's checks at one bit (binary: without the ASCII test)."""
+def block_predicate(data, bit: int, binary: bool = False, types: int = START_DYNAMIC):
+    """Appendix A's checks at one bit (binary: without the ASCII test; types:
+    the block types accepted as starts)."""
     a, p, n = _buf(data)
     r = C.c_int(0)
-    ok = lib().orc_block_predicate_mode(p, n, bit, 0 if binary else 1, C.byref(r))
+    ok = lib().orc_block_predicate_types(p, n, bit, 0 if binary else 1, types, C.byref(r))
     return bool(ok), REASONS.get(r.value, r.value)
 
 
-def find_start(data, lo_bit: int, hi_bit: int, static_only: bool = False, binary: bool = False) -> int:
+def find_start(data, lo_bit: int, hi_bit: int, static_only: bool = False, binary: bool = False,
+               types: int = START_DYNAMIC) -> int:
     a, p, n = _buf(data)
-    return int(lib().orc_find_start_mode(p, n, lo_bit, hi_bit, 1 if static_only else 0, 0 if binary else 1))
+    return int(lib().orc_find_start_types(p, n, lo_bit, hi_bit, 1 if static_only else 0, 0 if binary else 1,
+                                          types))
 
 
 class PugzResult:
     pass
 
 
-def pugz(data, n_chunks: int, binary: bool = False) -> PugzResult:
+def pugz(data, n_chunks: int, binary: bool = False, types: int = START_DYNAMIC) -> PugzResult:
     """The two-pass method on the CPU: per-chunk starts, ends, lengths, windows,
-    output (binary: block starts searched without the ASCII test)."""
+    output (binary: block starts searched without the ASCII test; types: the
+    block types accepted as chunk starts)."""
     a, p, n = _buf(data)
     L = lib()
-    rp = L.orc_pugz_mode(p, n, n_chunks, 0 if binary else 1)
+    rp = L.orc_pugz_types(p, n, n_chunks, 0 if binary else 1, types)
     r = rp.contents
     o = PugzResult()
     o.status = r.status
@@ -243,6 +258,7 @@ def pugz(data, n_chunks: int, binary: bool = False) -> PugzResult:
         setattr(o, k, _arr(getattr(r, k), N, np.int64))
     o.windows = _arr(r.windows, N * 32768, np.uint8).reshape(N, 32768) if N else None
     o.n_repairs = r.n_repairs
+    o.n_equivalent = r.n_equivalent
     o.out = _arr(r.out, r.out_len, np.uint8)
     o.crc_trailer = r.crc_trailer
     o.isize_trailer = r.isize_trailer

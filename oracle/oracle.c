@@ -587,13 +587,31 @@ void orc_sym_free(orc_sym_result *r) {
 #define MAX_BLOCK (4 << 20)
 
 int orc_block_static(const uint8_t *in, size_t n, int64_t bit, int *reason) {
+  return orc_block_static_types(in, n, bit, ORC_START_DYNAMIC, reason);
+}
+
+/* Start types (a reading of Appendix A, which rejects only BTYPE 11): a
+ * stored block is a candidate when its padding bits are zero, LEN and NLEN
+ * are complements and LEN > 1 KiB (the trial block's size bound); a fixed
+ * block has no table to check, so the trial block is its only test. */
+int orc_block_static_types(const uint8_t *in, size_t n, int64_t bit, int types, int *reason) {
   bitrd r = {in, n, bit, 0};
   int bfinal = (int)get_bit(&r);
   int btype = (int)get_bits(&r, 2);
   int e = R_OK;
   if (r.trunc) e = R_TRUNC;
   else if (bfinal) e = R_FINAL;
-  else if (btype != 2) e = R_NOT_DYNAMIC;
+  else if (btype == 0 && (types & ORC_START_STORED)) {
+    int64_t p = (bit + 3 + 7) & ~(int64_t)7;
+    while (r.pos < p && !r.trunc && !e)
+      if (get_bit(&r)) e = R_NOT_DYNAMIC;
+    uint32_t len = get_bits(&r, 16), nlen = get_bits(&r, 16);
+    if (!e && r.trunc) e = R_TRUNC;
+    else if (!e && (len ^ 0xFFFFu) != nlen) e = R_NLEN;
+    else if (!e && len <= MIN_BLOCK) e = R_SIZE;
+  } else if (btype == 1 && (types & ORC_START_FIXED)) {
+    e = R_OK;
+  } else if (btype != 2) e = R_NOT_DYNAMIC;
   else {
     huff lit, dist;
     int no_dist;
@@ -604,14 +622,18 @@ int orc_block_static(const uint8_t *in, size_t n, int64_t bit, int *reason) {
 }
 
 int orc_block_predicate(const uint8_t *in, size_t n, int64_t bit, int *reason) {
-  return orc_block_predicate_mode(in, n, bit, 1, reason);
+  return orc_block_predicate_types(in, n, bit, 1, ORC_START_DYNAMIC, reason);
+}
+
+int orc_block_predicate_mode(const uint8_t *in, size_t n, int64_t bit, int ascii, int *reason) {
+  return orc_block_predicate_types(in, n, bit, ascii, ORC_START_DYNAMIC, reason);
 }
 
 /* Binary inputs (Section VIII lists them as a limitation): the same checks
  * without the ASCII test of the literals. */
-int orc_block_predicate_mode(const uint8_t *in, size_t n, int64_t bit, int ascii, int *reason) {
+int orc_block_predicate_types(const uint8_t *in, size_t n, int64_t bit, int ascii, int types, int *reason) {
   int e;
-  if (!orc_block_static(in, n, bit, &e)) {
+  if (!orc_block_static_types(in, n, bit, types, &e)) {
     if (reason) *reason = e;
     return 0;
   }
@@ -640,8 +662,14 @@ int64_t orc_find_start(const uint8_t *in, size_t n, int64_t lo, int64_t hi, int 
 }
 
 int64_t orc_find_start_mode(const uint8_t *in, size_t n, int64_t lo, int64_t hi, int static_only, int ascii) {
+  return orc_find_start_types(in, n, lo, hi, static_only, ascii, ORC_START_DYNAMIC);
+}
+
+int64_t orc_find_start_types(const uint8_t *in, size_t n, int64_t lo, int64_t hi, int static_only, int ascii,
+                             int types) {
   for (int64_t b = lo; b < hi; b++) {
-    int ok = static_only ? orc_block_static(in, n, b, NULL) : orc_block_predicate_mode(in, n, b, ascii, NULL);
+    int ok = static_only ? orc_block_static_types(in, n, b, types, NULL)
+                         : orc_block_predicate_types(in, n, b, ascii, types, NULL);
     if (ok) return b;
   }
   return -1;
@@ -666,9 +694,25 @@ void orc_pugz_free(orc_pugz_result *r) {
   free(r);
 }
 
-orc_pugz_result *orc_pugz(const uint8_t *in, size_t n, int N) { return orc_pugz_mode(in, n, N, 1); }
+orc_pugz_result *orc_pugz(const uint8_t *in, size_t n, int N) { return orc_pugz_types(in, n, N, 1, ORC_START_DYNAMIC); }
 
 orc_pugz_result *orc_pugz_mode(const uint8_t *in, size_t n, int N, int ascii) {
+  return orc_pugz_types(in, n, N, ascii, ORC_START_DYNAMIC);
+}
+
+/* A chunk that starts on a stored header, at s, and a previous chunk that
+ * ended at e with s < e in the same run of zero bits before the same
+ * LEN/NLEN: both bits begin the same stored block, so decoding from either
+ * gives the same symbols and the same end. */
+static int stored_equivalent(const uint8_t *in, size_t n, int64_t s, int64_t e, int types) {
+  if (!(types & ORC_START_STORED) || !(s < e)) return 0;
+  if (((s + 3 + 7) >> 3) != ((e + 3 + 7) >> 3)) return 0;
+  bitrd r = {in, n, s, 0};
+  if (get_bits(&r, 3) != 0 || r.trunc) return 0;
+  return orc_block_static_types(in, n, s, ORC_START_STORED, NULL);
+}
+
+orc_pugz_result *orc_pugz_types(const uint8_t *in, size_t n, int N, int ascii, int types) {
   orc_pugz_result *res = (orc_pugz_result *)calloc(1, sizeof(*res));
   if (!res || N < 1) return res;
   res->n_chunks = N;
@@ -706,7 +750,7 @@ orc_pugz_result *orc_pugz_mode(const uint8_t *in, size_t n, int N, int ascii) {
   /* block starts: chunk 0 at the payload's first bit, others searched */
   res->start[0] = res->cand[0] = (int64_t)h * 8;
   for (int i = 1; i < N; i++) {
-    res->cand[i] = orc_find_start_mode(in, n, res->nominal[i] * 8, res->nominal[i + 1] * 8, 0, ascii);
+    res->cand[i] = orc_find_start_types(in, n, res->nominal[i] * 8, res->nominal[i + 1] * 8, 0, ascii, types);
     res->start[i] = res->cand[i];
   }
 
@@ -719,7 +763,8 @@ orc_pugz_result *orc_pugz_mode(const uint8_t *in, size_t n, int N, int ascii) {
     if (res->start[i] < 0) continue;
     if (final_seen) { res->start[i] = -1; continue; }
     if (prev >= 0 && res->end[prev] != res->start[i]) {
-      res->n_repairs++;
+      if (stored_equivalent(in, n, res->start[i], res->end[prev], types)) res->n_equivalent++;
+      else res->n_repairs++;
       res->start[i] = res->end[prev];
     }
     int64_t stop = INT64_MAX;

@@ -136,12 +136,20 @@ void orc_sym_free(orc_sym_result *r);
  * the confirmation with success).  Returns 1 or 0; *stage gets the failing
  * reason (R_*) or R_OK. */
 int orc_block_static(const uint8_t *in, size_t n, int64_t bit, int *reason);
+/* Block types accepted as chunk starts (a mask; dynamic is always on). */
+#define ORC_START_DYNAMIC 1
+#define ORC_START_STORED 2
+#define ORC_START_FIXED 4
+int orc_block_static_types(const uint8_t *in, size_t n, int64_t bit, int types, int *reason);
 int orc_block_predicate(const uint8_t *in, size_t n, int64_t bit, int *reason);
 /* ascii 0: binary inputs, the same checks without the ASCII test. */
 int orc_block_predicate_mode(const uint8_t *in, size_t n, int64_t bit, int ascii, int *reason);
+int orc_block_predicate_types(const uint8_t *in, size_t n, int64_t bit, int ascii, int types, int *reason);
 /* Smallest b in [lo, hi) passing the predicate (static only if static_only), or -1. */
 int64_t orc_find_start(const uint8_t *in, size_t n, int64_t lo, int64_t hi, int static_only);
 int64_t orc_find_start_mode(const uint8_t *in, size_t n, int64_t lo, int64_t hi, int static_only, int ascii);
+int64_t orc_find_start_types(const uint8_t *in, size_t n, int64_t lo, int64_t hi, int static_only, int ascii,
+                             int types);
 
 /* The whole two-pass method of Section VI-C on the CPU, single member.
  * Chunk i covers compressed bytes [nom_i, nom_{i+1}) of the payload with
@@ -165,6 +173,7 @@ typedef struct {
   int64_t *valid;         /* real history bytes before chunk i, capped at 32768 */
   uint8_t *windows;       /* n_chunks * 32768: resolved window before chunk i */
   int n_repairs;
+  int n_equivalent;       /* stored starts taken as the previous chunk's end (same block) */
   uint8_t *out;
   size_t out_len;
   uint32_t crc_trailer, isize_trailer, crc_computed;
@@ -173,6 +182,10 @@ typedef struct {
 orc_pugz_result *orc_pugz(const uint8_t *in, size_t n, int n_chunks);
 /* ascii 0: the block-start search of binary inputs (no ASCII test). */
 orc_pugz_result *orc_pugz_mode(const uint8_t *in, size_t n, int n_chunks, int ascii);
+/* types: also stored and/or fixed blocks as chunk starts.  A stored start
+ * that the previous chunk's end reaches in the same zero run before the same
+ * LEN/NLEN is taken as that end without a repair (n_equivalent). */
+orc_pugz_result *orc_pugz_types(const uint8_t *in, size_t n, int n_chunks, int ascii, int types);
 void orc_pugz_free(orc_pugz_result *r);
 
 #ifdef __cplusplus

@@ -38,7 +38,7 @@ class Opts(C.Structure):
     _fields_ = [("chunk_bytes", C.c_uint64), ("sym_factor", C.c_uint32), ("window_syms", C.c_uint32),
                 ("scan_groups", C.c_uint32), ("inflate_waves_per_cu", C.c_uint32), ("waves_per_chunk", C.c_uint32),
                 ("timing", C.c_uint32), ("confirm_decode", C.c_uint32), ("binary", C.c_uint32),
-                ("tuned", C.c_uint32), ("reserved", C.c_uint32 * 3)]
+                ("tuned", C.c_uint32), ("start_types", C.c_uint32), ("reserved", C.c_uint32 * 2)]
 
 
 class Job(C.Structure):
@@ -125,6 +125,7 @@ GZ_N_PASSES = N_PASSES = 13
 GZ_SCRATCH_BYTES = 256 << 20  # static workspace of gz_decompress_static, per GPU
 # defaults of gz_opts (include/gzgpu.h)
 DEFAULT_CHUNK_BYTES = 40 << 10
+GZ_START_STORED = 2  # opts.start_types: stored blocks as chunk starts
 DEFAULT_WINDOW = 512
 
 

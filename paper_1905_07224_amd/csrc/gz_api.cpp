@@ -22,8 +22,8 @@ hipError_t gzk_init(ChunkState *, uint32_t, FileState *, uint32_t, Counters *, h
 hipError_t gzk_scan(const FileDesc *, const ChunkDesc *, ChunkState *, const uint32_t *, uint32_t, uint32_t,
                     hipStream_t);
 hipError_t gzk_capacity(uint32_t, const FileDesc *, ChunkDesc *, const ChunkState *, uint32_t, hipStream_t);
-hipError_t gzk_inflate(int, uint32_t, const FileDesc *, const ChunkDesc *, ChunkState *, const uint32_t *, uint32_t,
-                       Counters *, uint16_t *, hipStream_t);
+hipError_t gzk_inflate(int, uint32_t, uint32_t, const FileDesc *, const ChunkDesc *, ChunkState *, const uint32_t *,
+                       uint32_t, Counters *, uint16_t *, hipStream_t);
 hipError_t gzk_confirm(int, uint32_t, const FileDesc *, const ChunkDesc *, ChunkState *, uint32_t, Counters *,
                        uint16_t *, uint32_t, hipStream_t);
 hipError_t gzk_redo(int, uint32_t, const FileDesc *, const ChunkDesc *, ChunkState *, uint32_t, Counters *, uint16_t *,
@@ -328,7 +328,8 @@ static int plan_common(gz_plan_t p) {
     if (p->probe) {
       // one chunk searching [probe_lo, probe_hi) bits; it decodes one block
       // and its confirmation
-      fd.mode = FD_PROBE | (p->opts.binary ? FD_BINARY : 0u);
+      fd.mode = FD_PROBE | (p->opts.binary ? FD_BINARY : 0u) |
+                ((p->opts.start_types & GZ_START_STORED) ? FD_STORED_STARTS : 0u);
       fd.stop_bit = p->probe_hi[f];
       fd.first_chunk = (uint32_t)p->chunks.size();
       fd.n_chunks = 1;
@@ -358,6 +359,7 @@ static int plan_common(gz_plan_t p) {
       fd.mode = p->seg.mode;
     }
     if (p->opts.binary) fd.mode |= FD_BINARY;
+    if (p->opts.start_types & GZ_START_STORED) fd.mode |= FD_STORED_STARTS;
     const uint64_t P = hi > lo ? hi - lo : 1;
     uint64_t cb = p->opts.chunk_bytes;
     if (p->opts.tuned && !p->seg.on) {
@@ -472,6 +474,9 @@ static int plan_common(gz_plan_t p) {
 // Ring sizes the decoder is built for: powers of two from 512 to 32768.
 static bool valid_ring(uint32_t win) { return win >= 512 && win <= 32768 && (win & (win - 1)) == 0; }
 
+// Options a plan can run with: a ring the decoder is built for, start types it offers.
+static bool valid_opts(const gz_plan_s *p) { return valid_ring(p->win) && (p->opts.start_types & ~GZ_START_STORED) == 0; }
+
 static void fill_defaults(gz_plan_t p, const gz_opts *opts, bool query_device = true) {
   if (opts) p->opts = *opts;
   if (p->opts.chunk_bytes == 0) p->opts.chunk_bytes = DEFAULT_CHUNK_BYTES;
@@ -492,7 +497,7 @@ static int make_plan(gz_plan_t *plan, const gz_job *jobs, int n, const gz_opts *
   gz_plan_t p = new (std::nothrow) gz_plan_s();
   if (!p) return GZ_E_ARG;
   fill_defaults(p, opts);
-  if (!valid_ring(p->win)) {
+  if (!valid_opts(p)) {
     gz_plan_destroy(p);
     return GZ_E_ARG;
   }
@@ -520,7 +525,7 @@ int gzi_plan_ws(const gz_job *jobs, int n, const gz_opts *opts, uint64_t *ws_byt
   gz_plan_s p;
   p.dry = true;
   fill_defaults(&p, opts);
-  if (!valid_ring(p.win)) return GZ_E_ARG;
+  if (!valid_opts(&p)) return GZ_E_ARG;
   p.jobs.assign(jobs, jobs + n);
   const int r = plan_common(&p);
   if (r == GZ_OK) *ws_bytes = p.lay.total;
@@ -545,7 +550,7 @@ int gzi_replan(gz_plan_t *plan, const gz_job *jobs, int n, const gz_opts *opts) 
   const bool timing_events = p->opts.timing != 0;
   fill_defaults(p, opts, false);
   p->opts.timing = timing_events ? p->opts.timing : 0;
-  if (!valid_ring(p->win)) return GZ_E_ARG;
+  if (!valid_opts(p)) return GZ_E_ARG;
   p->jobs.assign(jobs, jobs + n);
   return plan_common(p);
 }
@@ -583,7 +588,7 @@ int gz_plan_probes(gz_plan_t *plan, const void *d_comp, size_t comp_len, const u
   gz_plan_t p = new (std::nothrow) gz_plan_s();
   if (!p) return GZ_E_ARG;
   fill_defaults(p, opts);
-  if (!valid_ring(p->win)) {
+  if (!valid_opts(p)) {
     gz_plan_destroy(p);
     return GZ_E_ARG;
   }
@@ -671,7 +676,7 @@ int gz_plan_bgzf(gz_plan_t *plan, const void *d_comp, const void *h_comp, size_t
   gz_plan_t p = new (std::nothrow) gz_plan_s();
   if (!p) return GZ_E_ARG;
   fill_defaults(p, opts);
-  if (!valid_ring(p->win)) {
+  if (!valid_opts(p)) {
     gz_plan_destroy(p);
     return GZ_E_ARG;
   }
@@ -809,7 +814,8 @@ static int launch(gz_plan_t p, uint8_t *ws, size_t ws_bytes, hipStream_t st) {
   if ((e = gzk_capacity(F, files, (ChunkDesc *)(ws + L.chunks_off), cs, p->opts.sym_factor, st)) != hipSuccess)
     return hip_fail(e, "capacity");
   mark();
-  if ((e = gzk_inflate((int)p->win, grid, files, chunks, cs, order, N, ctr, pool, st)) != hipSuccess)
+  if ((e = gzk_inflate((int)p->win, (p->opts.start_types & GZ_START_STORED) ? 1u : 0u, grid, files, chunks, cs, order,
+                       N, ctr, pool, st)) != hipSuccess)
     return hip_fail(e, "inflate");
   mark();
   if ((e = gzk_confirm((int)p->win, grid, files, chunks, cs, N, ctr, pool, p->opts.confirm_decode, st)) != hipSuccess)

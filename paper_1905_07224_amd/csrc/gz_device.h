@@ -517,11 +517,30 @@ __device__ __forceinline__ void fixed_tables(TablesLDS &sh) {
 // ---------------------------------------------------------------------------
 // Block-start checks of Appendix A, cheap stage: one lane per candidate bit.
 // BFINAL = 0, BTYPE = 10, HLIT <= 286, HDIST <= 30, complete code-length code.
+// With FD_STORED_STARTS also a stored block: BFINAL = 0, BTYPE = 00, zero
+// padding to the byte boundary, LEN and NLEN complements, LEN > 1024 (the
+// trial block's size bound); that is its whole static check.
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ bool start_stage1(const Src &s, uint64_t b) {
-  if (b + 17 > s.end_bits) return false;
+// v: the 64 stream bits from b (b's bit first)
+__device__ __forceinline__ bool stored_start_bits(uint64_t v, uint64_t b, uint64_t end_bits) {
+  const uint32_t pad = (uint32_t)(((b + 10u) & ~7ull) - b);  // header and padding bits, 3..10
+  if (b + pad + 32u > end_bits) return false;
+  if (v & ((1ull << pad) - 1ull)) return false;
+  const uint32_t x = (uint32_t)(v >> pad);
+  const uint32_t len = x & 0xFFFFu;
+  return (len ^ 0xFFFFu) == (x >> 16) && len > 1024u;
+}
+
+__device__ __forceinline__ bool stored_start_at(const Src &s, uint64_t b) {
+  return stored_start_bits(s.peek64(b), b, s.end_bits);
+}
+
+template <bool STORED>
+__device__ __forceinline__ bool start_stage1(const Src &s, uint64_t b, uint32_t mode) {
+  if (b + 17 > s.end_bits) return STORED && (mode & FD_STORED_STARTS) && b < s.end_bits && stored_start_at(s, b);
   uint64_t v = s.peek64(b);
+  if (STORED && (mode & FD_STORED_STARTS) && (v & 7u) == 0u) return stored_start_at(s, b);
   if ((v & 7u) != 4u) return false;
   if (((v >> 3) & 31u) > 29u || ((v >> 8) & 31u) > 29u) return false;
   uint32_t hclen = (uint32_t)((v >> 13) & 15u) + 4u;
@@ -554,10 +573,24 @@ __device__ __forceinline__ void kraft3_fill(uint8_t *k3, int tid, int nthreads) 
 // word operations; the rest only where it holds (one position in eight).
 // The code-length code's Kraft sum takes seven lookups in k3 (kraft3_fill).
 __device__ __forceinline__ uint32_t start_stage1_word(const Src &s, int64_t W, uint32_t x0, uint32_t x1, uint32_t x2,
-                                                      uint32_t x3, const uint8_t *k3) {
+                                                      uint32_t x3, const uint8_t *k3, uint32_t mode) {
   const uint64_t lo = ((uint64_t)x1 << 32) | x0;
   uint32_t pat = (uint32_t)(~lo & ~(lo >> 1) & (lo >> 2));  // BFINAL = 0, BTYPE = 10
   uint32_t pass = 0;
+  if (mode & FD_STORED_STARTS) {
+    // BFINAL = 0, BTYPE = 00: the padding and LEN/NLEN lie within the four
+    // dwords (a byte boundary of the view is one of the file)
+    const uint64_t hi = ((uint64_t)x3 << 32) | x2;
+    uint32_t sp = (uint32_t)(~lo & ~(lo >> 1) & ~(lo >> 2));
+    for (int g = 0; g < 32 && sp; g++) {
+      const uint32_t k = (uint32_t)__builtin_ctz(sp);
+      sp &= sp - 1;
+      const int64_t b = 32 * W + (int64_t)k - 8 * (int64_t)s.mis;
+      if (b < 0) continue;
+      const uint64_t v = (lo >> k) | (k ? hi << (64 - k) : 0ull);
+      if (stored_start_bits(v, (uint64_t)b, s.end_bits)) pass |= 1u << k;
+    }
+  }
   for (int g = 0; g < 32 && pat; g++) {
     const uint32_t k = (uint32_t)__builtin_ctz(pat);
     pat &= pat - 1;
@@ -707,7 +740,9 @@ struct LaneBits {
   }
 };
 
-__device__ __forceinline__ bool lane_tables_ok(const Src &s, uint64_t b, uint8_t *tab, int lane) {
+__device__ __forceinline__ bool lane_tables_ok(const Src &s, uint64_t b, uint8_t *tab, int lane, uint32_t mode) {
+  // a stored candidate passed its whole static check in stage 1
+  if ((mode & FD_STORED_STARTS) && ((s.peek64(b) >> 1) & 3u) == 0u) return true;
   LaneBits br;
   br.init(s, b + 3);
   const uint32_t hlit = (uint32_t)(br.acc & 31u) + 257u;
@@ -800,7 +835,9 @@ __device__ __forceinline__ bool lane_tables_ok(const Src &s, uint64_t b, uint8_t
 }
 
 // Full static check, whole wave: the dynamic tables at b + 3 are valid.
-__device__ __forceinline__ bool start_stage2(const Src &s, uint64_t b, TablesLDS &sh) {
+template <bool STORED>
+__device__ __forceinline__ bool start_stage2(const Src &s, uint64_t b, TablesLDS &sh, uint32_t mode) {
+  if (STORED && (mode & FD_STORED_STARTS) && ((s.peek64(b) >> 1) & 3u) == 0u) return true;  // stored: checked in stage 1
   WaveBits br;
   br.s = s;
   br.init(b + 3);
@@ -810,18 +847,19 @@ __device__ __forceinline__ bool start_stage2(const Src &s, uint64_t b, TablesLDS
 // First candidate in [from, to) that passes the static checks, whole wave.
 // *n1 and *n2 (uniform) count the candidates given the table check and the
 // ones that passed it.
+template <bool STORED>
 __device__ __forceinline__ uint64_t wave_find_start(const Src &s, uint64_t from, uint64_t to, TablesLDS &sh,
-                                                    uint32_t *n1, uint32_t *n2) {
+                                                    uint32_t *n1, uint32_t *n2, uint32_t mode) {
   const int lane = lane_id();
   for (uint64_t b0 = from; b0 < to; b0 += 64) {
     uint64_t b = b0 + (uint64_t)lane;
-    bool p = b < to && start_stage1(s, b);
+    bool p = b < to && start_stage1<STORED>(s, b, mode);
     uint64_t m = __ballot(p);
     while (m) {
       int l = __ffsll((unsigned long long)m) - 1;
       m &= m - 1;
       (*n1)++;
-      if (start_stage2(s, b0 + (uint64_t)l, sh)) {
+      if (start_stage2<STORED>(s, b0 + (uint64_t)l, sh, mode)) {
         (*n2)++;
         return b0 + (uint64_t)l;
       }

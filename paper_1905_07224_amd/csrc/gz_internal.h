@@ -88,6 +88,7 @@ enum : uint32_t {
   FD_NOCHECK = 2u,  // decoding began inside the member: the trailer's CRC-32 and ISIZE do not apply
   FD_MEMBERS = 4u,  // more members may follow: the trailer is the 8 bytes after the final block
   FD_BINARY = 8u,   // binary input: block-start checks without the ASCII test of the literals
+  FD_STORED_STARTS = 16u,  // stored blocks are chunk-start candidates too
 };
 
 struct ChunkDesc {

@@ -60,7 +60,9 @@ struct DecodeResult {
   uint32_t cut_blocks, cut_nph;
 };
 
-template <int WIN>
+// STORED: the trial block may be a stored block (chunks searched with
+// FD_STORED_STARTS); false compiles the trial for dynamic blocks only.
+template <int WIN, bool STORED = false>
 struct Inflater {
   // The ring holds the last WIN symbols (WIN a power of two, 512..32768).
   // Symbols move to HBM in units of UNIT <= WIN / 2; fewer than UNIT are
@@ -90,6 +92,7 @@ struct Inflater {
   uint32_t nph_stop; // per lane placeholder count at the stop (symbols of D_i only)
   bool first;        // empty context
   bool ascii;        // checked blocks reject literals outside the ASCII set (text input)
+  bool stored_ok;    // a stored block may be the trial block (FD_STORED_STARTS)
   bool over;         // capacity exceeded somewhere
   bool emit;         // false: blocks past the stop are only parsed and counted
 
@@ -482,7 +485,7 @@ struct Inflater {
     br.skip(3);
     if (br.past_end()) return D_TRUNC;
     *final_out = bfinal != 0;
-    if (strict && (bfinal || btype != 2u)) return D_STATIC;
+    if (strict && (bfinal || !(btype == 2u || (STORED && btype == 0u && stored_ok)))) return D_STATIC;
     const uint64_t blk0 = pos;
     int r;
     if (btype == 0u) {
@@ -618,8 +621,8 @@ struct Inflater {
   }
 };
 
-template <int WIN>
-__device__ __forceinline__ void inflater_setup(Inflater<WIN> &inf, const FileDesc &fd, const ChunkDesc &cd,
+template <int WIN, bool STORED>
+__device__ __forceinline__ void inflater_setup(Inflater<WIN, STORED> &inf, const FileDesc &fd, const ChunkDesc &cd,
                                                uint16_t *pool) {
   inf.br.s.init(fd.comp, fd.comp_len);
   inf.D = pool + cd.sym_off;
@@ -631,6 +634,7 @@ __device__ __forceinline__ void inflater_setup(Inflater<WIN> &inf, const FileDes
   inf.nph_stop = 0;
   inf.first = (cd.flags & (CF_FIRST | CF_CARRIED)) == CF_FIRST;
   inf.ascii = (fd.mode & FD_BINARY) == 0u;
+  inf.stored_ok = (fd.mode & FD_STORED_STARTS) != 0u;
   inf.over = false;
   inf.emit = true;
   inf.pj = 0;
@@ -661,7 +665,9 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
 // defer: confirmation blocks past the stop are left to k_confirm.  from:
 // NONE to start at the scan candidate, else the first bit to search a
 // candidate from (a candidate rejected by k_confirm is redone from the next).
-template <int WIN>
+// STORED: stored blocks may be starts (FD_STORED_STARTS); false compiles the
+// search and the trial block for dynamic starts only.
+template <int WIN, bool STORED>
 __device__ __forceinline__ void inflate_chunk(InflateLDS<WIN> &sh, const FileDesc *files, const ChunkDesc *chunks, ChunkState *cs,
                               uint16_t *pool, uint32_t c, bool defer, uint64_t from) {
   const int lane = lane_id();
@@ -670,7 +676,7 @@ __device__ __forceinline__ void inflate_chunk(InflateLDS<WIN> &sh, const FileDes
   const bool first = (cd.flags & CF_FIRST) != 0;
   uint64_t b = first ? fd.payload_bit : uni64(cs[c].cand);
   const uint64_t stop = first || b != NONE ? uni64(next_start(fd, cs, c, false, nullptr)) : NONE;
-  Inflater<WIN> inf(sh);
+  Inflater<WIN, STORED> inf(sh);
   // search the next candidate from `search` at the top of an attempt (one
   // call site of the search, for code size)
   uint64_t search = !first && from != NONE ? from : NONE;
@@ -682,7 +688,7 @@ __device__ __forceinline__ void inflate_chunk(InflateLDS<WIN> &sh, const FileDes
     if (search != NONE) {
       Src src;
       src.init(fd.comp, fd.comp_len);
-      b = wave_find_start(src, search, cd.hi_bit, sh.t, &n1, &n2);
+      b = wave_find_start<STORED>(src, search, cd.hi_bit, sh.t, &n1, &n2, fd.mode);
       search = NONE;
     }
     if (tries > max_tries) b = NONE;
@@ -834,6 +840,7 @@ __global__ __launch_bounds__(256) void k_scan(const FileDesc *files, const Chunk
   const ChunkDesc cd = chunks[c];
   Src s;
   s.init(files[cd.file].comp, files[cd.file].comp_len);
+  const uint32_t mode = uni(files[cd.file].mode);
   const uint32_t wave = uni32(threadIdx.x >> 6);
   const int lane = lane_id();
   unsigned long long *cand = (unsigned long long *)&cs[c].cand;
@@ -846,7 +853,7 @@ __global__ __launch_bounds__(256) void k_scan(const FileDesc *files, const Chunk
     const uint64_t cur = uni64(__hip_atomic_load(cand, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
     const uint64_t b = (uint32_t)lane < k ? (uint64_t)q[lane] : NONE;
     const bool tried = b < cur;
-    const bool ok = tried && lane_tables_ok(s, b, cltab[wave], lane);
+    const bool ok = tried && lane_tables_ok(s, b, cltab[wave], lane, mode);
     const uint64_t m = __ballot(ok);
     const uint32_t n_tried = (uint32_t)__builtin_popcountll(__ballot(tried));
     if (lane == 0 && n_tried) {
@@ -878,7 +885,7 @@ __global__ __launch_bounds__(256) void k_scan(const FileDesc *files, const Chunk
     const int64_t W = Wt + lane;
     uint32_t surv = 0;
     if (W < W1) {
-      surv = start_stage1_word(s, W, s.dw(W), s.dw(W + 1), s.dw(W + 2), s.dw(W + 3), k3);
+      surv = start_stage1_word(s, W, s.dw(W), s.dw(W + 1), s.dw(W + 2), s.dw(W + 3), k3, mode);
       // only candidates in [lo_bit, hi_bit): bits [klo, khi) of this dword
       const int64_t b0 = 32 * W - mb;
       const int64_t klo = std::min<int64_t>(32, std::max<int64_t>(0, (int64_t)cd.lo_bit - b0));
@@ -993,7 +1000,7 @@ __global__ __launch_bounds__(256) void k_capacity(const FileDesc *files, ChunkDe
 // The 512-symbol ring: at most 96 VGPRs (5 waves per SIMD), so that 18
 // decoders fit in a CU's LDS and registers; what does not fit in 96 is
 // loop-invariant and reloaded once per chunk.
-template <int WIN>
+template <int WIN, bool STORED>
 __global__ __launch_bounds__(64, WIN == 512 ? 5 : 1) void k_inflate(const FileDesc *files, const ChunkDesc *chunks, ChunkState *cs,
                                                 const uint32_t *order, uint32_t n, Counters *ctr, uint16_t *pool) {
   __shared__ InflateLDS<WIN> sh;
@@ -1002,7 +1009,7 @@ __global__ __launch_bounds__(64, WIN == 512 ? 5 : 1) void k_inflate(const FileDe
     if (lane_id() == 0) item = atomicAdd(&ctr->inflate_next, 1u);
     item = uni(item);
     if (item >= n) break;
-    inflate_chunk<WIN>(sh, files, chunks, cs, pool, order[item], true, NONE);
+    inflate_chunk<WIN, STORED>(sh, files, chunks, cs, pool, order[item], true, NONE);
   }
 }
 
@@ -1093,7 +1100,7 @@ __global__ __launch_bounds__(64) void k_redo(const FileDesc *files, const ChunkD
   sparse_chunks(&ctr->redo_next, n, rejected, [&](uint32_t c) {
     const uint64_t s0 = uni64(cs[c].start);
     const uint32_t r0 = uni(cs[c].retries);
-    inflate_chunk<WIN>(sh, files, chunks, cs, pool, c, false, s0 + 1);
+    inflate_chunk<WIN, true>(sh, files, chunks, cs, pool, c, false, s0 + 1);
     if (lane_id() == 0) {
       cs[c].retries += r0 + 1;
       cs[c].confirm_rej += 1;
@@ -1210,8 +1217,19 @@ __global__ __launch_bounds__(64) void k_stitch(const FileDesc *files, const Chun
 // ---------------------------------------------------------------------------
 // k_finalize: one workgroup per file.  Checks that every accepted start is
 // the previous chunk's end, repairs sequentially if not, then the exclusive
-// scan of the chunk lengths gives the output offsets.
+// scan of the chunk lengths gives the output offsets.  A chunk that starts
+// on a stored header at s after a chunk that ended at e, s < e, in the same
+// run of zero bits before the same LEN/NLEN, began the same block: its start
+// becomes e with nothing decoded again.
 // ---------------------------------------------------------------------------
+
+__device__ __forceinline__ bool stored_equivalent(const FileDesc &fd, uint64_t s, uint64_t e) {
+  if (!(fd.mode & FD_STORED_STARTS) || !(s < e) || ((s + 10u) >> 3) != ((e + 10u) >> 3)) return false;
+  Src src;
+  src.init(fd.comp, fd.comp_len);
+  const uint64_t v = src.peek64(s);
+  return (v & 7u) == 0u && stored_start_bits(v, s, src.end_bits);
+}
 
 template <int WIN>
 __global__ __launch_bounds__(256) void k_finalize(const FileDesc *files, const ChunkDesc *chunks, ChunkState *cs,
@@ -1238,6 +1256,10 @@ __global__ __launch_bounds__(256) void k_finalize(const FileDesc *files, const C
       continue;
     }
     const ChunkState sp = cs[p];
+    if (sp.status == ST_OK && !(sp.flags & CS_FINAL) && sp.end != sj.start && stored_equivalent(fd, sj.start, sp.end)) {
+      cs[j].start = sp.end;  // the same stored block: the same symbols and end
+      continue;
+    }
     if (sp.status != ST_OK || (sp.flags & CS_FINAL) || sp.end != sj.start) bad = 1;
   }
   __syncthreads();
@@ -1260,7 +1282,9 @@ __global__ __launch_bounds__(256) void k_finalize(const FileDesc *files, const C
         }
         continue;
       }
-      if (j != c0 && sj != cur) {
+      if (j != c0 && sj != cur && stored_equivalent(fd, sj, cur)) {
+        if (tid == 0) cs[j].start = cur;
+      } else if (j != c0 && sj != cur) {
         repairs++;
         uint32_t nx;
         uint64_t stop = uni64(next_start(fd, cs, j, true, &nx));
@@ -2037,10 +2061,15 @@ hipError_t gzk_scan(const FileDesc *files, const ChunkDesc *chunks, ChunkState *
       return hipErrorInvalidValue; \
   }
 
-hipError_t gzk_inflate(int win, uint32_t grid, const FileDesc *files, const ChunkDesc *chunks, ChunkState *cs,
-                       const uint32_t *order, uint32_t n, Counters *ctr, uint16_t *pool, hipStream_t st) {
-  GZ_WIN_SWITCH(win, hipLaunchKernelGGL(k_inflate<W>, dim3(grid), dim3(64), 0, st, files, chunks, cs, order, n, ctr,
-                                        pool));
+hipError_t gzk_inflate(int win, uint32_t stored, uint32_t grid, const FileDesc *files, const ChunkDesc *chunks,
+                       ChunkState *cs, const uint32_t *order, uint32_t n, Counters *ctr, uint16_t *pool, hipStream_t st) {
+  if (stored) {
+    GZ_WIN_SWITCH(win, hipLaunchKernelGGL((k_inflate<W, true>), dim3(grid), dim3(64), 0, st, files, chunks, cs, order,
+                                          n, ctr, pool));
+  } else {
+    GZ_WIN_SWITCH(win, hipLaunchKernelGGL((k_inflate<W, false>), dim3(grid), dim3(64), 0, st, files, chunks, cs, order,
+                                          n, ctr, pool));
+  }
   return hipGetLastError();
 }
 

@@ -19,7 +19,7 @@ __global__ void k_stage2_diff(const uint8_t *buf, uint64_t n, const uint64_t *bi
   // one candidate per lane
   for (int i0 = 0; i0 < nb; i0 += 64) {
     const int i = i0 + (int)threadIdx.x;
-    if (i < nb) res_lane[i] = lane_tables_ok(s, bits[i], tab, (int)threadIdx.x) ? 1 : 0;
+    if (i < nb) res_lane[i] = lane_tables_ok(s, bits[i], tab, (int)threadIdx.x, 0u) ? 1 : 0;
   }
   for (int i = 0; i < nb; i++) {
     WaveBits a;

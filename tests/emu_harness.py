@@ -16,7 +16,7 @@ class Opts(C.Structure):
     _fields_ = [("chunk_bytes", C.c_uint64), ("sym_factor", C.c_uint32), ("window_syms", C.c_uint32),
                 ("scan_groups", C.c_uint32), ("inflate_waves_per_cu", C.c_uint32), ("waves_per_chunk", C.c_uint32),
                 ("timing", C.c_uint32), ("confirm_decode", C.c_uint32), ("binary", C.c_uint32),
-                ("tuned", C.c_uint32), ("reserved", C.c_uint32 * 3)]
+                ("tuned", C.c_uint32), ("start_types", C.c_uint32), ("reserved", C.c_uint32 * 2)]
 
 
 class Info(C.Structure):

@@ -717,3 +717,29 @@ def test_emu_binary_mode(orc):
     st, out, r, tab = E.run(comp, n, out_cap=len(raw) + 64, sync_limit=3_000_000_000)
     assert st == 0 and out == raw
     assert np.array_equal(_starts(tab), txt.start) and (txt.start[1:] < 0).all()
+
+
+def test_emu_stored_starts(orc):
+    """Stored blocks as chunk starts (opts.start_types): on a level-0 member
+    and on binary data with stored stretches (binary mode too), starts, ends,
+    lengths and repair counts equal the oracle's, starts found in the zero run
+    before a stored block's LEN/NLEN are taken as the previous chunk's end."""
+    T = orc.START_DYNAMIC | orc.START_STORED
+    cases = [(synth.fastq_like(400 << 10, 72), 0, 7, False)]
+    rawb = synth.binary_records(300 << 10, 8, noise_every=1, noise_bytes=80 << 10)
+    cases.append((rawb, 6, 6, True))
+    for raw, level, n, binary in cases:
+        comp = synth.gzip_member(raw, level)
+        ref = orc.pugz(comp, n, binary=binary, types=T)
+        assert ref.status == orc.OK and ref.out.tobytes() == raw and ref.n_equivalent >= 1
+        st, out, r, tab = E.run(comp, n, out_cap=len(raw) + 64, sync_limit=3_000_000_000, start_types=2,
+                                binary=int(binary))
+        assert st == 0 and out == raw
+        assert np.array_equal(_starts(tab), ref.start)
+        ne = ref.start >= 0
+        assert np.array_equal(tab["end"][ne].astype(np.int64), ref.end[ne])
+        assert np.array_equal(tab["len"][ne].astype(np.int64), ref.len[ne])
+        assert r.n_repairs == ref.n_repairs == 0
+    # fixed blocks are not offered as starts
+    st, out, r, tab = E.run(comp, 2, out_cap=len(rawb) + 64, start_types=4)
+    assert st == -1

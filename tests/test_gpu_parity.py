@@ -413,3 +413,35 @@ def test_binary_mode(orc, level):
     assert set(s[s >= 0].tolist()) <= blocks and (s >= 0).sum() > len(blocks) // 2
     got, plan = _run(comp, 24)
     assert got == raw and (_starts(plan.chunk_table())[1:] < 0).all()
+
+
+@pytest.mark.parametrize("case", ["level0-text", "binary-stored"])
+def test_stored_starts(orc, case):
+    """Stored blocks as chunk starts (opts.start_types = GZ_START_STORED): at
+    24 chunks the starts, ends, lengths and offsets equal the oracle's method
+    with stored starts, with no repair; with the default chunking every start
+    is a block of gunzip's map and the bytes are the source's."""
+    gz = _gz()
+    if case == "level0-text":
+        raw = synth.fastq_like(8 << 20, 75)
+        comp, binary = synth.gzip_member(raw, 0), 0
+    else:
+        raw = synth.binary_records(8 << 20, 76, noise_every=2, noise_bytes=256 << 10)
+        comp, binary = synth.gzip_member(raw, 6), 1
+    _say("stored starts", case)
+    ref = orc.pugz(comp, 24, binary=bool(binary), types=orc.START_DYNAMIC | orc.START_STORED)
+    assert ref.status == orc.OK and ref.out.tobytes() == raw and ref.n_repairs == 0
+    got, plan = _run(comp, 24, start_types=gz.GZ_START_STORED, binary=binary)
+    assert got == raw and plan.result().n_repairs == 0
+    tab = plan.chunk_table()
+    assert np.array_equal(_starts(tab), ref.start)
+    ne = ref.start >= 0
+    for k, v in (("end", ref.end), ("len", ref.len), ("out_off", ref.off)):
+        assert np.array_equal(tab[k][ne].astype(np.int64), v[ne]), k
+    g = orc.gunzip(comp)
+    got, plan = _run(comp, 0, start_types=gz.GZ_START_STORED, binary=binary)
+    assert got == raw
+    s = _starts(plan.chunk_table())
+    assert set(s[s >= 0].tolist()) <= set(g.block_bit.tolist())
+    with pytest.raises(gz.GzError):
+        gz.Plan(_dev(comp), 4, start_types=4)

@@ -789,3 +789,45 @@ def test_binary_mode_pugz(orc, n):
     t = orc.pugz(comp, n)
     assert t.status == orc.OK and t.out.tobytes() == raw
     assert (t.start[1:] < 0).all()
+
+
+def test_stored_start_predicate(orc):
+    """Stored blocks as chunk starts: on a level-0 member (stored blocks only)
+    every non-final stored block of more than 1 KiB passes the static check
+    with the stored type and not without it; a bit just after its LEN/NLEN
+    bytes does not; the first passing bit of a range holding a stored header
+    lies in the zero run just before that header's LEN/NLEN."""
+    raw = synth.fastq_like(1 << 20, 73)
+    comp = synth.gzip_member(raw, 0)
+    g = orc.gunzip(comp)
+    assert (g.block_type == 0).all() and len(g.block_bit) > 10
+    T = orc.START_DYNAMIC | orc.START_STORED
+    for b, f, size in zip(g.block_bit, g.block_final, g.block_out_len):
+        b = int(b)
+        ok, why = orc.block_static(comp, b, T)
+        assert ok == (not f and size > 1024), (b, why)
+        assert not orc.block_static(comp, b)[0]
+        p = (b + 10) >> 3  # byte holding LEN
+        assert not orc.block_static(comp, 8 * p + 33, T)[0]
+        if not f:
+            s = orc.find_start(comp, b - 12, b + 64, static_only=True, types=T)
+            assert b - 10 <= s <= b and ((s + 10) >> 3) == p
+
+
+@pytest.mark.parametrize("n", [2, 5, 11])
+def test_stored_starts_pugz(orc, n):
+    """The two-pass method with stored starts on a level-0 member: byte exact,
+    every chunk start after the stitch check is a block of the map, and the
+    starts found a bit or two early (in the zero run before the same LEN)
+    are taken as the previous chunk's end without a repair."""
+    raw = synth.fastq_like(1 << 20, 74)
+    comp = synth.gzip_member(raw, 0)
+    g = orc.gunzip(comp)
+    blocks = set(g.block_bit.tolist())
+    r = orc.pugz(comp, n, types=orc.START_DYNAMIC | orc.START_STORED)
+    assert r.status == orc.OK and r.out.tobytes() == raw and r.n_repairs == 0
+    s = r.start[r.start >= 0]
+    assert s.size == n and set(s.tolist()) <= blocks
+    assert r.n_equivalent == int((r.cand[1:] != r.start[1:]).sum()) and r.n_equivalent >= 1
+    d = orc.pugz(comp, n)
+    assert d.out.tobytes() == raw and (d.start[1:] < 0).all()
