@@ -831,3 +831,26 @@ def test_stored_starts_pugz(orc, n):
     assert r.n_equivalent == int((r.cand[1:] != r.start[1:]).sum()) and r.n_equivalent >= 1
     d = orc.pugz(comp, n)
     assert d.out.tobytes() == raw and (d.start[1:] < 0).all()
+
+
+def test_fixed_starts_resynchronise(orc):
+    """Why fixed blocks are not offered as chunk starts: on a member of fixed
+    blocks only (zlib's Z_FIXED strategy), searching fixed starts with
+    Appendix A's checks finds positions inside blocks whose decode has
+    resynchronised with the true code stream; the stitch check repairs them,
+    so the output stays exact, but most starts are repairs."""
+    import struct
+
+    raw = synth.fastq_like(2 << 20, 71)
+    co = zlib.compressobj(6, zlib.DEFLATED, -15, 9, zlib.Z_FIXED)
+    deflate = co.compress(raw) + co.flush()
+    comp = (b"\x1f\x8b\x08\x00\x00\x00\x00\x00\x00\x03" + deflate
+            + struct.pack("<II", zlib.crc32(raw) & 0xFFFFFFFF, len(raw) & 0xFFFFFFFF))
+    g = orc.gunzip(comp)
+    assert g.status == orc.OK and (g.block_type == 1).all()
+    r = orc.pugz(comp, 8, types=orc.START_DYNAMIC | orc.START_FIXED)
+    assert r.status == orc.OK and r.out.tobytes() == raw
+    found = r.cand[1:][r.cand[1:] >= 0]
+    assert found.size >= 4 and r.n_repairs * 2 > found.size
+    # the repaired starts were not blocks of the map
+    assert len(set(found.tolist()) - set(g.block_bit.tolist())) >= r.n_repairs
