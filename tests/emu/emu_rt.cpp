@@ -1,6 +1,9 @@
 // Test-side executor: runs HIP kernel source on the CPU.
 //
-// A block's threads are ucontext fibers.  A fiber runs until it reaches a
+// A block's threads are fibers, each on a stack of its own, switched by a
+// small x86-64 routine that saves only the callee-saved registers (ucontext's
+// swapcontext also saves the signal mask, a system call on every switch).  A
+// fiber runs until it reaches a
 // synchronisation point: a wave intrinsic (ballot, readlane, readfirstlane,
 // shuffle, wave barrier), which completes when all 64 lanes of its wave have
 // reached the same intrinsic, or __syncthreads, which completes when every
@@ -9,17 +12,49 @@
 // finished, and a block where nothing can advance are reported and abort the
 // process: on the GPU these are divergence bugs or hangs.
 #include <hip/hip_runtime.h>
-#include <signal.h>
-#include <ucontext.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
 
 #include <vector>
+
+// emu_switch(save, to): pushes rbp, rbx, r12-r15, stores the stack pointer
+// in *save, loads `to` as the stack pointer, pops the same registers of the
+// other fiber and returns into it.
+extern "C" void emu_switch(void **save, void *to);
+asm(R"(
+  .pushsection .text
+  .p2align 4
+  .globl emu_switch
+  .hidden emu_switch
+  .type emu_switch,@function
+emu_switch:
+  pushq %rbp
+  pushq %rbx
+  pushq %r12
+  pushq %r13
+  pushq %r14
+  pushq %r15
+  movq %rsp, (%rdi)
+  movq %rsi, %rsp
+  popq %r15
+  popq %r14
+  popq %r13
+  popq %r12
+  popq %rbx
+  popq %rbp
+  ret
+  .size emu_switch, .-emu_switch
+  .popsection
+)");
 
 namespace {
 
 enum State { RUNNABLE, AT_WAVE, AT_BLOCK, DONE };
 
 struct Fiber {
-  ucontext_t ctx;
+  void *sp = nullptr;
   unsigned tid = 0;
   State st = RUNNABLE;
   int kind = 0;
@@ -30,7 +65,7 @@ struct Fiber {
 struct Block {
   std::vector<Fiber> f;
   unsigned nthreads = 0, bid = 0, bdim = 0, gdim = 0;
-  ucontext_t sched;
+  void *sched = nullptr;
   void (*fn)(void *) = nullptr;
   void *arg = nullptr;
 };
@@ -41,10 +76,23 @@ const size_t STACK = 256 * 1024;
 uint64_t g_syncs = 0;
 uint64_t g_sync_limit = 0;  // 0: none
 
-void fiber_entry() {
+// First code of every fiber (entered by emu_switch's return); never returns.
+[[noreturn]] void fiber_entry() {
   g_blk->fn(g_blk->arg);
   g_cur->st = DONE;
-  swapcontext(&g_cur->ctx, &g_blk->sched);
+  emu_switch(&g_cur->sp, g_blk->sched);
+  abort();
+}
+
+// A fresh stack as emu_switch leaves one: six zero registers, then
+// fiber_entry as the return address, then an empty slot so that fiber_entry
+// starts with the stack aligned as after a call (rsp = 8 mod 16).
+void *fresh_stack(char *stack) {
+  void **sp = (void **)(((uintptr_t)stack + STACK) & ~(uintptr_t)15);
+  *--sp = nullptr;
+  *--sp = (void *)&fiber_entry;
+  for (int i = 0; i < 6; i++) *--sp = nullptr;
+  return sp;
 }
 
 [[noreturn]] void die(const char *msg, unsigned w) {
@@ -109,15 +157,27 @@ void resolve_wave(unsigned w) {
 
 extern "C" char __start_emu_lds[], __stop_emu_lds[];
 uint64_t g_fill = 0x9E3779B97F4A7C15ull;
+std::vector<char> g_garbage;  // xorshift bytes, twice the LDS section
 
-// LDS holds garbage when a block starts: fill every __shared__ variable
+// LDS holds garbage when a block starts: every __shared__ variable (of all
+// kernels: one section) is filled from a random pool at a random offset, so
+// that a value left by an earlier block, or a fixed pattern, cannot pass for
+// an initialised one.
 void scramble_lds() {
-  for (char *p = __start_emu_lds; p < __stop_emu_lds; p++) {
-    g_fill ^= g_fill << 13;
-    g_fill ^= g_fill >> 7;
-    g_fill ^= g_fill << 17;
-    *p = (char)g_fill;
+  const size_t n = (size_t)(__stop_emu_lds - __start_emu_lds);
+  if (g_garbage.size() < 2 * n) {
+    g_garbage.resize(2 * n);
+    for (auto &c : g_garbage) {
+      g_fill ^= g_fill << 13;
+      g_fill ^= g_fill >> 7;
+      g_fill ^= g_fill << 17;
+      c = (char)g_fill;
+    }
   }
+  g_fill ^= g_fill << 13;
+  g_fill ^= g_fill >> 7;
+  g_fill ^= g_fill << 17;
+  memcpy(__start_emu_lds, g_garbage.data() + (size_t)(g_fill % (n + 1)), n);
 }
 
 void run_block(unsigned bid) {
@@ -128,11 +188,7 @@ void run_block(unsigned bid) {
     Fiber &f = B.f[t];
     f.tid = t;
     f.st = RUNNABLE;
-    getcontext(&f.ctx);
-    f.ctx.uc_stack.ss_sp = f.stack;
-    f.ctx.uc_stack.ss_size = STACK;
-    f.ctx.uc_link = nullptr;
-    makecontext(&f.ctx, fiber_entry, 0);
+    f.sp = fresh_stack(f.stack);
   }
   const unsigned nw = (B.nthreads + 63) / 64;
   for (;;) {
@@ -142,7 +198,7 @@ void run_block(unsigned bid) {
       if (f.st != RUNNABLE) continue;
       ran = true;
       g_cur = &f;
-      swapcontext(&B.sched, &f.ctx);
+      emu_switch(&B.sched, f.sp);
       g_cur = nullptr;
     }
     for (unsigned w = 0; w < nw; w++) resolve_wave(w);
@@ -192,14 +248,14 @@ uint64_t emu_wave_sync(int kind, uint64_t v, uint64_t aux) {
   f->val = v;
   f->aux = aux;
   f->st = AT_WAVE;
-  swapcontext(&f->ctx, &g_blk->sched);
+  emu_switch(&f->sp, g_blk->sched);
   return f->res;
 }
 
 void emu_block_sync(void) {
   Fiber *f = g_cur;
   f->st = AT_BLOCK;
-  swapcontext(&f->ctx, &g_blk->sched);
+  emu_switch(&f->sp, g_blk->sched);
 }
 
 unsigned emu_tid(void) { return g_cur->tid; }
