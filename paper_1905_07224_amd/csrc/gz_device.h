@@ -205,13 +205,28 @@ struct WaveBits {
 
 // ---------------------------------------------------------------------------
 // Huffman lookup tables (RFC 1951 section 3.2.2 canonical codes).
-// Entry: [3:0] code length, [7:4] kind, [15:8] extra bits or literal byte,
-// [31:16] base length / distance.
+//
+// Distance (and code-length) entries: [3:0] code length, [7:4] kind, [15:8]
+// extra bits (code-length codes: the symbol), [31:16] base distance.
+//
+// Literal/length entries are the decoder's token words wherever the code
+// alone fixes the token: [7:0] bits used, [16:8] output symbols, [31:17]
+// payload.  A literal: 1 output symbol, the byte in [24:17], and bit 31 set
+// when the byte is outside the block-start check's ASCII set.  A special
+// token has 448 output symbols and its kind in [31:17] (end-of-block: its
+// code length in [7:0]).  A length code, whose token also depends on the
+// bits that follow it, has 0 output symbols: [3:0] code length, [7:4] extra
+// bits, [25:17] base length.
 // ---------------------------------------------------------------------------
 
-// K_LITX: a literal outside the block-start check's ASCII set (kind & 7 is
-// K_LIT for both literal kinds)
-enum : uint32_t { K_LIT = 0, K_LEN = 1, K_EOB = 2, K_LONG = 3, K_BAD = 4, K_BADSYM = 5, K_LITX = 8 };
+enum : uint32_t { K_LEN = 1, K_LONG = 3, K_BAD = 4, K_BADSYM = 5 };
+
+constexpr uint32_t TOK_SPECIAL = 448u << 8;
+constexpr uint32_t TOK_EOB = TOK_SPECIAL | (1u << 17);
+constexpr uint32_t TOK_SLOW = TOK_SPECIAL | (2u << 17);    // a code longer than the table: decoded alone
+constexpr uint32_t TOK_ASCII = TOK_SPECIAL | (3u << 17);   // (decoder only) a non-ASCII literal in a checked block
+constexpr uint32_t TOK_BADSYM = TOK_SPECIAL | (4u << 17);  // literal/length 286, 287, or no code at all
+constexpr uint32_t TOK_NONASCII = 1u << 31;
 
 constexpr int LIT_BITS = 10;
 constexpr int DIST_BITS = 9;
@@ -220,8 +235,8 @@ constexpr int CL_BITS = 7;
 // lengths 3..258 (section 3.2.5): codes 257..264 carry no extra bits, then
 // four codes per extra-bit count 1..5, then 285 = 258
 __device__ __forceinline__ uint32_t litlen_entry(uint32_t sym, uint32_t len) {
-  if (sym < 256u) return len | ((ascii_text(sym) ? K_LIT : K_LITX) << 4) | (sym << 8);
-  if (sym == 256u) return len | (K_EOB << 4);
+  if (sym < 256u) return len | (1u << 8) | (sym << 17) | (ascii_text(sym) ? 0u : TOK_NONASCII);
+  if (sym == 256u) return TOK_EOB | len;
   if (sym <= 285u) {
     uint32_t i = sym - 257u, ex, base;
     if (i < 8u) {
@@ -234,9 +249,9 @@ __device__ __forceinline__ uint32_t litlen_entry(uint32_t sym, uint32_t len) {
       ex = (i - 4u) >> 2;
       base = ((4u + (i & 3u)) << ex) + 3u;
     }
-    return len | (K_LEN << 4) | (ex << 8) | (base << 16);
+    return len | (ex << 4) | (base << 17);
   }
-  return len | (K_BADSYM << 4);
+  return TOK_BADSYM;
 }
 // distances 1..32768: codes 0..3 exact, then two codes per extra-bit count 1..13
 __device__ __forceinline__ uint32_t dist_entry(uint32_t sym, uint32_t len) {
@@ -267,7 +282,8 @@ enum TreeKind { TREE_LIT = 0, TREE_DIST = 1, TREE_CL = 2 };
 // Returns the Kraft remainder scaled by 2^15 (0 complete, > 0 incomplete,
 // < 0 over-subscribed) and the number of codes.  With fill, also writes the
 // sorted symbol list, the per-length info and the 2^LB-entry lookup table
-// (codes longer than LB get K_LONG, unused bit patterns K_BAD).
+// (codes longer than LB get K_LONG, unused bit patterns K_BAD; in the
+// literal/length table TOK_SLOW and TOK_BADSYM).
 template <int LB, int KIND>
 __device__ int build_tree(const uint8_t *lens, int n, uint32_t *tab, TreeInfo *ti, uint16_t *sorted, int *ncodes,
                           bool fill) {
@@ -359,9 +375,9 @@ __device__ int build_tree(const uint8_t *lens, int n, uint32_t *tab, TreeInfo *t
           : KIND == TREE_DIST ? dist_entry(sym, (uint32_t)len)
                               : cl_entry(sym, (uint32_t)len);
     } else if ((P << (15 - LB)) < end15) {
-      e = K_LONG << 4;
+      e = KIND == TREE_LIT ? TOK_SLOW : K_LONG << 4;
     } else {
-      e = K_BAD << 4;
+      e = KIND == TREE_LIT ? TOK_BADSYM : K_BAD << 4;
     }
     tab[x] = e;
   }
@@ -381,7 +397,7 @@ __device__ __forceinline__ uint32_t decode_long(uint64_t v, const TreeInfo *ti, 
       return KIND == TREE_LIT ? litlen_entry(sym, (uint32_t)l) : dist_entry(sym, (uint32_t)l);
     }
   }
-  return K_BAD << 4;
+  return KIND == TREE_LIT ? TOK_BADSYM : K_BAD << 4;
 }
 
 // ---------------------------------------------------------------------------

@@ -251,24 +251,24 @@ struct Inflater {
   __device__ int slow_symbol(bool check, uint32_t *lit, uint32_t *len_out, uint32_t *dist_out) {
     const uint64_t v = br.next();
     uint32_t e = uni32(sh.t.lit[v & ((1u << LIT_BITS) - 1u)]);
-    if (((e >> 4) & 15u) == K_LONG) e = decode_long<LIT_BITS, TREE_LIT>(v, &sh.t.li, sh.t.lsorted);
-    const uint32_t kind = (e >> 4) & 15u, cl = e & 15u;
+    if (e == TOK_SLOW) e = decode_long<LIT_BITS, TREE_LIT>(v, &sh.t.li, sh.t.lsorted);
+    const uint32_t nout = (e >> 8) & 511u, cl = e & 15u;
     nsyms++;
-    if ((kind & 7u) == K_LIT) {
-      if (check && ascii && kind == K_LITX) return D_ASCII;
-      *lit = (e >> 8) & 255u;
+    if (nout == 1u) {
+      if (check && ascii && (e & TOK_NONASCII)) return D_ASCII;
+      *lit = (e >> 17) & 255u;
       *len_out = 0;
       br.skip(cl);
       return br.past_end() ? D_TRUNC : D_OK;
     }
-    if (kind == K_EOB) {
+    if ((e & ~255u) == TOK_EOB) {
       *len_out = 0xFFFFFFFFu;
       br.skip(cl);
       return br.past_end() ? D_TRUNC : D_OK;
     }
-    if (kind != K_LEN) return D_BAD;
-    const uint32_t ex = (e >> 8) & 255u;
-    const uint32_t len = (e >> 16) + ((uint32_t)(v >> cl) & ((1u << ex) - 1u));
+    if (nout != 0u) return D_BAD;
+    const uint32_t ex = (e >> 4) & 15u;
+    const uint32_t len = (e >> 17) + ((uint32_t)(v >> cl) & ((1u << ex) - 1u));
     const uint32_t used = cl + ex;
     const uint64_t v2 = v >> used;
     uint32_t ed = uni32(sh.t.dist[v2 & ((1u << DIST_BITS) - 1u)]);
@@ -288,33 +288,30 @@ struct Inflater {
   // its packed (output symbols << 8 | bit offset) counter: the low 17 bits
   // hold the counter (fewer than 64 + 258 symbols, offsets below 256), the
   // bits above only collect the payloads and are never read.  A special
-  // token has length 448: added to fewer than 64 symbols it sets bits 14..16
-  // of the counter, which ends any walk, and stays below bit 17; its kind is
-  // in bits 31..17 (end-of-block: its code length in bits 7..0).
-  static constexpr uint32_t TOK_SPECIAL = 448u << 8;
-  static constexpr uint32_t TOK_EOB = TOK_SPECIAL | (1u << 17);
-  static constexpr uint32_t TOK_SLOW = TOK_SPECIAL | (2u << 17);   // longer code, or invalid: decoded alone
-  static constexpr uint32_t TOK_ASCII = TOK_SPECIAL | (3u << 17);  // non-ASCII literal in a checked block
+  // token (TOK_*) has length 448: added to fewer than 64 symbols it sets
+  // bits 14..16 of the counter, which ends any walk, and stays below bit 17.
+  // Literal and special tokens are literal/length table entries as they
+  // stand; only a length code's token is assembled here.
   __device__ __forceinline__ static bool tok_special(uint32_t t) { return (t & TOK_SPECIAL) == TOK_SPECIAL; }
 
   // The token word at bit offset k of a lookup round, from the 64 stream
   // bits at that offset (w: bits k .. k + 63) and its two table entries
   // (e: literal/length, ed: distance, looked up at the bits after the
-  // length's extra bits).  Straight-line code: every case is computed and
-  // one is selected.
+  // length's extra bits).  Straight-line code: the match case is computed
+  // for every lane and selected where e is a length code.
   template <bool CHECK>
   __device__ __forceinline__ static uint32_t token_word(uint64_t w, uint32_t e, uint32_t ed, bool ascii) {
     const uint32_t w0 = (uint32_t)w;
-    const uint32_t kind = (e >> 4) & 15u, cl = e & 15u, ex = (e >> 8) & 15u;
+    const uint32_t cl = e & 15u, ex = (e >> 4) & 15u;
     const uint32_t u = cl + ex;
     const uint32_t dl = ed & 15u, dex = (ed >> 8) & 15u;
-    const uint32_t len = (e >> 16) + ((w0 >> cl) & ((1u << ex) - 1u));
+    const uint32_t len = (e >> 17) + ((w0 >> cl) & ((1u << ex) - 1u));
     const uint32_t dist = (ed >> 16) + ((uint32_t)(w >> (u + dl)) & ((1u << dex) - 1u));
-    uint32_t wl = cl | (1u << 8) | (((e >> 8) & 255u) << 17);
-    if (CHECK) wl = (kind == K_LITX && ascii) ? TOK_ASCII : wl;
     const uint32_t wm = ((ed >> 4) & 15u) == K_LEN ? (u + dl + dex) | (len << 8) | ((dist - 1u) << 17) : TOK_SLOW;
-    const uint32_t wo = kind == K_EOB ? (TOK_EOB | cl) : TOK_SLOW;
-    return (kind & 7u) == K_LIT ? wl : kind == K_LEN ? wm : wo;
+    uint32_t t = (e & (511u << 8)) == 0u ? wm : e;
+    // only literal entries have bit 31 set
+    if (CHECK) t = (ascii && (e & TOK_NONASCII)) ? TOK_ASCII : t;
+    return t;
   }
 
   // Token words at bit offsets k (wa) and k + 64 (wb): both
@@ -324,7 +321,8 @@ struct Inflater {
     const uint32_t LMASK = (1u << LIT_BITS) - 1u, DMASK = (1u << DIST_BITS) - 1u;
     const uint32_t ea = sh_lit((uint32_t)wa & LMASK);
     const uint32_t eb = sh_lit((uint32_t)wb & LMASK);
-    const uint32_t ua = (ea & 15u) + ((ea >> 8) & 15u), ub = (eb & 15u) + ((eb >> 8) & 15u);
+    // the bits after a length code's extra bits (elsewhere unused)
+    const uint32_t ua = (ea & 15u) + ((ea >> 4) & 15u), ub = (eb & 15u) + ((eb >> 4) & 15u);
     const uint32_t eda = sh_dist((uint32_t)(wa >> ua) & DMASK);
     const uint32_t edb = sh_dist((uint32_t)(wb >> ub) & DMASK);
     ta = token_word<CHECK>(wa, ea, eda, ascii);
@@ -453,7 +451,8 @@ struct Inflater {
           if (r != D_OK) return r;
           return br.past_end() ? D_TRUNC : D_OK;
         }
-        // TOK_SLOW: one symbol decoded alone, then a new round
+        // TOK_SLOW or TOK_BADSYM: one symbol decoded alone (a bad one fails
+        // there), then a new round
         br.pos += off;
         off = 0;
         need = true;
