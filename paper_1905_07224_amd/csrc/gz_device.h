@@ -582,50 +582,61 @@ __device__ __forceinline__ void kraft3_fill(uint8_t *k3, int tid, int nthreads) 
   }
 }
 
-// The cheap stage for the 32 candidates of one aligned dword at once: bit k
-// of the result is start_stage1 of bit 32 * W + k of the aligned view (file
-// bit 32 * W + k - 8 * mis).  x0..x3: dwords W .. W + 3 (zero past the
-// buffer).  The 3-bit header pattern is tested for all 32 positions with
-// word operations; the rest only where it holds (one position in eight).
-// The code-length code's Kraft sum takes seven lookups in k3 (kraft3_fill).
-__device__ __forceinline__ uint32_t start_stage1_word(const Src &s, int64_t W, uint32_t x0, uint32_t x1, uint32_t x2,
-                                                      uint32_t x3, const uint8_t *k3, uint32_t mode) {
+// The cheap stage for the 32 candidates of one aligned dword (dword W of the
+// aligned view; its bit k is file bit 32 * W + k - 8 * mis), in three parts.
+// x0..x3: dwords W .. W + 3 (zero past the buffer).
+//
+// stage1_header_mask: the positions where BFINAL = 0, BTYPE = 10, HLIT <= 29
+// and HDIST <= 29, all 32 tested with word operations (a 5-bit count is 30
+// or 31 exactly when its upper four bits are set).
+__device__ __forceinline__ uint32_t stage1_header_mask(uint32_t x0, uint32_t x1) {
   const uint64_t lo = ((uint64_t)x1 << 32) | x0;
-  uint32_t pat = (uint32_t)(~lo & ~(lo >> 1) & (lo >> 2));  // BFINAL = 0, BTYPE = 10
+  const uint64_t hlit_hi = (lo >> 4) & (lo >> 5) & (lo >> 6) & (lo >> 7);
+  const uint64_t hdist_hi = (lo >> 9) & (lo >> 10) & (lo >> 11) & (lo >> 12);
+  return (uint32_t)(~lo & ~(lo >> 1) & (lo >> 2) & ~hlit_hi & ~hdist_hi);
+}
+
+// stage1_kraft_ok: for one position k with a passing header, whether the
+// code-length code is complete; its Kraft sum takes seven lookups in k3
+// (kraft3_fill) over the 3-bit lengths from bit 17 on, HCLEN of them.
+__device__ __forceinline__ bool stage1_kraft_ok(uint32_t x0, uint32_t x1, uint32_t x2, uint32_t x3, uint32_t k,
+                                                const uint8_t *k3) {
+  const uint32_t w0 = __builtin_amdgcn_alignbit(x1, x0, k);
+  const uint32_t w1 = __builtin_amdgcn_alignbit(x2, x1, k);
+  const uint32_t w2 = __builtin_amdgcn_alignbit(x3, x2, k);
+  const uint32_t hclen = ((w0 >> 13) & 15u) + 4u;
+  const uint64_t cl = ((uint64_t)(w0 >> 17) | ((uint64_t)w1 << 15) | ((uint64_t)w2 << 47)) &
+                      ((1ull << (3 * hclen)) - 1ull);
+  const uint32_t sum = (uint32_t)k3[cl & 511u] + k3[(cl >> 9) & 511u] + k3[(cl >> 18) & 511u] +
+                       k3[(cl >> 27) & 511u] + k3[(cl >> 36) & 511u] + k3[(cl >> 45) & 511u] + k3[cl >> 54];
+  return sum == 128u;
+}
+
+// stage1_stored_mask (FD_STORED_STARTS only): the positions where BFINAL = 0,
+// BTYPE = 00 and the padding and LEN/NLEN pass (they lie within the four
+// dwords: a byte boundary of the view is one of the file).
+__device__ __forceinline__ uint32_t stage1_stored_mask(const Src &s, int64_t W, uint32_t x0, uint32_t x1, uint32_t x2,
+                                                       uint32_t x3) {
+  const uint64_t lo = ((uint64_t)x1 << 32) | x0;
+  const uint64_t hi = ((uint64_t)x3 << 32) | x2;
+  uint32_t sp = (uint32_t)(~lo & ~(lo >> 1) & ~(lo >> 2));
   uint32_t pass = 0;
-  if (mode & FD_STORED_STARTS) {
-    // BFINAL = 0, BTYPE = 00: the padding and LEN/NLEN lie within the four
-    // dwords (a byte boundary of the view is one of the file)
-    const uint64_t hi = ((uint64_t)x3 << 32) | x2;
-    uint32_t sp = (uint32_t)(~lo & ~(lo >> 1) & ~(lo >> 2));
-    for (int g = 0; g < 32 && sp; g++) {
-      const uint32_t k = (uint32_t)__builtin_ctz(sp);
-      sp &= sp - 1;
-      const int64_t b = 32 * W + (int64_t)k - 8 * (int64_t)s.mis;
-      if (b < 0) continue;
-      const uint64_t v = (lo >> k) | (k ? hi << (64 - k) : 0ull);
-      if (stored_start_bits(v, (uint64_t)b, s.end_bits)) pass |= 1u << k;
-    }
-  }
-  for (int g = 0; g < 32 && pat; g++) {
-    const uint32_t k = (uint32_t)__builtin_ctz(pat);
-    pat &= pat - 1;
-    // file bit of this candidate must leave room for the 17 header bits
+  for (int g = 0; g < 32 && sp; g++) {
+    const uint32_t k = (uint32_t)__builtin_ctz(sp);
+    sp &= sp - 1;
     const int64_t b = 32 * W + (int64_t)k - 8 * (int64_t)s.mis;
-    if (b < 0 || (uint64_t)b + 17 > s.end_bits) continue;
-    const uint32_t w0 = __builtin_amdgcn_alignbit(x1, x0, k);
-    const uint32_t w1 = __builtin_amdgcn_alignbit(x2, x1, k);
-    const uint32_t w2 = __builtin_amdgcn_alignbit(x3, x2, k);
-    if (((w0 >> 3) & 31u) > 29u || ((w0 >> 8) & 31u) > 29u) continue;
-    const uint32_t hclen = ((w0 >> 13) & 15u) + 4u;
-    // code-length code lengths: 3 bits each from bit 17, hclen of them
-    const uint64_t cl = ((uint64_t)(w0 >> 17) | ((uint64_t)w1 << 15) | ((uint64_t)w2 << 47)) &
-                        ((1ull << (3 * hclen)) - 1ull);
-    const uint32_t sum = (uint32_t)k3[cl & 511u] + k3[(cl >> 9) & 511u] + k3[(cl >> 18) & 511u] +
-                         k3[(cl >> 27) & 511u] + k3[(cl >> 36) & 511u] + k3[(cl >> 45) & 511u] + k3[cl >> 54];
-    if (sum == 128u) pass |= 1u << k;
+    if (b < 0) continue;
+    const uint64_t v = (lo >> k) | (k ? hi << (64 - k) : 0ull);
+    if (stored_start_bits(v, (uint64_t)b, s.end_bits)) pass |= 1u << k;
   }
   return pass;
+}
+
+// Bits k of a dword whose file bit b0 + k lies in [lo, hi).
+__device__ __forceinline__ uint32_t bits_in(int64_t b0, int64_t lo, int64_t hi) {
+  const int64_t klo = std::min<int64_t>(32, std::max<int64_t>(0, lo - b0));
+  const int64_t khi = std::min<int64_t>(32, std::max<int64_t>(0, hi - b0));
+  return khi > klo ? (uint32_t)(((1ull << (khi - klo)) - 1ull) << klo) : 0u;
 }
 
 // The checks of read_dynamic_tables(strict, nothing stored), with the
@@ -724,11 +735,14 @@ __device__ int check_dynamic_tables(WaveBits &br, TablesLDS &sh) {
 // no wave operation (lanes check different candidates): the code-length
 // code's lookup table is built by the lane in its own column of `tab`
 // (128 entries, entry x at tab[64 * x + lane]: symbol | length << 5), and
-// the code lengths are read through a per-lane 64-bit bit buffer.
+// the code lengths are read through a per-lane 64-bit bit buffer, with the
+// dword after it loaded one refill ahead (so a refill does not wait for
+// memory).
 struct LaneBits {
   const Src *s;
-  int64_t D;     // next aligned dword to load
+  int64_t D;     // aligned dword after nxt
   uint64_t acc;  // unread bits, first one in bit 0
+  uint32_t nxt;  // the dword after acc's bits
   uint32_t n;    // bits in acc (>= 32 after every refill)
   uint64_t pos;  // file bit of acc's bit 0
   __device__ __forceinline__ void init(const Src &src, uint64_t b) {
@@ -736,12 +750,11 @@ struct LaneBits {
     const uint64_t a = b + 8ull * src.mis;
     D = (int64_t)(a >> 5);
     const uint32_t sh = (uint32_t)(a & 31);
-    acc = (uint64_t)src.dw(D) >> sh;
-    n = 32 - sh;
-    D++;
-    acc |= (uint64_t)src.dw(D) << n;
-    n += 32;
-    D++;
+    const uint32_t d0 = src.dw(D), d1 = src.dw(D + 1);
+    nxt = src.dw(D + 2);
+    D += 3;
+    acc = ((uint64_t)d0 >> sh) | ((uint64_t)d1 << (32 - sh));
+    n = 64 - sh;
     pos = b;
   }
   __device__ __forceinline__ void skip(uint32_t k) {
@@ -749,8 +762,9 @@ struct LaneBits {
     n -= k;
     pos += k;
     if (n < 32) {
-      acc |= (uint64_t)s->dw(D) << n;
+      acc |= (uint64_t)nxt << n;
       n += 32;
+      nxt = s->dw(D);
       D++;
     }
   }

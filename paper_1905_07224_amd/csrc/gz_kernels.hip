@@ -809,8 +809,12 @@ __global__ void k_init(ChunkState *cs, uint32_t n_chunks, FileState *fs, uint32_
 // ---------------------------------------------------------------------------
 // k_scan: for every chunk after the first of its file, the smallest bit in
 // [lo_bit, hi_bit) passing the static checks.  A wave covers 2048 candidate
-// bits per step, one aligned dword per lane (the cheap stage for all 32 bits
-// of it at once).  The survivors, rare, are queued in bit order; every
+// bits per step, one aligned dword per lane.  The header fields are tested
+// for all 32 bits of a dword at once; the positions that pass them (about
+// one in nine, at most eleven per dword) are compacted into a list in bit
+// order and their code-length codes tested 64 at a time, one per lane, so
+// that no lane idles while another works through its dword.  The
+// survivors, rare, are queued in bit order; every
 // SCAN_BATCH of them (and the rest at the end) are checked at once, one per
 // lane (the full table check), and the first that passes is the wave's
 // answer.  `groups` workgroups share one chunk and its 4 waves each take
@@ -829,7 +833,7 @@ __device__ __forceinline__ uint64_t readlane64(uint64_t v, int l) {
 __global__ __launch_bounds__(256) void k_scan(const FileDesc *files, const ChunkDesc *chunks, ChunkState *cs,
                                               const uint32_t *scan_list, uint32_t n_scan, uint32_t groups) {
   __shared__ uint8_t k3[512];
-  __shared__ uint8_t cltab[4][128 * 64];                  // per lane code-length tables, per wave
+  __shared__ uint8_t cltab[4][128 * 64] __attribute__((aligned(16)));  // per lane code-length tables, per wave
   __shared__ unsigned long long queue[4][2 * SCAN_BATCH];  // per wave: survivors in bit order
   kraft3_fill(k3, (int)threadIdx.x, (int)blockDim.x);
   __syncthreads();
@@ -879,18 +883,61 @@ __global__ __launch_bounds__(256) void k_scan(const FileDesc *files, const Chunk
   for (uint64_t t = (uint64_t)g + (uint64_t)groups * wave; t < steps && !found; t += (uint64_t)groups * 4u) {
     const int64_t Wt = W0 + 64 * (int64_t)t;
     const uint64_t first_bit = (uint64_t)std::max<int64_t>(32 * Wt - mb, (int64_t)cd.lo_bit);
+    // the step's 67 dwords: one per lane and the three after them (lanes 0..2),
+    // loaded together with the chunk's candidate so far; lane l takes dwords
+    // W + 1 .. W + 3 from the lanes after it
+    const int64_t W = Wt + lane;
+    const uint32_t x0 = s.dw(W);
+    const uint32_t xt = lane < 3 ? s.dw(Wt + 64 + lane) : 0u;
     const uint64_t cur = uni64(__hip_atomic_load(cand, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
     if (cur <= first_bit) break;
-    const int64_t W = Wt + lane;
-    uint32_t surv = 0;
+    const uint32_t t0 = (uint32_t)__builtin_amdgcn_readlane((int)xt, 0);
+    const uint32_t t1 = (uint32_t)__builtin_amdgcn_readlane((int)xt, 1);
+    const uint32_t t2 = (uint32_t)__builtin_amdgcn_readlane((int)xt, 2);
+    const uint32_t n1 = (uint32_t)__shfl((int)x0, (lane + 1) & 63);
+    const uint32_t n2 = (uint32_t)__shfl((int)x0, (lane + 2) & 63);
+    const uint32_t n3 = (uint32_t)__shfl((int)x0, (lane + 3) & 63);
+    const uint32_t x1 = lane < 63 ? n1 : t0;
+    const uint32_t x2 = lane < 62 ? n2 : lane == 62 ? t0 : t1;
+    const uint32_t x3 = lane < 61 ? n3 : lane == 61 ? t0 : lane == 62 ? t1 : t2;
+    uint32_t hdr = 0;   // positions whose header fields pass
+    uint32_t surv = 0;  // positions passing the whole cheap stage
     if (W < W1) {
-      surv = start_stage1_word(s, W, s.dw(W), s.dw(W + 1), s.dw(W + 2), s.dw(W + 3), k3, mode);
-      // only candidates in [lo_bit, hi_bit): bits [klo, khi) of this dword
+      // only candidates in [lo_bit, hi_bit); a dynamic header's 17 bits lie
+      // inside the file
       const int64_t b0 = 32 * W - mb;
-      const int64_t klo = std::min<int64_t>(32, std::max<int64_t>(0, (int64_t)cd.lo_bit - b0));
-      const int64_t khi = std::min<int64_t>(32, std::max<int64_t>(0, (int64_t)cd.hi_bit - b0));
-      const uint64_t keep = khi > klo ? (((1ull << (khi - klo)) - 1ull) << klo) : 0ull;
-      surv &= (uint32_t)keep;
+      const uint32_t keep = bits_in(b0, (int64_t)cd.lo_bit, (int64_t)cd.hi_bit);
+      hdr = stage1_header_mask(x0, x1) & keep & bits_in(b0, 0, (int64_t)s.end_bits - 16);
+      if (mode & FD_STORED_STARTS) surv = stage1_stored_mask(s, W, x0, x1, x2, x3) & keep;
+    }
+    // the header survivors of the wave in bit order (lane by lane, bits in a
+    // lane ascending): entry lane << 5 | bit, in this wave's table space,
+    // which is free until the survivors are checked below
+    {
+      const uint32_t cnt = (uint32_t)__builtin_popcount(hdr);
+      uint32_t at = 0, total = 0;
+      for (int bb = 0; bb < 4; bb++) {  // counts are at most 11
+        const uint64_t m = __ballot((cnt >> bb) & 1u);
+        at += (uint32_t)__builtin_popcountll(m & lanes_below()) << bb;
+        total += (uint32_t)__builtin_popcountll(m) << bb;
+      }
+      uint16_t *list = reinterpret_cast<uint16_t *>(cltab[wave]);
+      for (uint32_t p = hdr; p; p &= p - 1) list[at++] = (uint16_t)(((uint32_t)lane << 5) | (uint32_t)__builtin_ctz(p));
+      wave_sync();
+      for (uint32_t r = 0; r < total; r += 64) {
+        const uint32_t i = r + (uint32_t)lane;
+        const uint32_t e = i < total ? (uint32_t)list[i] : 0u;
+        const int src = (int)(e >> 5);
+        const uint32_t y0 = (uint32_t)__shfl((int)x0, src), y1 = (uint32_t)__shfl((int)x1, src);
+        const uint32_t y2 = (uint32_t)__shfl((int)x2, src), y3 = (uint32_t)__shfl((int)x3, src);
+        const bool ok = i < total && stage1_kraft_ok(y0, y1, y2, y3, e & 31u, k3);
+        // survivors are rare: each goes back to its lane's mask
+        for (uint64_t m = __ballot(ok); m; m &= m - 1) {
+          const uint32_t el = (uint32_t)__builtin_amdgcn_readlane((int)e, __ffsll((unsigned long long)m) - 1);
+          if ((uint32_t)lane == (el >> 5)) surv |= 1u << (el & 31u);
+        }
+      }
+      wave_sync();
     }
     // queue the survivors in bit order (lanes in order, bits within a lane)
     uint64_t m = __ballot(surv != 0);
