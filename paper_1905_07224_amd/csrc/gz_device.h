@@ -824,42 +824,30 @@ __device__ __forceinline__ bool lane_tables_ok(const Src &s, uint64_t b, uint8_t
   const uint32_t total = hlit + hdist;
   uint32_t i = 0, prev = 0, eob = 0, ndist = 0, d1 = 0;
   int lit_left = 32768, dist_left = 32768;
-  for (uint32_t it = 0; it < 320u && i < total; it++) {
+  bool bad = false;
+  // straight-line body: every case is computed and selected (lanes decode
+  // different candidates, so branches would diverge); a lane that fails
+  // stops at the next test of the loop condition
+  for (uint32_t it = 0; it < 320u && i < total && !bad; it++) {
     const uint32_t e = tab[64u * (uint32_t)(br.acc & 127u) + (uint32_t)lane];
     const uint32_t sym = e & 31u, cl = e >> 5;
-    uint32_t L, rep;
-    if (sym < 16u) {
-      br.skip(cl);
-      L = sym;
-      rep = 1;
-    } else {
-      const uint32_t ex = sym == 16u ? 2u : sym == 17u ? 3u : 7u;
-      const uint32_t extra = (uint32_t)(br.acc >> cl) & ((1u << ex) - 1u);
-      br.skip(cl + ex);
-      if (sym == 16u) {
-        if (i == 0) return false;
-        L = prev;
-        rep = 3u + extra;
-      } else {
-        L = 0;
-        rep = (sym == 17u ? 3u : 11u) + extra;
-      }
-    }
-    if (i + rep > total) return false;
-    if (L) {
-      const uint32_t nl = i < hlit ? min(i + rep, hlit) - i : 0u;
-      lit_left -= (int)nl << (15 - L);
-      dist_left -= (int)(rep - nl) << (15 - L);
-      ndist += rep - nl;
-      if (L == 1u) d1 += rep - nl;
-    }
-    if (i <= 256u && 256u < i + rep) eob = L;
+    const uint32_t ex = sym == 16u ? 2u : sym == 17u ? 3u : sym == 18u ? 7u : 0u;
+    const uint32_t extra = (uint32_t)(br.acc >> cl) & ((1u << ex) - 1u);
+    br.skip(cl + ex);
+    const uint32_t L = sym < 16u ? sym : sym == 16u ? prev : 0u;
+    const uint32_t rep = sym < 16u ? 1u : (sym == 18u ? 11u : 3u) + extra;
+    const uint32_t nl = i < hlit ? min(i + rep, hlit) - i : 0u;
+    const uint32_t wgt = L ? 1u << (15u - L) : 0u;  // Kraft weight of one length-L code
+    lit_left -= (int)(nl * wgt);
+    dist_left -= (int)((rep - nl) * wgt);
+    ndist += L ? rep - nl : 0u;
+    d1 += L == 1u ? rep - nl : 0u;
+    eob = i <= 256u && 256u < i + rep ? L : eob;
+    bad = (sym == 16u && i == 0u) || i + rep > total || br.pos > s.end_bits || lit_left < 0 || dist_left < 0;
     prev = L;
     i += rep;
-    if (br.pos > s.end_bits) return false;
-    if (lit_left < 0 || dist_left < 0) return false;
   }
-  if (i < total || eob == 0 || lit_left != 0) return false;
+  if (bad || i < total || eob == 0 || lit_left != 0) return false;
   if (dist_left > 0 && ndist != 0 && !(ndist == 1u && d1 == 1u)) return false;
   return true;
 }
