@@ -48,6 +48,19 @@ def test_emu_handbuilt(orc):
         assert st == 0 and out == data, name
 
 
+def test_emu_long_codes_across_chunks(orc):
+    """Blocks whose literal/length and distance codes reach 15 bits (longer
+    than the lookup tables: decoded alone) as chunk starts found by the scan,
+    trial and confirmation blocks included: same starts, ends and bytes as
+    the oracle."""
+    from test_oracle import _LONG_DIST, _LONG_LIT, _LONG_TOKENS, wrap_tokens
+
+    kw = {"lit_lengths": _LONG_LIT, "dist_lengths": _LONG_DIST}
+    deflate, data = wrap_tokens([("dynamic", _LONG_TOKENS * 4, kw)] * 30)
+    r, tab = _check(orc, gzip_wrap(deflate, data), 8, data)
+    assert (tab["start"] != NONE).sum() == 8
+
+
 @pytest.mark.parametrize("kind,level,n", [("fastq", 6, 3), ("words", 6, 4), ("fastq", 1, 3), ("fastq", 9, 2)])
 def test_emu_multichunk(orc, kind, level, n):
     raw = (synth.fastq_like(160 << 10, 301) if kind == "fastq" else synth.word_stream(160 << 10, 302))

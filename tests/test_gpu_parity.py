@@ -143,6 +143,17 @@ def test_handbuilt_streams(orc):
         assert got == data, name
 
 
+def test_long_codes_across_chunks(orc):
+    """Literal/length and distance codes of up to 15 bits (decoded alone,
+    past the lookup tables) in chunk starts, trial and confirmation blocks."""
+    from test_oracle import _LONG_DIST, _LONG_LIT, _LONG_TOKENS, wrap_tokens
+
+    kw = {"lit_lengths": _LONG_LIT, "dist_lengths": _LONG_DIST}
+    deflate, data = wrap_tokens([("dynamic", _LONG_TOKENS * 4, kw)] * 30)
+    _say("long codes across chunks")
+    _check_against_oracle(orc, gzip_wrap(deflate, data), 8, data)
+
+
 def test_negative_statuses(orc):
     gz = _gz()
     raw = synth.fastq_like(600 << 10, 81)

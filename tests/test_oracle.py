@@ -128,6 +128,22 @@ def test_roundtrip_gzip_cli(orc, level):
 
 HIST32K = bytes((i * 7 + 3) & 0xFF for i in range(32768))
 
+def _chain_lengths(order, n):
+    """Code lengths 1, 2, ..., k - 1, k - 1 for the symbols in `order` (a
+    complete code whose last two codes are the longest, k - 1 bits)."""
+    lengths = [0] * n
+    for i, sym in enumerate(order):
+        lengths[sym] = min(i + 1, len(order) - 1)
+    return lengths
+
+
+# Literal/length and distance codes of 13 to 15 bits, longer than any lookup
+# table of the decoder, including end-of-block, a length code and two
+# distance codes at 15 bits (distances 129..256 of codes 14 and 15).
+_LONG_LIT = _chain_lengths(list(range(97, 110)) + [257, 256, 110], 286)
+_LONG_DIST = _chain_lengths(list(range(16)), 30)
+_LONG_TOKENS = list(b"abcdefghijklmn") * 25 + [(3, 200), (3, 150), (3, 1), 110, (3, 130), 97, (3, 256), (3, 2)]
+
 HAND = {
     "stored_len0": [("stored", b"", {})],
     "stored_len65535": [("stored", bytes(range(256)) * 255 + bytes(range(255)), {}), ("stored", b"", {})],
@@ -145,6 +161,8 @@ HAND = {
     "dynamic_literal_only": [("dynamic", list(b"hello, literal-only block"), {})],
     "mixed_blocks": [("dynamic", list(b"abcabcabcabc") + [(20, 3)], {}), ("stored", b"raw bytes", {}),
                      ("fixed", [(9, 12), 33], {}), ("dynamic", [(30, 30), 10], {})],
+    "dynamic_15bit_codes": [("dynamic", _LONG_TOKENS, {"lit_lengths": _LONG_LIT, "dist_lengths": _LONG_DIST}),
+                            ("dynamic", _LONG_TOKENS, {"lit_lengths": _LONG_LIT, "dist_lengths": _LONG_DIST})],
 }
 
 
