@@ -970,10 +970,12 @@ __global__ __launch_bounds__(256) void k_scan(const FileDesc *files, const Chunk
 // of factor * (1.5 P + 2 N) + N * (slack + unit) symbols always suffices.
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(256) void k_capacity(const FileDesc *files, ChunkDesc *chunks, const ChunkState *cs,
+constexpr int CAP_THREADS = 1024;
+
+__global__ __launch_bounds__(CAP_THREADS) void k_capacity(const FileDesc *files, ChunkDesc *chunks, const ChunkState *cs,
                                                   uint32_t factor) {
-  __shared__ uint64_t part[256];
-  __shared__ uint64_t nxt[256];
+  __shared__ uint64_t part[CAP_THREADS];
+  __shared__ uint64_t nxt[CAP_THREADS];
   const uint32_t f = blockIdx.x;
   const FileDesc fd = files[f];
   const uint32_t c0 = fd.first_chunk, n = fd.n_chunks;
@@ -986,21 +988,21 @@ __global__ __launch_bounds__(256) void k_capacity(const FileDesc *files, ChunkDe
                                                                          : tr_bit;
   // pass 1, last tile first: next start after each chunk (suffix minimum)
   uint64_t later = end_bit;
-  const uint32_t ntiles = (n + 255) / 256;
+  const uint32_t ntiles = (n + CAP_THREADS - 1) / CAP_THREADS;
   for (uint32_t t = ntiles; t-- > 0;) {
-    const uint32_t i = t * 256 + (uint32_t)tid;
+    const uint32_t i = t * CAP_THREADS + (uint32_t)tid;
     uint64_t s = NONE;
     if (i < n) s = (chunks[c0 + i].flags & CF_FIRST) ? fd.payload_bit : cs[c0 + i].cand;
     part[tid] = s;
     __syncthreads();
     // inclusive suffix minimum within the tile
-    for (int o = 1; o < 256; o <<= 1) {
-      const uint64_t b = tid + o < 256 ? part[tid + o] : NONE;
+    for (int o = 1; o < CAP_THREADS; o <<= 1) {
+      const uint64_t b = tid + o < CAP_THREADS ? part[tid + o] : NONE;
       __syncthreads();
       part[tid] = part[tid] < b ? part[tid] : b;
       __syncthreads();
     }
-    const uint64_t after = tid + 1 < 256 ? part[tid + 1] : NONE;
+    const uint64_t after = tid + 1 < CAP_THREADS ? part[tid + 1] : NONE;
     nxt[tid] = after < later ? after : later;
     const uint64_t tile_min = part[0];
     __syncthreads();
@@ -1023,18 +1025,18 @@ __global__ __launch_bounds__(256) void k_capacity(const FileDesc *files, ChunkDe
   // pass 2: exclusive prefix sum of the capacities
   uint64_t carry = fd.pool_base;
   for (uint32_t t = 0; t < ntiles; t++) {
-    const uint32_t i = t * 256 + (uint32_t)tid;
+    const uint32_t i = t * CAP_THREADS + (uint32_t)tid;
     const uint64_t cap = i < n ? chunks[c0 + i].sym_cap : 0;
     part[tid] = cap;
     __syncthreads();
-    for (int o = 1; o < 256; o <<= 1) {
+    for (int o = 1; o < CAP_THREADS; o <<= 1) {
       const uint64_t a = tid >= o ? part[tid - o] : 0;
       __syncthreads();
       part[tid] += a;
       __syncthreads();
     }
     if (i < n) chunks[c0 + i].sym_off = carry + part[tid] - cap;
-    carry += part[255];
+    carry += part[CAP_THREADS - 1];
     __syncthreads();
   }
 }
@@ -1277,12 +1279,14 @@ __device__ __forceinline__ bool stored_equivalent(const FileDesc &fd, uint64_t s
   return (v & 7u) == 0u && stored_start_bits(v, s, src.end_bits);
 }
 
+constexpr int FIN_THREADS = 1024;
+
 template <int WIN>
-__global__ __launch_bounds__(256) void k_finalize(const FileDesc *files, const ChunkDesc *chunks, ChunkState *cs,
+__global__ __launch_bounds__(FIN_THREADS) void k_finalize(const FileDesc *files, const ChunkDesc *chunks, ChunkState *cs,
                                                   FileState *fs, uint16_t *pool) {
   __shared__ InflateLDS<WIN> sh;
   __shared__ int bad;
-  __shared__ uint64_t part[256];
+  __shared__ uint64_t part[FIN_THREADS];
   const uint32_t f = blockIdx.x;
   const FileDesc fd = files[f];
   const uint32_t c0 = fd.first_chunk, c1 = fd.first_chunk + fd.n_chunks;
@@ -1390,8 +1394,8 @@ __global__ __launch_bounds__(256) void k_finalize(const FileDesc *files, const C
     }
     part[tid] = L;
     __syncthreads();
-    // Hillis-Steele inclusive scan (256 entries)
-    for (int o = 1; o < 256; o <<= 1) {
+    // Hillis-Steele inclusive scan (FIN_THREADS entries)
+    for (int o = 1; o < FIN_THREADS; o <<= 1) {
       uint64_t a = tid >= o ? part[tid - o] : 0;
       __syncthreads();
       part[tid] += a;
@@ -1403,13 +1407,13 @@ __global__ __launch_bounds__(256) void k_finalize(const FileDesc *files, const C
       const uint64_t hist = off + fd.win_valid;
       cs[j].valid = (uint32_t)(hist < WINDOW ? hist : WINDOW);
     }
-    carry += part[255];
+    carry += part[FIN_THREADS - 1];
     __syncthreads();
   }
   // reductions of the statistics
   part[tid] = nsyms;
   __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
+  for (int o = FIN_THREADS / 2; o > 0; o >>= 1) {
     if (tid < o) part[tid] += part[tid + o];
     __syncthreads();
   }
@@ -1417,7 +1421,7 @@ __global__ __launch_bounds__(256) void k_finalize(const FileDesc *files, const C
   __syncthreads();
   part[tid] = nph;
   __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
+  for (int o = FIN_THREADS / 2; o > 0; o >>= 1) {
     if (tid < o) part[tid] += part[tid + o];
     __syncthreads();
   }
@@ -1425,7 +1429,7 @@ __global__ __launch_bounds__(256) void k_finalize(const FileDesc *files, const C
   __syncthreads();
   part[tid] = nblk | ((uint64_t)nonempty << 40);
   __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
+  for (int o = FIN_THREADS / 2; o > 0; o >>= 1) {
     if (tid < o) part[tid] += part[tid + o];
     __syncthreads();
   }
@@ -1433,7 +1437,7 @@ __global__ __launch_bounds__(256) void k_finalize(const FileDesc *files, const C
   __syncthreads();
   part[tid] = (uint64_t)ext | ((uint64_t)retries << 20) | ((uint64_t)overflow << 42);
   __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
+  for (int o = FIN_THREADS / 2; o > 0; o >>= 1) {
     if (tid < o) part[tid] += part[tid + o];
     __syncthreads();
   }
@@ -2062,7 +2066,7 @@ hipError_t gzk_init(ChunkState *cs, uint32_t n_chunks, FileState *fs, uint32_t n
 
 hipError_t gzk_capacity(uint32_t n_files, const FileDesc *files, ChunkDesc *chunks, const ChunkState *cs,
                         uint32_t factor, hipStream_t st) {
-  hipLaunchKernelGGL(k_capacity, dim3(n_files), dim3(256), 0, st, files, chunks, cs, factor);
+  hipLaunchKernelGGL(k_capacity, dim3(n_files), dim3(CAP_THREADS), 0, st, files, chunks, cs, factor);
   return hipGetLastError();
 }
 
@@ -2140,7 +2144,7 @@ hipError_t gzk_stitch(int win, uint32_t grid, const FileDesc *files, const Chunk
 
 hipError_t gzk_finalize(int win, uint32_t n_files, const FileDesc *files, const ChunkDesc *chunks, ChunkState *cs,
                         FileState *fs, uint16_t *pool, hipStream_t st) {
-  GZ_WIN_SWITCH(win, hipLaunchKernelGGL(k_finalize<W>, dim3(n_files), dim3(256), 0, st, files, chunks, cs, fs, pool));
+  GZ_WIN_SWITCH(win, hipLaunchKernelGGL(k_finalize<W>, dim3(n_files), dim3(FIN_THREADS), 0, st, files, chunks, cs, fs, pool));
   return hipGetLastError();
 }
 
